@@ -1,0 +1,85 @@
+"""Pins of the oracle's derivatives: adjoint identity, eps-gradient against
+central finite differences of freshly re-solved systems, and the banded solve
+against the dense inverse."""
+
+import numpy as np
+import pytest
+
+from oracle import apply, grad, grid, inverse, quant
+from paper_1602_00001_amd import workloads
+
+
+def test_adjoint_dot_product_identity_quantised():
+    """<G^ x, y> = <x, G^T y> exactly on the integer parts."""
+    g = np.random.default_rng(2)
+    N = 25
+    G = g.standard_normal((N, N))
+    qG, e = quant.quantize_rows(G, 2)
+    x = g.integers(-1000, 1000, (N, 3))
+    y = g.integers(-1000, 1000, (N, 3))
+    lhs = np.sum((qG @ x) * y, axis=0)
+    rhs = np.sum(x * (qG.T @ y), axis=0)
+    assert np.array_equal(lhs, rhs)
+
+
+def test_banded_solve_matches_dense():
+    g = np.random.default_rng(3)
+    nx, ny, h = 11, 9, 0.1
+    eps = workloads.random_eps(nx, ny, g)
+    ub = g.standard_normal((ny, nx))
+    rho = g.standard_normal(((nx - 2) * (ny - 2), 2))
+    K, bB = grid.conservative_operator(nx, ny, eps, ub)
+    G = inverse.lu_inverse(K)
+    u_dense = apply.plain_apply(G, rho, h, apply.lift(G, bB))
+    u_band = grad.banded_solve(nx, ny, h, eps, rho, ub)
+    assert np.max(np.abs(u_dense - u_band)) < 1e-12 * np.max(np.abs(u_dense))
+
+
+@pytest.mark.parametrize("with_boundary", [False, True])
+def test_grad_eps_matches_central_differences(with_boundary):
+    """dLoss/deps from (u, lambda) equals central differences of the re-solved
+    loss along random directions, to 1e-6 relative."""
+    g = np.random.default_rng(4 + with_boundary)
+    nx, ny = 12, 10
+    h = 1.0 / (nx - 1)
+    N = (nx - 2) * (ny - 2)
+    eps = 1.0 + 0.5 * g.uniform(0, 1, (ny, nx))
+    ub = g.standard_normal((ny, nx)) if with_boundary else None
+    rho = g.standard_normal((N, 3))
+    sample = np.sort(g.choice(N, 15, replace=False))
+    d = g.standard_normal((15, 3)) * 0.01
+
+    K, bB = grid.conservative_operator(nx, ny, eps, ub)
+    G = inverse.lu_inverse(K)
+    u = apply.plain_apply(G, rho, h, apply.lift(G, bB))
+    gu = grad.sampling_loss_grad_u(u, sample, d)
+    lam = grad.adjoint(G, gu, h)
+    ge = grad.grad_eps_nodes(nx, ny, h, u, lam, ub)
+
+    def loss(e):
+        return grad.sampling_loss(nx, ny, h, e, rho, sample, d, ub)
+
+    for t in range(3):
+        v = g.standard_normal((ny, nx))
+        fd = grad.central_difference(loss, eps, v, 1e-6)
+        an = float(np.sum(ge * v))
+        assert abs(fd - an) <= 1e-6 * max(abs(fd), 1e-30), (fd, an)
+
+    # dLoss/drho = lambda, also against central differences
+    for t in range(2):
+        v = g.standard_normal(rho.shape)
+        fd = grad.central_difference(lambda r: grad.sampling_loss(nx, ny, h, eps, r, sample, d, ub), rho, v, 1e-6)
+        an = float(np.sum(lam * v))
+        assert abs(fd - an) <= 1e-6 * abs(fd)
+
+
+def test_grad_eps_faces_between_boundary_nodes_do_not_count():
+    """eps at a corner node touches only boundary-boundary faces: zero gradient."""
+    g = np.random.default_rng(8)
+    nx, ny, h = 7, 6, 0.2
+    N = (nx - 2) * (ny - 2)
+    u = g.standard_normal((N, 2))
+    lam = g.standard_normal((N, 2))
+    ge = grad.grad_eps_nodes(nx, ny, h, u, lam, g.standard_normal((ny, nx)))
+    for (i, j) in ((0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1)):
+        assert ge[i, j] == 0.0

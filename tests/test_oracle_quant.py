@@ -1,0 +1,171 @@
+"""Pins of the quantiser and the integer apply: brute force with exact rational
+arithmetic (Python Fraction) on small inputs, digit identities and bounds."""
+
+from fractions import Fraction
+import math
+
+import numpy as np
+import pytest
+
+from oracle import apply, grid, inverse, metrics, quant
+
+
+def _frexp_exp_exact(x):
+    """Smallest e with |x| < 2^e, by exact comparison (0 -> 0)."""
+    x = abs(Fraction(x))
+    if x == 0:
+        return 0
+    e = 0
+    while x >= Fraction(2) ** e:
+        e += 1
+    while x < Fraction(2) ** (e - 1):
+        e -= 1
+    return e
+
+
+def _round_half_even(fr):
+    fl = math.floor(fr)
+    rem = fr - fl
+    if rem > Fraction(1, 2):
+        return fl + 1
+    if rem < Fraction(1, 2):
+        return fl
+    return fl if fl % 2 == 0 else fl + 1
+
+
+def _brute_quantize_row(row, S):
+    M = 127 * (256 ** S - 1) // 255
+    e = _frexp_exp_exact(max(abs(float(v)) for v in row))
+    out = []
+    for v in row:
+        # one float64 multiply (correctly rounded) of the exactly scaled value
+        prod = Fraction(float(Fraction(v) / Fraction(2) ** e * M))
+        out.append(_round_half_even(prod))
+    return out, e
+
+
+def test_max_mag():
+    assert [quant.max_mag(s) for s in (1, 2, 3)] == [127, 32639, 8355711]
+    for s in (1, 2, 3):
+        # the largest value with s balanced digits, top digit <= 127
+        assert quant.max_mag(s) == sum(127 * 256 ** k for k in range(s))
+
+
+@pytest.mark.parametrize("S", [1, 2, 3])
+def test_quantize_rows_brute_force(S):
+    g = np.random.default_rng(S)
+    G = g.standard_normal((6, 9)) * np.exp(g.uniform(-8, 3, (6, 1)))
+    G[2, :] = 0.0
+    G[3, 4] = 0.75  # an exact power-of-two-scaled value
+    q, e = quant.quantize_rows(G, S)
+    for i in range(G.shape[0]):
+        qb, eb = _brute_quantize_row(G[i], S)
+        assert e[i] == eb
+        assert list(q[i]) == qb
+    assert e[2] == 0 and np.all(q[2] == 0)
+    assert np.all(np.abs(q) <= quant.max_mag(S))
+
+
+def test_quantize_ties_to_even():
+    """Products that land exactly on k + 1/2 round to the even neighbour."""
+    S, M = 1, quant.max_mag(1)
+    xs = [(2 * k + 1) / (2.0 * M) for k in range(50)]
+    row = np.array([0.5] + xs + [-x for x in xs])      # max 0.5 -> e = 0
+    q, e = quant.quantize_rows(row[None, :], S)
+    assert e[0] == 0
+    ties = 0
+    for idx, x in enumerate(row[1:], start=1):
+        p = x * M
+        if abs(p - np.trunc(p)) == 0.5:
+            ties += 1
+            assert q[0, idx] % 2 == 0
+            assert abs(q[0, idx] - p) == 0.5
+    assert ties >= 20
+
+
+@pytest.mark.parametrize("S", [1, 2, 3])
+def test_balanced_digits_identity_and_range(S):
+    M = quant.max_mag(S)
+    g = np.random.default_rng(10 + S)
+    extra = np.array([M, -M, 0, 127, -127, 128, -128, 255, -255, 32767, -32768])
+    q = np.concatenate([g.integers(-M, M + 1, 5000), extra[np.abs(extra) <= M]])
+    d = quant.balanced_digits(q, S)
+    rec = sum(d[s] * 256 ** (S - 1 - s) for s in range(S))
+    assert np.array_equal(rec, q)
+    assert d.min() >= -128 and d.max() <= 127
+    assert np.all(np.abs(d[0]) <= 127)
+
+
+def test_balanced_digits_reject_overflow():
+    with pytest.raises(ValueError):
+        quant.balanced_digits(np.array([quant.max_mag(1) + 200]), 1)
+
+
+@pytest.mark.parametrize("S", [1, 2, 3])
+def test_quantisation_error_bound(S):
+    """|G^ - G| <= 2^e / (2 M_S) per entry, with equality impossible beyond it."""
+    g = np.random.default_rng(20 + S)
+    G = g.standard_normal((40, 50))
+    q, e = quant.quantize_rows(G, S)
+    Gh = quant.dequantize_rows(q, e, S)
+    bound = np.ldexp(np.ones((40, 1)) / (2 * quant.max_mag(S)), e[:, None])
+    assert np.all(np.abs(Gh - G) <= bound * (1 + 1e-12))
+
+
+def test_quantize_cols_pre_exponent_is_exact_scaling():
+    g = np.random.default_rng(4)
+    X = g.standard_normal((30, 5))
+    pe = g.integers(-4, 4, 30)
+    q1, f1 = quant.quantize_cols(X, 2, pre_exponent=pe)
+    q2, f2 = quant.quantize_cols(np.ldexp(X, pe[:, None]), 2)
+    assert np.array_equal(q1, q2) and np.array_equal(f1, f2)
+
+
+def test_integer_apply_brute_force():
+    """acc is the exact integer product; u = RNE(RNE(acc * scale) + w)."""
+    g = np.random.default_rng(9)
+    N, R, S, Sr, h = 7, 3, 3, 2, 0.125
+    G = g.standard_normal((N, N))
+    rho = g.standard_normal((N, R))
+    w = g.standard_normal(N)
+    qG, e = quant.quantize_rows(G, S)
+    qR, f = quant.quantize_cols(rho, Sr)
+    u, acc = apply.integer_apply(qG, e, S, qR, f, Sr, h, w)
+    c = Fraction(-(h * h) / (quant.max_mag(S) * quant.max_mag(Sr)))
+    cf = float(c)  # the constant is computed once in float64
+    for i in range(N):
+        for r in range(R):
+            a = sum(int(qG[i, k]) * int(qR[k, r]) for k in range(N))
+            assert acc[i, r] == a
+            scale = Fraction(cf) * Fraction(2) ** (int(e[i]) + int(f[r]))
+            v = float(Fraction(float(Fraction(a) * scale)) + Fraction(float(w[i])))
+            assert u[i, r] == v
+
+
+def test_slice_pairs_recombine_to_integer_product():
+    g = np.random.default_rng(12)
+    S, Sr, N = 3, 2, 33
+    qG = g.integers(-quant.max_mag(S), quant.max_mag(S) + 1, (N, N))
+    qR = g.integers(-quant.max_mag(Sr), quant.max_mag(Sr) + 1, (N, 4))
+    P = apply.slice_pair_products(quant.balanced_digits(qG, S), quant.balanced_digits(qR, Sr))
+    tot = sum(P[s, t] * 256 ** ((S - 1 - s) + (Sr - 1 - t)) for s in range(S) for t in range(Sr))
+    assert np.array_equal(tot, apply.integer_product(qG, qR))
+
+
+def test_quantised_solve_error_envelope():
+    """The quantised solve tracks the FP64 solve within the rounding envelope,
+    and the 24x16-bit variant is within 1e-4 relative L2 on uniform RHS."""
+    n = 40
+    K, _ = grid.conservative_operator(n, n)
+    G = inverse.lu_inverse(K)
+    h = 1.0 / (n - 1)
+    rho = np.random.default_rng(1).uniform(-1, 1, (G.shape[0], 8))
+    ref = apply.plain_apply(G, rho, h)
+    errs = {}
+    for S in (1, 2, 3):
+        qG, e = quant.quantize_rows(G, S)
+        qR, f = quant.quantize_cols(rho, 2)
+        u, _ = apply.integer_apply(qG, e, S, qR, f, 2, h)
+        errs[S] = np.max(metrics.rel_l2_per_rhs(u, ref))
+    assert errs[1] > errs[2] > errs[3]
+    assert errs[3] < 1e-4
