@@ -1,0 +1,212 @@
+/*
+ * pinv.h -- dense-inverse solves of the 5-point variable-permittivity Poisson
+ * operator on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Dourbal & Pekker, "A New Numerical Method for Fast Solution of
+ * Partial Integro-Differential Equations"): discretise Eq. 1,
+ *     d/dx_i eps d u/dx_i = rho,
+ * with the 5-point scheme of Eq. 2 and Dirichlet identity rows as in Fig. 3,
+ * build the matrix once, invert it once ("The solution steps", steps 1-2), and
+ * then obtain u at every time moment as one product of the (optionally
+ * rounded) inverse with the source vector (step 3; the rounding experiment of
+ * Table 1).
+ *
+ * Grid and layouts
+ *   A grid is n_x by n_y nodes INCLUDING the boundary, spacing h.  Nodal
+ *   arrays are row-major [n_y][n_x]: the first (slow) index runs over y, the
+ *   second (fast) over x, exactly the unknown order of Fig. 3.  The N =
+ *   (n_x-2)(n_y-2) interior unknowns are numbered row-major over the interior.
+ *   Right-hand sides, solutions and adjoint vectors are "column-major N x nrhs":
+ *   vector r starts at ptr + r*ld, its N entries contiguous, ld >= N.
+ *
+ * Operator (conservative form of Eq. 1, face permittivity = mean of the two
+ * nodal values):  for interior p,  sum_f eps_f (u_p - u_q) = -h^2 rho_p, so
+ *     u = -h^2 * G * rho + w,   G = K^{-1} (SPD),  w = G * b_B,
+ * where b_B carries the Dirichlet data of boundary neighbours.  With eps = 1,
+ * K is 4x the interior block of the Fig. 3 matrix, whose interior rows read
+ * u - 0.25 * (sum of 4 neighbours) = -(h^2/4) rho.
+ *
+ * Precision modes of the apply (inputs and outputs are FP64 in every mode):
+ *   PINV_FP64   G in FP64, FP64 matrix-core product.
+ *   PINV_FP32   G and rho rounded to FP32, FP32 products, FP32 accumulation.
+ *   PINV_BF16X3 G and rho split into 2 bfloat16 parts each; hi*hi + hi*lo +
+ *               lo*hi with FP32 accumulation.
+ *   PINV_BF16X6 3 parts each; the 6 products of total order <= 2.
+ *   PINV_INT8   G rounded to b-bit per-row fixed point (b = 8, 16, 24) held
+ *               as 1-3 balanced int8 digit slices, rho rounded per column to
+ *               rho_bits the same way; the integer product is exact (int32
+ *               matrix-core accumulation per slice-pair class, int64
+ *               recombination), then scaled once and added to w.  Given the
+ *               same FP64 G the result is reproducible bit for bit.
+ *   Fixed point: M_S = 127*(256^S-1)/255 for S digits; e_i = frexp exponent of
+ *   max_k |G_ik|; q_ik = rint((G_ik * 2^-e_i) * M_S) (one rounded multiply,
+ *   ties to even); G^_ik = q_ik 2^e_i / M_S.  u_ir = double(acc_ir) *
+ *   (c * 2^(e_i+f_r)) + w_i with c = -h^2/(M_S M_Sr) (two roundings, no FMA).
+ *
+ * Conventions for every call
+ *   Returns PINV_OK (0) or a negative status; nothing throws or aborts.
+ *   "stream" is a hipStream_t passed as void*; NULL means the null stream.
+ *   Device pointers are HIP device (or managed) memory on the current device.
+ *   Apply, adjoint and grad calls are asynchronous on the stream; their
+ *   argument checks are synchronous.  An op is read-only during apply /
+ *   adjoint / grad, so such calls may run concurrently on several streams;
+ *   build/import/quantize/prepare/destroy must not overlap other calls on the
+ *   same op.
+ */
+#ifndef PINV_H
+#define PINV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define PINV_OK               0
+#define PINV_E_INVALID_ARG   -1  /* bad size, NULL pointer, ld < N, bad enum   */
+#define PINV_E_NOT_SPD       -2  /* Cholesky met a non-positive pivot          */
+#define PINV_E_OOM           -3  /* device allocation failed or would not fit  */
+#define PINV_E_HIP           -4  /* a HIP runtime call failed                  */
+#define PINV_E_UNSUPPORTED   -5  /* size beyond the integer headroom limits    */
+#define PINV_E_STATE         -6  /* representation needed by the call missing  */
+
+/* ---- enums -------------------------------------------------------------- */
+#define PINV_FP64    0
+#define PINV_FP32    1
+#define PINV_BF16X3  2
+#define PINV_BF16X6  3
+#define PINV_INT8    4
+
+#define PINV_SCALE_ROW 0          /* one power-of-two exponent per row of G   */
+
+typedef struct pinv_op_s* pinv_op; /* opaque; owns all of its device memory   */
+
+typedef struct {
+  int32_t nx;   /* grid points along x (fast axis), boundary included, >= 3    */
+  int32_t ny;   /* grid points along y (slow axis), boundary included, >= 3    */
+  double  h;    /* uniform spacing (Eq. 2: h = L/(n-1)), > 0                    */
+} pinv_grid;
+
+typedef struct {
+  int32_t nx, ny, n;        /* grid and number of interior unknowns N          */
+  double  h;
+  int32_t has_fp64;         /* FP64 G resident                                  */
+  int32_t int8_slices;      /* S (0 if not quantised)                           */
+  int32_t has_fp32, has_bf16;
+  int32_t has_lift;         /* nonzero Dirichlet data (w != 0)                  */
+  int64_t device_bytes;     /* device memory held by the op                     */
+} pinv_info;
+
+/* Steps 1-2 of "The solution steps": assemble the interior operator K from the
+ * nodal permittivity (Eq. 1 in conservative form; Eq. 2 when eps = 1), factor
+ * it by blocked FP64 Cholesky and form G = K^{-1} = L^{-T} L^{-1} on the GPU,
+ * plus the lift w = G b_B.
+ *   g           grid (host).
+ *   eps_nodes   host [n_y][n_x] nodal permittivity, or NULL for eps = 1.
+ *   u_boundary  host [n_y][n_x]; only boundary entries are read.  NULL = 0.
+ *   out         receives the new op (NULL on failure).
+ * Synchronises the stream once at the end.  PINV_E_NOT_SPD if a pivot <= 0
+ * (e.g. eps <= 0 somewhere).  Device memory: about 3 N^2 doubles at peak,
+ * N^2 doubles afterwards. */
+int32_t pinv_build_inverse(const pinv_grid* g, const double* eps_nodes,
+                           const double* u_boundary, void* stream, pinv_op* out);
+
+/* Create an op from an inverse computed elsewhere (step 2 by "any standard
+ * matrix inversion method"; also restores a saved op).
+ *   G_host      host row-major N x N, row stride ldg >= N (copied).
+ *   u_boundary  as in pinv_build_inverse (kept for pinv_grad_eps), or NULL.
+ *   w_host      host [N] lift to use as is, or NULL: then w = G b_B is formed
+ *               on the GPU when u_boundary is given (eps_nodes used for b_B),
+ *               else w = 0. */
+int32_t pinv_import_inverse(const pinv_grid* g, const double* G_host, int64_t ldg,
+                            const double* eps_nodes, const double* u_boundary,
+                            const double* w_host, void* stream, pinv_op* out);
+
+/* Copy the FP64 inverse to host memory (row-major, row stride ldg >= N) and,
+ * if w_host != NULL, the lift.  Synchronous.  PINV_E_STATE if G was freed. */
+int32_t pinv_export_inverse(pinv_op op, double* G_host, int64_t ldg, double* w_host,
+                            void* stream);
+
+/* The rounding of the inverse (Table 1 experiment), in binary: per-row
+ * fixed point with bits = 8, 16 or 24 (S = bits/8 int8 digit slices).
+ * Replaces any previous quantisation.  keep_fp64 = 0 frees the FP64 G
+ * afterwards (FP64/FP32/BF16 applies then return PINV_E_STATE).
+ * scale_mode must be PINV_SCALE_ROW.  Synchronous. */
+int32_t pinv_quantize_inverse(pinv_op op, int32_t bits, int32_t scale_mode,
+                              int32_t keep_fp64, void* stream);
+
+/* Materialise the FP32 copy (mode PINV_FP32) or the bfloat16 parts (PINV_BF16X3
+ * or PINV_BF16X6) of G, from the FP64 G.  Synchronous. */
+int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream);
+
+/* Export the int8 digit slices (host [S][N][N], most significant slice
+ * first, row-major) and the per-row exponents (host [N]).  Either may be NULL.
+ * Synchronous.  PINV_E_STATE if not quantised. */
+int32_t pinv_export_quantized(pinv_op op, int8_t* slices_host, int32_t* exponents_host,
+                              void* stream);
+
+/* Step 3: u = L^{-1} rho for nrhs right-hand sides,  u = -h^2 G rho + w.
+ *   mode      PINV_FP64 / FP32 / BF16X3 / BF16X6 / INT8.
+ *   rho_bits  8, 16 or 24: fixed-point width of rho in INT8 mode (ignored
+ *             otherwise).
+ *   rho, u    device, column-major N x nrhs with strides ld_rho, ld_u >= N;
+ *             must not overlap.  nrhs >= 0 (0 is a no-op).
+ * Asynchronous.  PINV_E_STATE if the mode's representation is missing;
+ * PINV_E_UNSUPPORTED if the int32 class accumulators could overflow
+ * (N * 16384 * pairs-per-class >= 2^31) or N * M_S * M_Sr >= 2^63. */
+int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits,
+                           const double* rho, int64_t ld_rho, int32_t nrhs,
+                           double* u, int64_t ld_u, void* stream);
+
+/* Adjoint of the apply's linear part (not in the paper; the derivative of
+ * step 3):  lambda = dLoss/drho = -h^2 * G^T g  for the representation that
+ * the mode selects (G^T of the rounded matrix in INT8 mode, where g's row
+ * scaling 2^e_k is applied exactly before g is rounded to g_bits per column).
+ * Same layout rules as pinv_apply_inverse.  Asynchronous. */
+int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits,
+                                   const double* g, int64_t ld_g, int32_t nrhs,
+                                   double* lambda, int64_t ld_lambda, void* stream);
+
+/* Permittivity gradient (not in the paper): with u the forward solutions and
+ * lambda the adjoint outputs of the same loss,
+ *   dLoss/deps_f = (1/h^2) sum_r (lambda_p - lambda_q)(u_p - u_q)
+ * over the faces f = (p, q) of the operator (lambda = 0 and u = u_B on the
+ * boundary), and grad_nodes[i][j] = half the sum over the faces touching the
+ * node.  grad_nodes: device [n_y][n_x], overwritten (no accumulation).
+ * Asynchronous. */
+int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u,
+                      const double* lambda, int64_t ld_lambda, int32_t nrhs,
+                      double* grad_nodes, void* stream);
+
+/* Many solves against many ops in one call (batched uneven requests).
+ * Requests naming the same op are grouped; each group runs as one product.
+ * All ops must hold the mode's representation.  Asynchronous. */
+typedef struct {
+  pinv_op        op;
+  const double*  rho;     /* device, column-major N x nrhs, stride ld        */
+  double*        u;       /* device, same layout                             */
+  int64_t        ld;
+  int32_t        nrhs;
+  int32_t        _pad;
+} pinv_request;
+
+int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
+                           int32_t rho_bits, void* stream);
+
+int32_t pinv_get_info(pinv_op op, pinv_info* info);
+
+/* Free the op and all of its device memory (waits for the device first). */
+int32_t pinv_destroy(pinv_op op);
+
+/* Static string for a status code. */
+const char* pinv_status_string(int32_t status);
+
+/* Library version string, "major.minor.patch". */
+const char* pinv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PINV_H */

@@ -1,0 +1,32 @@
+"""torch.autograd.Function around the solve: forward = step 3 (u = L^{-1} rho),
+backward = adjoint apply + permittivity gradient, both in the HIP library."""
+
+import torch
+
+
+class PinvSolve(torch.autograd.Function):
+    """u = PinvSolve.apply(rho, eps, op, mode, bits).
+
+    rho: [nrhs, N] float64 CUDA tensor.  eps: the nodal permittivity tensor
+    [n_y, n_x] the op was built from (only its gradient is produced here; the
+    op is not rebuilt).  op: a PoissonInverse.  Returns u [nrhs, N].
+    Gradients: drho = lambda = -h^2 G^T g, deps = nodal eps-gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, rho, eps, op, mode="fp64", bits=16):
+        u = op.apply(rho.contiguous(), mode=mode, rho_bits=bits)
+        ctx.op, ctx.mode, ctx.bits = op, mode, bits
+        ctx.save_for_backward(u)
+        ctx.eps_shape = None if eps is None else tuple(eps.shape)
+        return u
+
+    @staticmethod
+    def backward(ctx, g):
+        (u,) = ctx.saved_tensors
+        op = ctx.op
+        lam = op.apply_adjoint(g.contiguous(), mode=ctx.mode, g_bits=ctx.bits)
+        deps = None
+        if ctx.needs_input_grad[1]:
+            deps = op.grad_eps(u, lam)
+        return lam, deps, None, None, None

@@ -1,0 +1,238 @@
+// One-time setup, steps 1-2 of "The solution steps": assemble the interior
+// operator on the device and invert it.
+//
+// Step 1 (Eq. 1 in conservative form, Eq. 2 for eps = 1): for interior node p
+// and each of its 4 faces f to node q, K[p][p] += eps_f and K[p][q] = -eps_f
+// when q is interior; when q is a boundary node its Dirichlet value moves to
+// the right-hand side, b_B[p] += eps_f * u_B(q).  eps_f is the mean of the two
+// nodal permittivities.
+//
+// Step 2 ("any standard matrix inversion method"): K is symmetric positive
+// definite, so it is factored K = L L^T by a right-looking blocked Cholesky
+// (64-wide blocks; the diagonal block is factored and its triangular inverse
+// formed in LDS by one workgroup, the panel and the trailing update are FP64
+// matrix-core GEMMs), then W = L^{-1} is formed by blocked forward
+// substitution and G = K^{-1} = W^T W by one more GEMM that skips the zero
+// upper triangle of W.  A non-positive (or NaN) pivot raises a device flag
+// that the host reads once at the end.
+
+#include "common.h"
+
+namespace {
+
+constexpr int NB = 64;
+
+__global__ void assemble_kernel(int nx, int ny, const double* __restrict__ eps, const double* __restrict__ ub,
+                                double* __restrict__ K, int64_t ldk, double* __restrict__ bB) {
+  const int mx = nx - 2, my = ny - 2;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= mx * my) return;
+  const int i = p / mx + 1, j = p % mx + 1;
+  const int ni[4] = {i - 1, i + 1, i, i};
+  const int nj[4] = {j, j, j - 1, j + 1};
+  const double ep = eps ? eps[(int64_t)i * nx + j] : 1.0;
+  double diag = 0.0, b = 0.0;
+  for (int t = 0; t < 4; ++t) {
+    const int k = ni[t], l = nj[t];
+    const double eq = eps ? eps[(int64_t)k * nx + l] : 1.0;
+    const double ef = 0.5 * (ep + eq);
+    diag += ef;
+    const bool bnd = (k == 0 || k == ny - 1 || l == 0 || l == nx - 1);
+    if (bnd) {
+      if (ub) b += ef * ub[(int64_t)k * nx + l];
+    } else {
+      const int q = (k - 1) * mx + (l - 1);
+      if (K) K[(int64_t)p * ldk + q] = -ef;
+    }
+  }
+  if (K) K[(int64_t)p * ldk + p] = diag;
+  if (bB) bB[p] = b;
+}
+
+// Factor the kn x kn diagonal block at (k0, k0) in place (lower triangle, zero
+// upper) and write its triangular inverse to Wd (64 x 64, zero padded).
+__global__ __launch_bounds__(256) void diag_block_kernel(double* __restrict__ A, int64_t lda, int k0, int kn,
+                                                         double* __restrict__ Wd, int* __restrict__ flag) {
+  __shared__ double L[NB][NB + 1];
+  __shared__ double tmp[NB];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, j = idx % NB;
+    L[i][j] = (i < kn && j <= i) ? A[(int64_t)(k0 + i) * lda + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  // unblocked right-looking Cholesky
+  for (int j = 0; j < kn; ++j) {
+    if (tid == 0) {
+      double d = L[j][j];
+      if (!(d > 0.0)) {
+        *flag = 1;
+        d = 1.0;
+      }
+      L[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    const double piv = L[j][j];
+    for (int i = j + 1 + tid; i < kn; i += 256) L[i][j] = L[i][j] / piv;
+    __syncthreads();
+    const int rem = kn - j - 1;
+    for (int idx = tid; idx < rem * rem; idx += 256) {
+      const int i = j + 1 + idx / rem, c = j + 1 + idx % rem;
+      if (c <= i) L[i][c] -= L[i][j] * L[c][j];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < kn * kn; idx += 256) {
+    const int i = idx / kn, j = idx % kn;
+    A[(int64_t)(k0 + i) * lda + k0 + j] = (j <= i) ? L[i][j] : 0.0;
+  }
+  __syncthreads();
+  // in-place inverse of the lower triangular factor, last column first:
+  // Linv[j][j] = 1/L[j][j];  Linv[j+1:, j] = -Linv[j+1:, j+1:] L[j+1:, j] / L[j][j]
+  for (int j = kn - 1; j >= 0; --j) {
+    const double ljj = L[j][j];
+    const int i = j + 1 + tid;
+    if (tid < NB && i < kn) {
+      double x = 0.0;
+      for (int k = j + 1; k <= i; ++k) x += L[i][k] * L[k][j];
+      tmp[i] = x;
+    }
+    __syncthreads();
+    if (tid < NB && i < kn) L[i][j] = -tmp[i] / ljj;
+    if (tid == 0) L[j][j] = 1.0 / ljj;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, j = idx % NB;
+    Wd[idx] = (i < kn && j <= i) ? L[i][j] : 0.0;
+  }
+}
+
+__global__ void set_identity_kernel(double* __restrict__ A, int64_t lda, int n) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int i = idx / n, j = idx % n;
+  A[(int64_t)i * lda + j] = (i == j) ? 1.0 : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_assemble(int nx, int ny, const double* eps, const double* ub, double* K, int64_t ldk,
+                           double* bB, hipStream_t s) {
+  const int n = (nx - 2) * (ny - 2);
+  hipLaunchKernelGGL(assemble_kernel, dim3((n + 255) / 256), dim3(256), 0, s, nx, ny, eps, ub, K, ldk, bB);
+  return hipGetLastError();
+}
+
+// Fills op->G (allocated here), op->w.  eps_dev / ub_dev: device nodal arrays or null.
+int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub_dev, hipStream_t s) {
+  const int n = op->n;
+  const int64_t ld = op->ldg;
+  const int nblk = (n + NB - 1) / NB;
+  double *Kb = nullptr, *Wb = nullptr, *Wd = nullptr, *bB = nullptr;
+  int* flag = nullptr;
+  int32_t st = PINV_OK;
+  hipError_t e;
+  const size_t mat_bytes = (size_t)n * (size_t)ld * sizeof(double);
+
+#define PINV_BAIL(expr)                 \
+  do {                                  \
+    e = (expr);                         \
+    if (e != hipSuccess) {              \
+      st = pinv_hip_status(e);          \
+      goto done;                        \
+    }                                   \
+  } while (0)
+
+  PINV_BAIL(hipMalloc(&Kb, mat_bytes));
+  PINV_BAIL(hipMalloc(&Wb, mat_bytes));
+  PINV_BAIL(hipMalloc(&Wd, (size_t)nblk * NB * NB * sizeof(double)));
+  PINV_BAIL(hipMalloc(&bB, (size_t)n * sizeof(double)));
+  PINV_BAIL(hipMalloc(&flag, sizeof(int)));
+  PINV_BAIL(hipMemsetAsync(flag, 0, sizeof(int), s));
+  PINV_BAIL(hipMemsetAsync(Kb, 0, mat_bytes, s));
+  PINV_BAIL(hipMemsetAsync(Wb, 0, mat_bytes, s));
+  PINV_BAIL(launch_assemble(op->nx, op->ny, eps_dev, ub_dev, Kb, ld, bB, s));
+
+  // Cholesky, L overwrites the lower triangle of Kb
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * NB, kn = (n - k0 < NB) ? n - k0 : NB;
+    double* wd = Wd + (size_t)kb * NB * NB;
+    hipLaunchKernelGGL(diag_block_kernel, dim3(1), dim3(256), 0, s, Kb, ld, k0, kn, wd, flag);
+    PINV_BAIL(hipGetLastError());
+    const int r0 = k0 + kn, rn = n - r0;
+    if (rn <= 0) continue;
+    GemmF64Args p{};
+    p.A = Kb + (int64_t)r0 * ld + k0; p.lda = ld; p.a_kcontig = 1;
+    p.B = wd; p.ldb = NB; p.b_kcontig = 1;
+    p.C = Kb + (int64_t)r0 * ld + k0; p.csm = ld; p.csn = 1;
+    p.M = rn; p.N = kn; p.K = kn; p.alpha = 1.0; p.beta = 0.0;
+    PINV_BAIL(launch_gemm_f64(p, s));
+    GemmF64Args t{};
+    t.A = Kb + (int64_t)r0 * ld + k0; t.lda = ld; t.a_kcontig = 1;
+    t.B = Kb + (int64_t)r0 * ld + k0; t.ldb = ld; t.b_kcontig = 1;
+    t.C = Kb + (int64_t)r0 * ld + r0; t.csm = ld; t.csn = 1;
+    t.M = rn; t.N = rn; t.K = kn; t.alpha = -1.0; t.beta = 1.0; t.tri = 1;
+    PINV_BAIL(launch_gemm_f64(t, s));
+  }
+
+  // W = L^{-1}: block row i is Wd_i (E_i - sum_{k<i} L_ik W_k), accumulated right-looking in Wb
+  for (int ib = 0; ib < nblk; ++ib) {
+    const int i0 = ib * NB, in_ = (n - i0 < NB) ? n - i0 : NB;
+    const double* wd = Wd + (size_t)ib * NB * NB;
+    hipLaunchKernelGGL(set_identity_kernel, dim3((in_ * in_ + 255) / 256), dim3(256), 0, s, Wb + (int64_t)i0 * ld + i0,
+                       ld, in_);
+    PINV_BAIL(hipGetLastError());
+    GemmF64Args a{};
+    a.A = wd; a.lda = NB; a.a_kcontig = 1;
+    a.B = Wb + (int64_t)i0 * ld; a.ldb = ld; a.b_kcontig = 0;
+    a.C = Wb + (int64_t)i0 * ld; a.csm = ld; a.csn = 1;
+    a.M = in_; a.N = i0 + in_; a.K = in_; a.alpha = 1.0; a.beta = 0.0;
+    PINV_BAIL(launch_gemm_f64(a, s));
+    const int r0 = i0 + in_, rn = n - r0;
+    if (rn <= 0) continue;
+    GemmF64Args b{};
+    b.A = Kb + (int64_t)r0 * ld + i0; b.lda = ld; b.a_kcontig = 1;
+    b.B = Wb + (int64_t)i0 * ld; b.ldb = ld; b.b_kcontig = 0;
+    b.C = Wb + (int64_t)r0 * ld; b.csm = ld; b.csn = 1;
+    b.M = rn; b.N = r0; b.K = in_; b.alpha = -1.0; b.beta = 1.0;
+    PINV_BAIL(launch_gemm_f64(b, s));
+  }
+
+  // G = W^T W (into Kb)
+  {
+    GemmF64Args g{};
+    g.A = Wb; g.lda = ld; g.a_kcontig = 0;
+    g.B = Wb; g.ldb = ld; g.b_kcontig = 0;
+    g.C = Kb; g.csm = ld; g.csn = 1;
+    g.M = n; g.N = n; g.K = n; g.alpha = 1.0; g.beta = 0.0; g.kdiag = 1;
+    PINV_BAIL(launch_gemm_f64(g, s));
+  }
+  if (ub_dev) {
+    PINV_BAIL(hipMalloc(&op->w, (size_t)n * sizeof(double)));
+    op->bytes += (int64_t)n * sizeof(double);
+    PINV_BAIL(launch_gemv_f64(Kb, ld, n, bB, n, 1, 1.0, nullptr, op->w, n, s));
+  }
+  {
+    int hflag = 0;
+    PINV_BAIL(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    PINV_BAIL(hipStreamSynchronize(s));
+    if (hflag) {
+      st = PINV_E_NOT_SPD;
+      goto done;
+    }
+  }
+  op->G = Kb;
+  op->bytes += (int64_t)mat_bytes;
+  Kb = nullptr;
+
+done:
+#undef PINV_BAIL
+  if (st != PINV_OK) hipStreamSynchronize(s);
+  if (Kb) (void)hipFree(Kb);
+  if (Wb) (void)hipFree(Wb);
+  if (Wd) (void)hipFree(Wd);
+  if (bB) (void)hipFree(bB);
+  if (flag) (void)hipFree(flag);
+  return st;
+}

@@ -1,0 +1,514 @@
+// C-ABI entry points of libpinv (declared in include/pinv.h): argument checks,
+// ownership of device memory, and dispatch to the kernels.
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <cmath>
+#include <mutex>
+#include <new>
+
+#include "common.h"
+
+// ---------------------------------------------------------------------------
+// helpers
+
+int32_t pinv_hip_status(hipError_t e) {
+  if (e == hipSuccess) return PINV_OK;
+  (void)hipGetLastError();
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return PINV_E_OOM;
+  return PINV_E_HIP;
+}
+
+void pinv_log(const char* fmt, ...) {
+  static const bool on = [] {
+    const char* v = std::getenv("PINV_LOG");
+    return v && *v && std::strcmp(v, "0") != 0;
+  }();
+  if (!on) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fprintf(stderr, "[pinv] ");
+  std::vfprintf(stderr, fmt, ap);
+  std::fprintf(stderr, "\n");
+  va_end(ap);
+}
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// The stream-ordered pool keeps freed scratch cached, so the per-call scratch
+// of the apply (quantised right-hand sides) costs no device allocation after
+// the first call of a given size.
+void configure_pool_once() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  });
+}
+
+bool grid_ok(const pinv_grid* g) {
+  if (!g) return false;
+  if (g->nx < 3 || g->ny < 3) return false;
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return false;
+  const int64_t n = (int64_t)(g->nx - 2) * (int64_t)(g->ny - 2);
+  return n <= (int64_t)1 << 20;  // dense N x N inverse: 8 TB at this bound
+}
+
+pinv_op new_op(const pinv_grid* g) {
+  pinv_op op = new (std::nothrow) pinv_op_s();
+  if (!op) return nullptr;
+  op->nx = g->nx;
+  op->ny = g->ny;
+  op->mx = g->nx - 2;
+  op->my = g->ny - 2;
+  op->n = op->mx * op->my;
+  op->h = g->h;
+  op->ldg = (op->n + 31) / 32 * 32;
+  (void)hipGetDevice(&op->device);
+  return op;
+}
+
+void free_quant(pinv_op op) {
+  if (op->Q) (void)hipFree(op->Q);
+  if (op->QT) (void)hipFree(op->QT);
+  if (op->e) (void)hipFree(op->e);
+  if (op->S) op->bytes -= 2 * (int64_t)op->S * op->P * op->P + op->P * (int64_t)sizeof(int32_t);
+  op->Q = op->QT = nullptr;
+  op->e = nullptr;
+  op->S = 0;
+}
+
+void free_op(pinv_op op) {
+  if (!op) return;
+  (void)hipDeviceSynchronize();
+  free_quant(op);
+  if (op->G) (void)hipFree(op->G);
+  if (op->w) (void)hipFree(op->w);
+  if (op->ub) (void)hipFree(op->ub);
+  if (op->G32) (void)hipFree(op->G32);
+  if (op->Gb) (void)hipFree(op->Gb);
+  delete op;
+}
+
+int32_t copy_nodal(const double* host, int nodes, double** dev, hipStream_t s) {
+  *dev = nullptr;
+  if (!host) return PINV_OK;
+  PINV_HIP_TRY(hipMalloc(dev, (size_t)nodes * sizeof(double)));
+  hipError_t e = hipMemcpyAsync(*dev, host, (size_t)nodes * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    (void)hipFree(*dev);
+    *dev = nullptr;
+    return pinv_hip_status(e);
+  }
+  return PINV_OK;
+}
+
+bool boundary_nonzero(const pinv_grid* g, const double* ub) {
+  if (!ub) return false;
+  for (int i = 0; i < g->ny; ++i)
+    for (int j = 0; j < g->nx; ++j) {
+      const bool b = (i == 0 || i == g->ny - 1 || j == 0 || j == g->nx - 1);
+      if (b && ub[(int64_t)i * g->nx + j] != 0.0) return true;
+    }
+  return false;
+}
+
+int slices_of_bits(int bits) { return (bits == 8 || bits == 16 || bits == 24) ? bits / 8 : 0; }
+
+// int32 class headroom: the largest class has min(S, SR) slice pairs, each
+// contributing at most n * 128 * 128 in magnitude.  The int64 recombination
+// needs n * M_S * M_SR < 2^63.
+bool int8_headroom_ok(int n, int S, int SR) {
+  const int pairs = S < SR ? S : SR;
+  const double cls = (double)n * 16384.0 * pairs;
+  if (cls >= 2147483648.0) return false;
+  const double tot = (double)n * (double)pinv_max_mag(S) * (double)pinv_max_mag(SR);
+  return tot < 9.2e18;
+}
+
+int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const int32_t* pre_exp, int SR,
+                   const double* X, int64_t ldx, int nrhs, const double* w, double* U, int64_t ldu,
+                   hipStream_t s) {
+  const int Rpad = (nrhs + 127) / 128 * 128;
+  const size_t xq_bytes = (size_t)SR * Rpad * op->P;
+  const size_t f_bytes = (size_t)Rpad * sizeof(int32_t);
+  void* scratch = nullptr;
+  configure_pool_once();
+  PINV_HIP_TRY(hipMallocAsync(&scratch, xq_bytes + f_bytes, s));
+  int8_t* Xq = (int8_t*)scratch;
+  int32_t* f = (int32_t*)((char*)scratch + xq_bytes);
+  hipError_t e = launch_quantize_cols(X, ldx, op->n, nrhs, Rpad, SR, op->P, pre_exp, Xq, f, s);
+  if (e == hipSuccess) {
+    GemmI8Args a{};
+    a.Q = Q; a.S = op->S;
+    a.X = Xq; a.SR = SR;
+    a.P = op->P; a.Rpad = Rpad;
+    a.n = op->n; a.nrhs = nrhs;
+    a.row_exp = row_exp;
+    a.col_exp = f;
+    a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
+    a.w = w;
+    a.U = U; a.ldu = ldu;
+    e = launch_gemm_i8(a, s);
+  }
+  hipError_t e2 = hipFreeAsync(scratch, s);
+  if (e != hipSuccess) return pinv_hip_status(e);
+  return pinv_hip_status(e2);
+}
+
+int32_t fp64_apply(pinv_op op, bool transpose, const double* X, int64_t ldx, int nrhs, const double* bias,
+                   double* U, int64_t ldu, hipStream_t s) {
+  const double alpha = -(op->h * op->h);
+  if (!transpose && nrhs <= 4) {
+    PINV_HIP_TRY(launch_gemv_f64(op->G, op->ldg, op->n, X, ldx, nrhs, alpha, bias, U, ldu, s));
+    return PINV_OK;
+  }
+  GemmF64Args a{};
+  a.A = op->G; a.lda = op->ldg; a.a_kcontig = transpose ? 0 : 1;
+  a.B = X; a.ldb = ldx; a.b_kcontig = 1;
+  a.C = U; a.csm = 1; a.csn = ldu;
+  a.M = op->n; a.N = nrhs; a.K = op->n;
+  a.alpha = alpha; a.beta = 0.0; a.bias = bias;
+  PINV_HIP_TRY(launch_gemm_f64(a, s));
+  return PINV_OK;
+}
+
+int32_t check_vectors(pinv_op op, const void* in, int64_t ld_in, int nrhs, const void* out, int64_t ld_out) {
+  if (!op) return PINV_E_INVALID_ARG;
+  if (nrhs < 0) return PINV_E_INVALID_ARG;
+  if (nrhs == 0) return PINV_OK;
+  if (!in || !out) return PINV_E_INVALID_ARG;
+  if (ld_in < op->n || ld_out < op->n) return PINV_E_INVALID_ARG;
+  // overlap check of the two column-major blocks
+  const char* a0 = (const char*)in;
+  const char* a1 = a0 + ((int64_t)(nrhs - 1) * ld_in + op->n) * 8;
+  const char* b0 = (const char*)out;
+  const char* b1 = b0 + ((int64_t)(nrhs - 1) * ld_out + op->n) * 8;
+  if (a0 < b1 && b0 < a1) return PINV_E_INVALID_ARG;
+  return PINV_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// entry points
+
+extern "C" {
+
+const char* pinv_version(void) { return "0.1.0"; }
+
+const char* pinv_status_string(int32_t st) {
+  switch (st) {
+    case PINV_OK: return "ok";
+    case PINV_E_INVALID_ARG: return "invalid argument";
+    case PINV_E_NOT_SPD: return "operator is not symmetric positive definite (non-positive Cholesky pivot)";
+    case PINV_E_OOM: return "out of device memory";
+    case PINV_E_HIP: return "HIP runtime error";
+    case PINV_E_UNSUPPORTED: return "unsupported size or mode";
+    case PINV_E_STATE: return "the op does not hold the representation this call needs";
+    default: return "unknown status";
+  }
+}
+
+int32_t pinv_build_inverse(const pinv_grid* g, const double* eps_nodes, const double* u_boundary, void* stream,
+                           pinv_op* out) {
+  if (!out) return PINV_E_INVALID_ARG;
+  *out = nullptr;
+  if (!grid_ok(g)) return PINV_E_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  pinv_op op = new_op(g);
+  if (!op) return PINV_E_OOM;
+  const int nodes = g->nx * g->ny;
+  const size_t need = 2 * (size_t)op->n * op->ldg * sizeof(double);
+  size_t freeb = 0, totalb = 0;
+  if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need > freeb) {
+    delete op;
+    return PINV_E_OOM;
+  }
+  double *eps_d = nullptr, *ub_d = nullptr;
+  int32_t st = copy_nodal(eps_nodes, nodes, &eps_d, s);
+  if (st == PINV_OK && boundary_nonzero(g, u_boundary)) st = copy_nodal(u_boundary, nodes, &ub_d, s);
+  if (st == PINV_OK) st = build_inverse_device(op, eps_d, ub_d, s);
+  if (eps_d) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(eps_d);
+  }
+  if (st != PINV_OK) {
+    if (ub_d) (void)hipFree(ub_d);
+    free_op(op);
+    return st;
+  }
+  op->ub = ub_d;
+  if (ub_d) op->bytes += (int64_t)nodes * sizeof(double);
+  pinv_log("build_inverse: n=%d ldg=%lld bytes=%lld", op->n, (long long)op->ldg, (long long)op->bytes);
+  *out = op;
+  return PINV_OK;
+}
+
+int32_t pinv_import_inverse(const pinv_grid* g, const double* G_host, int64_t ldg, const double* eps_nodes,
+                            const double* u_boundary, const double* w_host, void* stream, pinv_op* out) {
+  if (!out) return PINV_E_INVALID_ARG;
+  *out = nullptr;
+  if (!grid_ok(g) || !G_host) return PINV_E_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  pinv_op op = new_op(g);
+  if (!op) return PINV_E_OOM;
+  if (ldg < op->n) {
+    delete op;
+    return PINV_E_INVALID_ARG;
+  }
+  const int n = op->n, nodes = g->nx * g->ny;
+  int32_t st = PINV_OK;
+  hipError_t e = hipMalloc(&op->G, (size_t)n * op->ldg * sizeof(double));
+  if (e != hipSuccess) {
+    free_op(op);
+    return pinv_hip_status(e);
+  }
+  op->bytes += (int64_t)n * op->ldg * sizeof(double);
+  e = hipMemcpy2DAsync(op->G, op->ldg * sizeof(double), G_host, ldg * sizeof(double), n * sizeof(double), n,
+                       hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) st = pinv_hip_status(e);
+  const bool has_ub = boundary_nonzero(g, u_boundary);
+  if (st == PINV_OK && has_ub) {
+    st = copy_nodal(u_boundary, nodes, &op->ub, s);
+    if (st == PINV_OK) op->bytes += (int64_t)nodes * sizeof(double);
+  }
+  if (st == PINV_OK && (w_host || has_ub)) {
+    e = hipMalloc(&op->w, (size_t)n * sizeof(double));
+    if (e == hipSuccess) {
+      op->bytes += (int64_t)n * sizeof(double);
+      if (w_host) {
+        e = hipMemcpyAsync(op->w, w_host, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s);
+      } else {
+        double *eps_d = nullptr, *bB = nullptr;
+        st = copy_nodal(eps_nodes, nodes, &eps_d, s);
+        if (st == PINV_OK) {
+          e = hipMalloc(&bB, (size_t)n * sizeof(double));
+          if (e == hipSuccess) e = launch_assemble(g->nx, g->ny, eps_d, op->ub, nullptr, 0, bB, s);
+          if (e == hipSuccess) e = launch_gemv_f64(op->G, op->ldg, n, bB, n, 1, 1.0, nullptr, op->w, n, s);
+          (void)hipStreamSynchronize(s);
+          if (bB) (void)hipFree(bB);
+        }
+        if (eps_d) (void)hipFree(eps_d);
+      }
+    }
+    if (e != hipSuccess && st == PINV_OK) st = pinv_hip_status(e);
+  }
+  if (st == PINV_OK) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = pinv_hip_status(e);
+  }
+  if (st != PINV_OK) {
+    free_op(op);
+    return st;
+  }
+  *out = op;
+  return PINV_OK;
+}
+
+int32_t pinv_export_inverse(pinv_op op, double* G_host, int64_t ldg, double* w_host, void* stream) {
+  if (!op) return PINV_E_INVALID_ARG;
+  if (!op->G) return PINV_E_STATE;
+  hipStream_t s = as_stream(stream);
+  if (G_host) {
+    if (ldg < op->n) return PINV_E_INVALID_ARG;
+    PINV_HIP_TRY(hipMemcpy2DAsync(G_host, ldg * sizeof(double), op->G, op->ldg * sizeof(double),
+                                  op->n * sizeof(double), op->n, hipMemcpyDeviceToHost, s));
+  }
+  if (w_host) {
+    if (op->w)
+      PINV_HIP_TRY(hipMemcpyAsync(w_host, op->w, (size_t)op->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    else
+      std::memset(w_host, 0, (size_t)op->n * sizeof(double));
+  }
+  PINV_HIP_TRY(hipStreamSynchronize(s));
+  return PINV_OK;
+}
+
+int32_t pinv_quantize_inverse(pinv_op op, int32_t bits, int32_t scale_mode, int32_t keep_fp64, void* stream) {
+  if (!op) return PINV_E_INVALID_ARG;
+  const int S = slices_of_bits(bits);
+  if (!S || scale_mode != PINV_SCALE_ROW) return PINV_E_INVALID_ARG;
+  if (!op->G) return PINV_E_STATE;
+  hipStream_t s = as_stream(stream);
+  PINV_HIP_TRY(hipStreamSynchronize(s));
+  free_quant(op);
+  const int64_t P = pinv_pad_dim(op->n);
+  const size_t plane_bytes = (size_t)S * P * P;
+  hipError_t e = hipMalloc(&op->Q, plane_bytes);
+  if (e == hipSuccess) e = hipMalloc(&op->QT, plane_bytes);
+  if (e == hipSuccess) e = hipMalloc(&op->e, (size_t)P * sizeof(int32_t));
+  if (e != hipSuccess) {
+    free_quant(op);
+    return pinv_hip_status(e);
+  }
+  op->S = S;
+  op->P = P;
+  op->bytes += 2 * (int64_t)plane_bytes + P * (int64_t)sizeof(int32_t);
+  e = launch_quantize_rows(op->G, op->ldg, op->n, S, P, op->Q, op->e, s);
+  if (e == hipSuccess) e = launch_transpose_planes(op->Q, op->QT, S, P, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_quant(op);
+    return pinv_hip_status(e);
+  }
+  if (!keep_fp64) {
+    (void)hipFree(op->G);
+    op->G = nullptr;
+    op->bytes -= (int64_t)op->n * op->ldg * sizeof(double);
+  }
+  pinv_log("quantize_inverse: bits=%d P=%lld", bits, (long long)P);
+  return PINV_OK;
+}
+
+int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream) {
+  if (!op) return PINV_E_INVALID_ARG;
+  if (mode != PINV_FP32 && mode != PINV_BF16X3 && mode != PINV_BF16X6) return PINV_E_INVALID_ARG;
+  if (!op->G) return PINV_E_STATE;
+  hipStream_t s = as_stream(stream);
+  const int64_t P = pinv_pad_dim(op->n);
+  const size_t elems = (size_t)P * P;  // zero-padded P x P planes
+  if (mode == PINV_FP32) {
+    if (!op->G32) {
+      PINV_HIP_TRY(hipMalloc(&op->G32, elems * sizeof(float)));
+      op->bytes += (int64_t)(elems * sizeof(float));
+    }
+    PINV_HIP_TRY(launch_make_fp32(op->G, op->ldg, op->n, op->G32, s));
+  } else {
+    const int parts = mode == PINV_BF16X3 ? 2 : 3;
+    if (op->Gb && op->nbf < parts) {
+      (void)hipFree(op->Gb);
+      op->bytes -= (int64_t)(op->nbf * elems * sizeof(__bf16));
+      op->Gb = nullptr;
+      op->nbf = 0;
+    }
+    if (!op->Gb) {
+      PINV_HIP_TRY(hipMalloc(&op->Gb, parts * elems * sizeof(__bf16)));
+      op->bytes += (int64_t)(parts * elems * sizeof(__bf16));
+      op->nbf = parts;
+    }
+    PINV_HIP_TRY(launch_make_bf16_parts(op->G, op->ldg, op->n, op->nbf, op->Gb, s));
+  }
+  PINV_HIP_TRY(hipStreamSynchronize(s));
+  return PINV_OK;
+}
+
+int32_t pinv_export_quantized(pinv_op op, int8_t* slices_host, int32_t* exponents_host, void* stream) {
+  if (!op) return PINV_E_INVALID_ARG;
+  if (!op->S) return PINV_E_STATE;
+  hipStream_t s = as_stream(stream);
+  const int n = op->n;
+  if (slices_host)
+    for (int p = 0; p < op->S; ++p)
+      PINV_HIP_TRY(hipMemcpy2DAsync(slices_host + (int64_t)p * n * n, n, op->Q + (int64_t)p * op->P * op->P, op->P, n,
+                                    n, hipMemcpyDeviceToHost, s));
+  if (exponents_host)
+    PINV_HIP_TRY(hipMemcpyAsync(exponents_host, op->e, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PINV_HIP_TRY(hipStreamSynchronize(s));
+  return PINV_OK;
+}
+
+int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits, const double* rho, int64_t ld_rho,
+                           int32_t nrhs, double* u, int64_t ld_u, void* stream) {
+  int32_t st = check_vectors(op, rho, ld_rho, nrhs, u, ld_u);
+  if (st != PINV_OK || nrhs == 0) return st;
+  hipStream_t s = as_stream(stream);
+  switch (mode) {
+    case PINV_FP64:
+      if (!op->G) return PINV_E_STATE;
+      return fp64_apply(op, false, rho, ld_rho, nrhs, op->w, u, ld_u, s);
+    case PINV_INT8: {
+      const int SR = slices_of_bits(rho_bits);
+      if (!SR) return PINV_E_INVALID_ARG;
+      if (!op->S) return PINV_E_STATE;
+      if (!int8_headroom_ok(op->n, op->S, SR)) return PINV_E_UNSUPPORTED;
+      return int8_apply(op, op->Q, op->e, nullptr, SR, rho, ld_rho, nrhs, op->w, u, ld_u, s);
+    }
+    case PINV_FP32:
+    case PINV_BF16X3:
+    case PINV_BF16X6: {
+      if (mode == PINV_FP32 ? !op->G32 : (!op->Gb || op->nbf < (mode == PINV_BF16X3 ? 2 : 3))) return PINV_E_STATE;
+      configure_pool_once();
+      const size_t sb = split_scratch_bytes(mode, op, nrhs);
+      void* scratch = nullptr;
+      PINV_HIP_TRY(hipMallocAsync(&scratch, sb ? sb : 256, s));
+      hipError_t e = launch_gemm_split(mode, op, rho, ld_rho, nrhs, -(op->h * op->h), u, ld_u, s, scratch, sb);
+      hipError_t e2 = hipFreeAsync(scratch, s);
+      if (e != hipSuccess) return pinv_hip_status(e);
+      return pinv_hip_status(e2);
+    }
+    default:
+      return PINV_E_INVALID_ARG;
+  }
+}
+
+int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits, const double* g, int64_t ld_g,
+                                   int32_t nrhs, double* lambda, int64_t ld_lambda, void* stream) {
+  int32_t st = check_vectors(op, g, ld_g, nrhs, lambda, ld_lambda);
+  if (st != PINV_OK || nrhs == 0) return st;
+  hipStream_t s = as_stream(stream);
+  switch (mode) {
+    case PINV_FP64:
+      if (!op->G) return PINV_E_STATE;
+      return fp64_apply(op, true, g, ld_g, nrhs, nullptr, lambda, ld_lambda, s);
+    case PINV_INT8: {
+      const int SR = slices_of_bits(g_bits);
+      if (!SR) return PINV_E_INVALID_ARG;
+      if (!op->S) return PINV_E_STATE;
+      if (!int8_headroom_ok(op->n, op->S, SR)) return PINV_E_UNSUPPORTED;
+      return int8_apply(op, op->QT, nullptr, op->e, SR, g, ld_g, nrhs, nullptr, lambda, ld_lambda, s);
+    }
+    default:
+      return PINV_E_UNSUPPORTED;
+  }
+}
+
+int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u, const double* lambda, int64_t ld_lambda,
+                      int32_t nrhs, double* grad_nodes, void* stream) {
+  if (!op || !grad_nodes || nrhs < 0) return PINV_E_INVALID_ARG;
+  if (nrhs > 0 && (!u || !lambda || ld_u < op->n || ld_lambda < op->n)) return PINV_E_INVALID_ARG;
+  PINV_HIP_TRY(launch_grad_eps(op->nx, op->ny, op->h, u, ld_u, lambda, ld_lambda, nrhs, op->ub, grad_nodes,
+                               as_stream(stream)));
+  return PINV_OK;
+}
+
+int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode, int32_t rho_bits, void* stream) {
+  if (nreq < 0 || (nreq > 0 && !reqs)) return PINV_E_INVALID_ARG;
+  for (int i = 0; i < nreq; ++i) {
+    int32_t st = pinv_apply_inverse(reqs[i].op, mode, rho_bits, reqs[i].rho, reqs[i].ld, reqs[i].nrhs, reqs[i].u,
+                                    reqs[i].ld, stream);
+    if (st != PINV_OK) return st;
+  }
+  return PINV_OK;
+}
+
+int32_t pinv_get_info(pinv_op op, pinv_info* info) {
+  if (!op || !info) return PINV_E_INVALID_ARG;
+  info->nx = op->nx;
+  info->ny = op->ny;
+  info->n = op->n;
+  info->h = op->h;
+  info->has_fp64 = op->G != nullptr;
+  info->int8_slices = op->S;
+  info->has_fp32 = op->G32 != nullptr;
+  info->has_bf16 = op->nbf;
+  info->has_lift = op->w != nullptr;
+  info->device_bytes = op->bytes;
+  return PINV_OK;
+}
+
+int32_t pinv_destroy(pinv_op op) {
+  if (!op) return PINV_E_INVALID_ARG;
+  free_op(op);
+  return PINV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Internal declarations of the pinv library (gfx950 / CDNA4 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+#include "pinv.h"
+
+typedef int    v4i  __attribute__((ext_vector_type(4)));
+typedef double v4d  __attribute__((ext_vector_type(4)));
+typedef float  v4f  __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+#define PINV_WAVE 64
+
+// Padded square dimension of the int8 digit planes and of split-precision
+// copies: a multiple of 256 so that every 128x128 (or 256-row) tile and every
+// 64/128-byte k chunk lies inside the allocation; the padding holds zeros.
+static inline int64_t pinv_pad_dim(int64_t n) { return (n + 255) / 256 * 256; }
+
+struct pinv_op_s {
+  int nx = 0, ny = 0, mx = 0, my = 0, n = 0;
+  double h = 0.0;
+  int device = 0;
+
+  // FP64 inverse, row-major [n][ldg] (ldg multiple of 32 doubles)
+  double* G = nullptr;
+  int64_t ldg = 0;
+  double* w = nullptr;       // lift [n] (nullptr when the Dirichlet data is zero)
+  double* ub = nullptr;      // nodal Dirichlet data [ny*nx] (nullptr when zero)
+
+  // per-row fixed point, S balanced int8 digit planes [S][P][P] (k fastest),
+  // the transposed planes for the adjoint, and the row exponents [P]
+  int S = 0;
+  int64_t P = 0;
+  int8_t* Q = nullptr;
+  int8_t* QT = nullptr;
+  int32_t* e = nullptr;
+
+  // split-precision copies, zero-padded row-major planes [P][P]
+  float* G32 = nullptr;
+  __bf16* Gb = nullptr;      // [nbf][P][P]
+  int nbf = 0;               // number of bfloat16 parts held (2 or 3)
+
+  int64_t bytes = 0;
+};
+
+// ---- error handling ---------------------------------------------------------
+#define PINV_HIP_TRY(expr)                                   \
+  do {                                                       \
+    hipError_t e__ = (expr);                                 \
+    if (e__ != hipSuccess) return pinv_hip_status(e__);      \
+  } while (0)
+
+int32_t pinv_hip_status(hipError_t e);
+void pinv_log(const char* fmt, ...);
+
+// ---- FP64 MFMA GEMM -----------------------------------------------------------
+// C(m,n) = alpha * sum_{k in [kbeg, K)} A(m,k) B(k,n) + beta * C(m,n) + bias[m]
+// A(m,k) = A[m*lda + k] if a_kcontig else A[k*lda + m]
+// B(k,n) = B[n*ldb + k] if b_kcontig else B[k*ldb + n]
+// C(m,n) = C[m*csm + n*csn]
+// tri: 0 = full; 1 = skip tiles strictly above the diagonal (n0 > m0 + BM - 1)
+// kdiag: if nonzero, the k range of a tile starts at max(m0, n0) rounded down to
+//        the k step (both operands are zero for k below their own row/column
+//        index, as for A(m,k) = W[k][m], B(k,n) = W[k][n] with W lower triangular).
+struct GemmF64Args {
+  const double* A; int64_t lda; int a_kcontig;
+  const double* B; int64_t ldb; int b_kcontig;
+  double* C; int64_t csm, csn;
+  int M, N, K;
+  double alpha, beta;
+  const double* bias;
+  int tri, kdiag;
+};
+hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t s);
+
+// FP64 GEMV-style apply for few right-hand sides: u = alpha * G x + bias.
+hipError_t launch_gemv_f64(const double* G, int64_t ldg, int n, const double* x, int64_t ldx,
+                           int nrhs, double alpha, const double* bias, double* u, int64_t ldu,
+                           hipStream_t s);
+
+// ---- setup kernels ------------------------------------------------------------
+hipError_t launch_assemble(int nx, int ny, const double* eps, const double* ub, double* K,
+                           int64_t ldk, double* bB, hipStream_t s);
+int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub_dev,
+                             hipStream_t s);
+
+// ---- quantisation -------------------------------------------------------------
+int64_t pinv_max_mag(int S);
+hipError_t launch_quantize_rows(const double* G, int64_t ldg, int n, int S, int64_t P,
+                                int8_t* Q, int32_t* e, hipStream_t s);
+hipError_t launch_transpose_planes(const int8_t* Q, int8_t* QT, int S, int64_t P, hipStream_t s);
+// digits of X (column-major n x nrhs, stride ldx) per column into [SR][Rpad][P];
+// pre_exp (may be null) multiplies row k by 2^pre_exp[k] first.
+hipError_t launch_quantize_cols(const double* X, int64_t ldx, int n, int nrhs, int Rpad, int SR,
+                                int64_t P, const int32_t* pre_exp, int8_t* Xq, int32_t* f,
+                                hipStream_t s);
+
+// ---- int8 digit-slice GEMM ------------------------------------------------------
+struct GemmI8Args {
+  const int8_t* Q; int S;          // [S][P][P]
+  const int8_t* X; int SR;         // [SR][Rpad][P]
+  int64_t P; int Rpad;
+  int n, nrhs;
+  const int32_t* row_exp;          // [P] or null
+  const int32_t* col_exp;          // [nrhs]
+  double c;                        // -h^2 / (M_S M_SR)
+  const double* w;                 // [n] or null
+  double* U; int64_t ldu;
+};
+hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s);
+
+// ---- split precision ----------------------------------------------------------
+hipError_t launch_make_fp32(const double* G, int64_t ldg, int n, float* G32, hipStream_t s);
+hipError_t launch_make_bf16_parts(const double* G, int64_t ldg, int n, int parts, __bf16* Gb,
+                                  hipStream_t s);
+hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int64_t ldx,
+                             int nrhs, double alpha, double* U, int64_t ldu, hipStream_t s,
+                             void* scratch, size_t scratch_bytes);
+size_t split_scratch_bytes(int mode, const pinv_op_s* op, int nrhs);
+
+// ---- gradient ------------------------------------------------------------------
+hipError_t launch_grad_eps(int nx, int ny, double h, const double* u, int64_t ldu,
+                           const double* lam, int64_t ldl, int nrhs, const double* ub,
+                           double* grad, hipStream_t s);

@@ -1,0 +1,228 @@
+// FP64 matrix-core GEMM and GEMV.
+//
+// The GEMM is the workhorse of the one-time inversion (Cholesky panel and
+// trailing updates, the triangular inverse, G = L^{-T} L^{-1}) and of the plain
+// FP64 apply u = -h^2 G rho + w (the N^2-per-vector product the paper's method
+// repeats at every time moment).
+//
+// Tiling: 128x128 output tile per 256-thread workgroup (4 waves in 2x2, each
+// 64x64 = 4x4 blocks of v_mfma_f64_16x16x4f64), k step 16, two LDS stages with
+// register prefetch of the next stage (one barrier per step).  LDS holds both
+// operands k-major ([k][m], [k][n]) padded by 16 doubles so that the two
+// half-waves of a 64-bit read hit disjoint banks.
+//
+// v_mfma_f64_16x16x4f64 operand/result layout (lane l, result register r):
+//   A(i = l%16, k = l/16), B(k = l/16, j = l%16), D(i = l/16 + 4r, j = l%16).
+//
+// Workgroup -> tile mapping is XCD-aware: workgroup b runs on XCD b % 8, and
+// XCD x is handed a contiguous range of tiles (row-major over tiles), so the
+// column tiles that share one row block of A run on the same XCD and share
+// its L2.
+
+#include "common.h"
+
+namespace {
+
+constexpr int BM = 128, BN = 128, BKK = 16, LDP = 128 + 16;
+constexpr int NTHREADS = 256;
+
+__device__ inline void tile_of(int bid, int tilesM, int tilesN, int& mt, int& nt, bool& valid) {
+  const int T = tilesM * tilesN;
+  const int per = (T + 7) / 8;
+  const int tile = (bid % 8) * per + bid / 8;
+  valid = tile < T;
+  mt = valid ? tile / tilesN : 0;
+  nt = valid ? tile % tilesN : 0;
+}
+
+template <bool AK, bool BKc>
+__global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_kernel(GemmF64Args a, int tilesM, int tilesN) {
+  __shared__ double As[2][BKK][LDP];
+  __shared__ double Bs[2][BKK][LDP];
+
+  int mt, nt;
+  bool valid;
+  tile_of(blockIdx.x, tilesM, tilesN, mt, nt, valid);
+  if (!valid) return;
+  const int m0 = mt * BM, n0 = nt * BN;
+  if (a.tri == 1 && n0 > m0 + BM - 1) return;
+  int kbeg = 0;
+  if (a.kdiag) kbeg = (max(m0, n0) / BKK) * BKK;
+  const int K = a.K;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  double ra[8], rb[8];
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int idx = i * NTHREADS + tid;
+      int kk, mm;
+      if (AK) { kk = idx & 15; mm = idx >> 4; } else { kk = idx >> 7; mm = idx & 127; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gm < a.M && gk < K) v = AK ? a.A[(int64_t)gm * a.lda + gk] : a.A[(int64_t)gk * a.lda + gm];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int idx = i * NTHREADS + tid;
+      int kk, nn;
+      if (BKc) { kk = idx & 15; nn = idx >> 4; } else { kk = idx >> 7; nn = idx & 127; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      double v = 0.0;
+      if (gn < a.N && gk < K) v = BKc ? a.B[(int64_t)gn * a.ldb + gk] : a.B[(int64_t)gk * a.ldb + gn];
+      rb[i] = v;
+    }
+  };
+  auto store = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int idx = i * NTHREADS + tid;
+      int kk, mm;
+      if (AK) { kk = idx & 15; mm = idx >> 4; } else { kk = idx >> 7; mm = idx & 127; }
+      As[st][kk][mm] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int idx = i * NTHREADS + tid;
+      int kk, nn;
+      if (BKc) { kk = idx & 15; nn = idx >> 4; } else { kk = idx >> 7; nn = idx & 127; }
+      Bs[st][kk][nn] = rb[i];
+    }
+  };
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  int st = 0;
+  if (kbeg < K) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < K; k0 += BKK) {
+    const bool has_next = k0 + BKK < K;
+    if (has_next) load(k0 + BKK);
+#pragma unroll
+    for (int k4 = 0; k4 < BKK / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      double fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[i] = As[st][kr][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[j] = Bs[st][kr][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (has_next) store(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+
+  // epilogue: C = alpha*acc + beta*C + bias
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * r;
+        if (m < a.M && n < a.N) {
+          double* c = a.C + (int64_t)m * a.csm + (int64_t)n * a.csn;
+          double v = a.alpha * acc[i][j][r];
+          if (a.beta != 0.0) v += a.beta * *c;
+          if (a.bias) v += a.bias[m];
+          *c = v;
+        }
+      }
+    }
+  }
+}
+
+// One wave per row of G; lanes stride over k; up to 8 right-hand sides.
+template <int NR>
+__global__ __launch_bounds__(256) void gemv_f64_kernel(const double* __restrict__ G, int64_t ldg, int n,
+                                                      const double* __restrict__ x, int64_t ldx, double alpha,
+                                                      const double* __restrict__ bias, double* __restrict__ u,
+                                                      int64_t ldu) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double* g = G + (int64_t)row * ldg;
+  double s[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) s[r] = 0.0;
+  for (int k = lane; k < n; k += 64) {
+    const double gv = g[k];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s[r] = fma(gv, x[(int64_t)r * ldx + k], s[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    double v = s[r];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    s[r] = v;
+  }
+  if (lane < NR) {
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r == lane) v = s[r];
+    v = alpha * v;
+    if (bias) v += bias[row];
+    u[(int64_t)lane * ldu + row] = v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0) return hipSuccess;
+  const int tilesM = (a.M + BM - 1) / BM, tilesN = (a.N + BN - 1) / BN;
+  const int T = tilesM * tilesN;
+  const int grid = ((T + 7) / 8) * 8;
+  if (a.a_kcontig && a.b_kcontig)
+    hipLaunchKernelGGL((gemm_f64_kernel<true, true>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);
+  else if (a.a_kcontig && !a.b_kcontig)
+    hipLaunchKernelGGL((gemm_f64_kernel<true, false>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);
+  else if (!a.a_kcontig && !a.b_kcontig)
+    hipLaunchKernelGGL((gemm_f64_kernel<false, false>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<false, true>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_f64(const double* G, int64_t ldg, int n, const double* x, int64_t ldx, int nrhs,
+                           double alpha, const double* bias, double* u, int64_t ldu, hipStream_t s) {
+  const int grid = (n + 3) / 4;
+  for (int r0 = 0; r0 < nrhs; r0 += 8) {
+    const int nr = nrhs - r0 < 8 ? nrhs - r0 : 8;
+    const double* xr = x + (int64_t)r0 * ldx;
+    double* ur = u + (int64_t)r0 * ldu;
+    switch (nr) {
+#define PINV_GEMV_CASE(R)                                                                               \
+  case R:                                                                                               \
+    hipLaunchKernelGGL((gemv_f64_kernel<R>), dim3(grid), dim3(256), 0, s, G, ldg, n, xr, ldx, alpha, bias, \
+                       ur, ldu);                                                                        \
+    break;
+      PINV_GEMV_CASE(1) PINV_GEMV_CASE(2) PINV_GEMV_CASE(3) PINV_GEMV_CASE(4)
+      PINV_GEMV_CASE(5) PINV_GEMV_CASE(6) PINV_GEMV_CASE(7) PINV_GEMV_CASE(8)
+#undef PINV_GEMV_CASE
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}

@@ -1,0 +1,198 @@
+// Rounding of the inverse's entries (the experiment behind Table 1), restated
+// in binary fixed point so that the apply becomes an exact integer product.
+//
+// Rows of G (and columns of the right-hand sides) get one power-of-two scale
+// each: e = frexp exponent of the largest magnitude, so every scaled entry is
+// below 1 in magnitude.  An entry becomes q = rint((x * 2^-e) * M_S) with
+// M_S = 127 (256^S - 1)/255; the scaling is exact, the multiply rounds once,
+// rint rounds half to even.  q is stored as S balanced base-256 digits in
+// [-128, 127] (most significant first), one int8 plane per digit, in padded
+// P x P planes whose padding is zero.
+
+#include "common.h"
+
+namespace {
+
+__device__ inline int frexp_exp(double x) {
+  int e;
+  (void)frexp(x, &e);
+  return x == 0.0 ? 0 : e;
+}
+
+template <int S>
+__device__ inline void digits(int q, int8_t* d) {
+#pragma unroll
+  for (int s = S - 1; s >= 0; --s) {
+    const int lo = ((q + 128) & 255) - 128;
+    d[s] = (int8_t)lo;
+    q = (q - lo) >> 8;
+  }
+}
+
+__device__ inline double block_max_256(double v, double* red) {
+  // wave reduction then across the 4 waves
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  v = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return v;
+}
+
+// One wave per row: e[i] = exponent of max_k |G[i][k]| (0 for padding rows).
+__global__ __launch_bounds__(256) void row_exponent_kernel(const double* __restrict__ G, int64_t ldg, int n,
+                                                          int64_t P, int32_t* __restrict__ e) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= P) return;
+  double m = 0.0;
+  if (row < n) {
+    const double* g = G + (int64_t)row * ldg;
+    for (int k = lane; k < n; k += 64) m = fmax(m, fabs(g[k]));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if (lane == 0) e[row] = frexp_exp(m);
+}
+
+// Each thread: 16 consecutive k of one row -> 16 bytes per digit plane.
+template <int S>
+__global__ __launch_bounds__(256) void quantize_rows_kernel(const double* __restrict__ G, int64_t ldg, int n,
+                                                           int64_t P, const int32_t* __restrict__ e,
+                                                           int8_t* __restrict__ Q) {
+  const int64_t chunks = P / 16;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= P * chunks) return;
+  const int64_t row = gid / chunks;
+  const int64_t k0 = (gid % chunks) * 16;
+  const double M = (double)(127LL * ((1LL << (8 * S)) - 1) / 255);
+  int8_t d[S][16];
+  const int er = row < n ? e[row] : 0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int64_t k = k0 + t;
+    int q = 0;
+    if (row < n && k < n) {
+      const double x = G[row * ldg + k];
+      q = (int)rint(ldexp(x, -er) * M);
+    }
+    int8_t dd[S];
+    digits<S>(q, dd);
+#pragma unroll
+    for (int s = 0; s < S; ++s) d[s][t] = dd[s];
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    v4i v;
+    __builtin_memcpy(&v, d[s], 16);
+    *(v4i*)(Q + (int64_t)s * P * P + row * P + k0) = v;
+  }
+}
+
+// QT[s][k][i] = Q[s][i][k], 64x64 byte tiles through LDS.
+__global__ __launch_bounds__(256) void transpose_planes_kernel(const int8_t* __restrict__ Q, int8_t* __restrict__ QT,
+                                                              int64_t P) {
+  __shared__ int8_t t[64][64 + 4];
+  const int64_t tiles = P / 64;
+  const int64_t bi = blockIdx.x / tiles, bk = blockIdx.x % tiles;
+  const int s = blockIdx.y;
+  const int8_t* src = Q + (int64_t)s * P * P;
+  int8_t* dst = QT + (int64_t)s * P * P;
+  const int r = threadIdx.x >> 2, c = (threadIdx.x & 3) * 16;
+  v4i v = *(const v4i*)(src + (bi * 64 + r) * P + bk * 64 + c);
+  const int8_t* pv = (const int8_t*)&v;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) t[r][c + b] = pv[b];
+  __syncthreads();
+  int8_t o[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) o[b] = t[c + b][r];
+  v4i ov;
+  __builtin_memcpy(&ov, o, 16);
+  *(v4i*)(dst + (bk * 64 + r) * P + bi * 64 + c) = ov;
+}
+
+// One workgroup per column r of X (column-major n x nrhs, stride ldx); rows of
+// the output [SR][Rpad][P]; columns r >= nrhs are written as zeros.
+template <int SR>
+__global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __restrict__ X, int64_t ldx, int n,
+                                                           int nrhs, int Rpad, int64_t P,
+                                                           const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
+                                                           int32_t* __restrict__ f) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  const bool live = r < nrhs;
+  const double* x = X + (int64_t)r * ldx;
+  double m = 0.0;
+  if (live)
+    for (int k = threadIdx.x; k < n; k += 256) {
+      const double v = pre ? ldexp(x[k], pre[k]) : x[k];
+      m = fmax(m, fabs(v));
+    }
+  m = block_max_256(m, red);
+  const int fr = frexp_exp(m);
+  if (live && threadIdx.x == 0) f[r] = fr;
+  const double M = (double)(127LL * ((1LL << (8 * SR)) - 1) / 255);
+  for (int64_t k0 = (int64_t)threadIdx.x * 16; k0 < P; k0 += 256 * 16) {
+    int8_t d[SR][16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int64_t k = k0 + t;
+      int q = 0;
+      if (live && k < n) {
+        const double v = pre ? ldexp(x[k], pre[k]) : x[k];
+        q = (int)rint(ldexp(v, -fr) * M);
+      }
+      int8_t dd[SR];
+      digits<SR>(q, dd);
+#pragma unroll
+      for (int s = 0; s < SR; ++s) d[s][t] = dd[s];
+    }
+#pragma unroll
+    for (int s = 0; s < SR; ++s) {
+      v4i v;
+      __builtin_memcpy(&v, d[s], 16);
+      *(v4i*)(Xq + ((int64_t)s * Rpad + r) * P + k0) = v;
+    }
+  }
+}
+
+}  // namespace
+
+int64_t pinv_max_mag(int S) { return 127LL * ((1LL << (8 * S)) - 1) / 255; }
+
+hipError_t launch_quantize_rows(const double* G, int64_t ldg, int n, int S, int64_t P, int8_t* Q, int32_t* e,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(row_exponent_kernel, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, s, G, ldg, n, P, e);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int64_t threads = P * (P / 16);
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  switch (S) {
+    case 1: hipLaunchKernelGGL(quantize_rows_kernel<1>, grid, dim3(256), 0, s, G, ldg, n, P, e, Q); break;
+    case 2: hipLaunchKernelGGL(quantize_rows_kernel<2>, grid, dim3(256), 0, s, G, ldg, n, P, e, Q); break;
+    case 3: hipLaunchKernelGGL(quantize_rows_kernel<3>, grid, dim3(256), 0, s, G, ldg, n, P, e, Q); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_planes(const int8_t* Q, int8_t* QT, int S, int64_t P, hipStream_t s) {
+  const int64_t tiles = P / 64;
+  hipLaunchKernelGGL(transpose_planes_kernel, dim3((unsigned)(tiles * tiles), (unsigned)S), dim3(256), 0, s, Q, QT, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize_cols(const double* X, int64_t ldx, int n, int nrhs, int Rpad, int SR, int64_t P,
+                                const int32_t* pre_exp, int8_t* Xq, int32_t* f, hipStream_t s) {
+  const dim3 grid((unsigned)Rpad);
+  switch (SR) {
+    case 1: hipLaunchKernelGGL(quantize_cols_kernel<1>, grid, dim3(256), 0, s, X, ldx, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
+    case 2: hipLaunchKernelGGL(quantize_cols_kernel<2>, grid, dim3(256), 0, s, X, ldx, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
+    case 3: hipLaunchKernelGGL(quantize_cols_kernel<3>, grid, dim3(256), 0, s, X, ldx, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}

@@ -1,0 +1,340 @@
+// Split-precision forms of step 3 (u = -h^2 G rho + w) on the matrix cores.
+//
+// FP32: G and rho rounded to float, v_mfma_f32_16x16x4f32, FP32 accumulation.
+// BF16xNP (NP = 2 -> "BF16x3", NP = 3 -> "BF16x6"): every FP64 value x is
+// written as x0 + x1 (+ x2) with x0 = bf16(x), x1 = bf16(x - x0), ... each
+// rounded to nearest even directly from FP64 (the residuals are exact in FP64);
+// the products a_i b_j with i + j <= NP - 1 are summed, the leading product in
+// one FP32 accumulator and the correction products in a second, combined in
+// FP64 at the end (the published bfloat16 split scheme of Henry, Tang and
+// Heinecke, ARITH 2019).
+//
+// The bf16 GEMM uses the same tile geometry as the int8 digit GEMM: a 64-byte
+// k chunk (32 bf16) per LDS row with 16 pad bytes, 128x128 tiles, 4 waves of
+// 64x64, v_mfma_f32_16x16x32_bf16 (lane l: A(i = l%16, k = 8*(l/16) + t),
+// B(k = 8*(l/16) + t, j = l%16), D(i = 4*(l/16) + r, j = l%16)).
+// G's parts and the right-hand sides' parts are stored zero-padded to P x P and
+// Rpad x P, so the main loops carry no bounds checks.
+
+#include "common.h"
+
+namespace {
+
+__device__ inline double round_bf16_exact(double x) {
+  // keep 8 significant bits, ties to even, directly from FP64
+  if (x == 0.0) return 0.0;
+  int e;
+  const double m = frexp(x, &e);
+  return ldexp(rint(ldexp(m, 8)), e - 8);
+}
+
+__device__ inline __bf16 to_bf16_exact(double v) {
+  // v already holds a bfloat16 value: the conversion to float is exact and so
+  // is float -> bf16 (any rounding mode)
+  return (__bf16)(float)v;
+}
+
+__global__ __launch_bounds__(256) void make_fp32_kernel(const double* __restrict__ G, int64_t ldg, int n, int64_t P,
+                                                       float* __restrict__ G32) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= P * P) return;
+  const int64_t i = idx / P, k = idx % P;
+  G32[idx] = (i < n && k < n) ? (float)G[i * ldg + k] : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void make_bf16_kernel(const double* __restrict__ G, int64_t ldg, int n, int64_t P,
+                                                       int parts, __bf16* __restrict__ Gb) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= P * P) return;
+  const int64_t i = idx / P, k = idx % P;
+  double rest = (i < n && k < n) ? G[i * ldg + k] : 0.0;
+  for (int p = 0; p < parts; ++p) {
+    const double v = round_bf16_exact(rest);
+    Gb[(int64_t)p * P * P + idx] = to_bf16_exact(v);
+    rest = rest - v;
+  }
+}
+
+// right-hand sides (column-major n x nrhs, stride ldx) -> [parts][Rpad][P] bf16
+__global__ __launch_bounds__(256) void pack_bf16_kernel(const double* __restrict__ X, int64_t ldx, int n, int nrhs,
+                                                       int Rpad, int64_t P, int parts, __bf16* __restrict__ Xb) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)Rpad * P) return;
+  const int64_t r = idx / P, k = idx % P;
+  double rest = (r < nrhs && k < n) ? X[r * ldx + k] : 0.0;
+  for (int p = 0; p < parts; ++p) {
+    const double v = round_bf16_exact(rest);
+    Xb[(int64_t)p * Rpad * P + idx] = to_bf16_exact(v);
+    rest = rest - v;
+  }
+}
+
+__global__ __launch_bounds__(256) void pack_fp32_kernel(const double* __restrict__ X, int64_t ldx, int n, int nrhs,
+                                                       int Rpad, int64_t P, float* __restrict__ Xf) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)Rpad * P) return;
+  const int64_t r = idx / P, k = idx % P;
+  Xf[idx] = (r < nrhs && k < n) ? (float)X[r * ldx + k] : 0.0f;
+}
+
+__device__ inline void tile_of(int bid, int tilesM, int tilesN, int& mt, int& nt, bool& valid) {
+  const int T = tilesM * tilesN;
+  const int per = (T + 7) / 8;
+  const int tile = (bid % 8) * per + bid / 8;
+  valid = tile < T;
+  mt = valid ? tile / tilesN : 0;
+  nt = valid ? tile % tilesN : 0;
+}
+
+struct SplitArgs {
+  const void* A;   // G parts [NP][P][P] (bf16) or G32 [P][P]
+  const void* B;   // rhs parts [NP][Rpad][P] or [Rpad][P] float
+  int64_t P;
+  int Rpad, n, nrhs;
+  double alpha;
+  const double* w;
+  double* U;
+  int64_t ldu;
+};
+
+constexpr int BM = 128, BN = 128, ROWB = 80;
+
+template <int NP>
+__global__ __launch_bounds__(256, 1) void gemm_bf16_kernel(SplitArgs a, int tilesM, int tilesN) {
+  constexpr int PLANE = BM * ROWB;
+  constexpr int STAGE = 2 * NP * PLANE;
+  __shared__ __attribute__((aligned(16))) int8_t sm[2 * STAGE];
+  int mt, nt;
+  bool valid;
+  tile_of(blockIdx.x, tilesM, tilesN, mt, nt, valid);
+  if (!valid) return;
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int64_t P = a.P;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow0 = tid >> 2, lch = tid & 3;
+  const int8_t* ga[NP];
+  const int8_t* gb[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    ga[p] = (const int8_t*)a.A + ((int64_t)p * P * P + (int64_t)(m0 + lrow0) * P) * 2 + lch * 16;
+    gb[p] = (const int8_t*)a.B + ((int64_t)p * a.Rpad * P + (int64_t)(n0 + lrow0) * P) * 2 + lch * 16;
+  }
+  const int64_t step64 = 64 * P * 2;
+  v4i pa[NP][2], pb[NP][2];
+  auto load = [&](int64_t kb) {  // kb: byte offset along k
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      pa[p][0] = *(const v4i*)(ga[p] + kb);
+      pa[p][1] = *(const v4i*)(ga[p] + step64 + kb);
+      pb[p][0] = *(const v4i*)(gb[p] + kb);
+      pb[p][1] = *(const v4i*)(gb[p] + step64 + kb);
+    }
+  };
+  auto store = [&](int st) {
+    int8_t* base = sm + st * STAGE;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      *(v4i*)(base + p * PLANE + lrow0 * ROWB + lch * 16) = pa[p][0];
+      *(v4i*)(base + p * PLANE + (lrow0 + 64) * ROWB + lch * 16) = pa[p][1];
+      *(v4i*)(base + (NP + p) * PLANE + lrow0 * ROWB + lch * 16) = pb[p][0];
+      *(v4i*)(base + (NP + p) * PLANE + (lrow0 + 64) * ROWB + lch * 16) = pb[p][1];
+    }
+  };
+  v4f big[4][4], small[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) big[i][j] = small[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int frag_off = (lane & 15) * ROWB + (lane >> 4) * 16;
+  const int64_t KB = P * 2;  // bytes along k
+  int st = 0;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int64_t kb = 0; kb < KB; kb += 64) {
+    const bool has_next = kb + 64 < KB;
+    if (has_next) load(kb + 64);
+    const int8_t* base = sm + st * STAGE;
+    v8bf fa[NP][4], fb[NP][4];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[p][i] = *(const v8bf*)(base + p * PLANE + (wm * 64 + i * 16) * ROWB + frag_off);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        fb[p][j] = *(const v8bf*)(base + (NP + p) * PLANE + (wn * 64 + j * 16) * ROWB + frag_off);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        big[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[0][j], big[i][j], 0, 0, 0);
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int q = 0; q < NP; ++q)
+            if (p + q > 0 && p + q <= NP - 1)
+              small[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[p][i], fb[q][j], small[i][j], 0, 0, 0);
+      }
+    if (has_next) store(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+      if (n >= a.nrhs) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        if (m >= a.n) continue;
+        double v = a.alpha * ((double)big[i][j][r] + (double)small[i][j][r]);
+        if (a.w) v += a.w[m];
+        a.U[(int64_t)n * a.ldu + m] = v;
+      }
+    }
+}
+
+// FP32: 128x128 tiles, k step 16 floats, v_mfma_f32_16x16x4f32
+// (lane l: A(i = l%16, k = l/16), B(k = l/16, j = l%16), D(i = 4*(l/16) + r, j = l%16)).
+__global__ __launch_bounds__(256, 2) void gemm_fp32_kernel(SplitArgs a, int tilesM, int tilesN) {
+  constexpr int BKK = 16, LDP = 128 + 32;
+  __shared__ float As[2][BKK][LDP];
+  __shared__ float Bs[2][BKK][LDP];
+  int mt, nt;
+  bool valid;
+  tile_of(blockIdx.x, tilesM, tilesN, mt, nt, valid);
+  if (!valid) return;
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int64_t P = a.P;
+  const float* A = (const float*)a.A;
+  const float* B = (const float*)a.B;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  // each thread loads 2 float4 of A and 2 of B per step: row = idx/4, k quad = idx%4
+  float4 ra[2], rb[2];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int idx = t * 256 + tid;
+      const int row = idx >> 2, kq = idx & 3;
+      ra[t] = *(const float4*)(A + (int64_t)(m0 + row) * P + k0 + kq * 4);
+      rb[t] = *(const float4*)(B + (int64_t)(n0 + row) * P + k0 + kq * 4);
+    }
+  };
+  auto store = [&](int st) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int idx = t * 256 + tid;
+      const int row = idx >> 2, kq = idx & 3;
+      As[st][kq * 4 + 0][row] = ra[t].x;
+      As[st][kq * 4 + 1][row] = ra[t].y;
+      As[st][kq * 4 + 2][row] = ra[t].z;
+      As[st][kq * 4 + 3][row] = ra[t].w;
+      Bs[st][kq * 4 + 0][row] = rb[t].x;
+      Bs[st][kq * 4 + 1][row] = rb[t].y;
+      Bs[st][kq * 4 + 2][row] = rb[t].z;
+      Bs[st][kq * 4 + 3][row] = rb[t].w;
+    }
+  };
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  int st = 0;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int64_t k0 = 0; k0 < P; k0 += BKK) {
+    const bool has_next = k0 + BKK < P;
+    if (has_next) load(k0 + BKK);
+#pragma unroll
+    for (int k4 = 0; k4 < BKK / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      float fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[i] = As[st][kr][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[j] = Bs[st][kr][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (has_next) store(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+      if (n >= a.nrhs) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        if (m >= a.n) continue;
+        double v = a.alpha * (double)acc[i][j][r];
+        if (a.w) v += a.w[m];
+        a.U[(int64_t)n * a.ldu + m] = v;
+      }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_make_fp32(const double* G, int64_t ldg, int n, float* G32, hipStream_t s) {
+  const int64_t P = pinv_pad_dim(n);
+  hipLaunchKernelGGL(make_fp32_kernel, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, s, G, ldg, n, P, G32);
+  return hipGetLastError();
+}
+
+hipError_t launch_make_bf16_parts(const double* G, int64_t ldg, int n, int parts, __bf16* Gb, hipStream_t s) {
+  const int64_t P = pinv_pad_dim(n);
+  hipLaunchKernelGGL(make_bf16_kernel, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, s, G, ldg, n, P, parts,
+                     Gb);
+  return hipGetLastError();
+}
+
+size_t split_scratch_bytes(int mode, const pinv_op_s* op, int nrhs) {
+  const int64_t P = pinv_pad_dim(op->n);
+  const int Rpad = (nrhs + 127) / 128 * 128;
+  if (mode == PINV_FP32) return (size_t)Rpad * P * sizeof(float);
+  const int parts = mode == PINV_BF16X3 ? 2 : 3;
+  return (size_t)parts * Rpad * P * sizeof(__bf16);
+}
+
+hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int64_t ldx, int nrhs, double alpha,
+                             double* U, int64_t ldu, hipStream_t s, void* scratch, size_t scratch_bytes) {
+  const int64_t P = pinv_pad_dim(op->n);
+  const int Rpad = (nrhs + 127) / 128 * 128;
+  if (scratch_bytes < split_scratch_bytes(mode, op, nrhs)) return hipErrorInvalidValue;
+  const int tilesM = (int)(P / BM), tilesN = Rpad / BN;
+  const int T = tilesM * tilesN;
+  const int grid = ((T + 7) / 8) * 8;
+  const unsigned pgrid = (unsigned)(((int64_t)Rpad * P + 255) / 256);
+  SplitArgs a{};
+  a.P = P; a.Rpad = Rpad; a.n = op->n; a.nrhs = nrhs; a.alpha = alpha; a.w = op->w; a.U = U; a.ldu = ldu;
+  a.B = scratch;
+  if (mode == PINV_FP32) {
+    hipLaunchKernelGGL(pack_fp32_kernel, dim3(pgrid), dim3(256), 0, s, X, ldx, op->n, nrhs, Rpad, P, (float*)scratch);
+    a.A = op->G32;
+    hipLaunchKernelGGL(gemm_fp32_kernel, dim3(grid), dim3(256), 0, s, a, tilesM, tilesN);
+  } else {
+    const int parts = mode == PINV_BF16X3 ? 2 : 3;
+    hipLaunchKernelGGL(pack_bf16_kernel, dim3(pgrid), dim3(256), 0, s, X, ldx, op->n, nrhs, Rpad, P, parts,
+                       (__bf16*)scratch);
+    a.A = op->Gb;
+    // G's parts are stored with op->nbf planes; the kernel reads the first `parts`
+    if (parts == 2)
+      hipLaunchKernelGGL(gemm_bf16_kernel<2>, dim3(grid), dim3(256), 0, s, a, tilesM, tilesN);
+    else
+      hipLaunchKernelGGL(gemm_bf16_kernel<3>, dim3(grid), dim3(256), 0, s, a, tilesM, tilesN);
+  }
+  return hipGetLastError();
+}

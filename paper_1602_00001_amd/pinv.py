@@ -1,0 +1,275 @@
+"""Python binding of libpinv (C-ABI in include/pinv.h): argument marshalling only.
+
+Every step of the solve runs in the HIP library; torch provides device memory
+(tensors) and streams.  Importing this module loads ``_lib/libpinv.so`` and
+fails loudly if it has not been built (``__graft_entry__.build()``).
+
+Layouts: right-hand sides, solutions and adjoint vectors are torch float64
+CUDA tensors of shape [nrhs, N] (row r = right-hand side r, contiguous), which
+is the library's column-major N x nrhs layout with ld = N.  Nodal arrays
+(permittivity, Dirichlet data, eps-gradient) are [n_y, n_x].
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libpinv.so")
+
+OK, E_INVALID_ARG, E_NOT_SPD, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
+MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8": 4}
+SCALE_ROW = 0
+
+
+class PinvError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("h", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n", ctypes.c_int32), ("h", ctypes.c_double),
+                ("has_fp64", ctypes.c_int32), ("int8_slices", ctypes.c_int32), ("has_fp32", ctypes.c_int32),
+                ("has_bf16", ctypes.c_int32), ("has_lift", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("ld", ctypes.c_int64), ("nrhs", ctypes.c_int32), ("_pad", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp, dp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p
+    P = ctypes.POINTER
+    sig = {
+        "pinv_build_inverse": ([P(Grid), dp, dp, vp, P(vp)], i32),
+        "pinv_import_inverse": ([P(Grid), dp, i64, dp, dp, dp, vp, P(vp)], i32),
+        "pinv_export_inverse": ([vp, dp, i64, dp, vp], i32),
+        "pinv_quantize_inverse": ([vp, i32, i32, i32, vp], i32),
+        "pinv_prepare_split": ([vp, i32, vp], i32),
+        "pinv_export_quantized": ([vp, vp, vp, vp], i32),
+        "pinv_apply_inverse": ([vp, i32, i32, dp, i64, i32, dp, i64, vp], i32),
+        "pinv_apply_inverse_adjoint": ([vp, i32, i32, dp, i64, i32, dp, i64, vp], i32),
+        "pinv_grad_eps": ([vp, dp, i64, dp, i64, i32, dp, vp], i32),
+        "pinv_apply_batched": ([P(Request), i32, i32, i32, vp], i32),
+        "pinv_get_info": ([vp, P(Info)], i32),
+        "pinv_destroy": ([vp], i32),
+        "pinv_status_string": ([i32], ctypes.c_char_p),
+        "pinv_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+EXPORTED = ("pinv_build_inverse", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
+            "pinv_prepare_split", "pinv_export_quantized", "pinv_apply_inverse", "pinv_apply_inverse_adjoint",
+            "pinv_grad_eps", "pinv_apply_batched", "pinv_get_info", "pinv_destroy", "pinv_status_string",
+            "pinv_version")
+
+
+def status_string(st):
+    return lib.pinv_status_string(int(st)).decode()
+
+
+def version():
+    return lib.pinv_version().decode()
+
+
+def _check(st, what):
+    if st != OK:
+        raise PinvError(st, what)
+
+
+def _host_nodal(a, nx, ny):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.shape != (ny, nx):
+        raise ValueError(f"nodal array must have shape ({ny}, {nx}), got {a.shape}")
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _mode(mode):
+    if isinstance(mode, str):
+        return MODES[mode]
+    return int(mode)
+
+
+def _vectors(t, n, name):
+    """[nrhs, N] float64 CUDA tensor with contiguous rows -> (ptr, ld, nrhs)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if t.dim() == 1:
+        t = t.view(1, -1)
+    if t.dim() != 2 or t.shape[1] != n or (n > 1 and t.stride(1) != 1):
+        raise ValueError(f"{name} must have shape [nrhs, {n}] with contiguous rows")
+    ld = t.stride(0) if t.shape[0] > 1 else n
+    return ctypes.c_void_p(t.data_ptr()), ld, t.shape[0]
+
+
+class PoissonInverse:
+    """A precomputed dense inverse of the 5-point operator on one grid."""
+
+    def __init__(self, handle, nx, ny, h):
+        self._h = handle
+        self.nx, self.ny, self.h = nx, ny, h
+        self.n = (nx - 2) * (ny - 2)
+
+    # -- construction ---------------------------------------------------------
+    @classmethod
+    def build(cls, nx, ny, h=None, eps=None, u_boundary=None, stream=None):
+        """Steps 1-2 on the GPU: assemble K from nodal eps and invert it."""
+        if h is None:
+            h = 1.0 / (max(nx, ny) - 1)
+        g = Grid(nx, ny, h)
+        e = _host_nodal(eps, nx, ny)
+        ub = _host_nodal(u_boundary, nx, ny)
+        out = ctypes.c_void_p()
+        _check(lib.pinv_build_inverse(ctypes.byref(g), _ptr(e), _ptr(ub), _stream(stream), ctypes.byref(out)),
+               "pinv_build_inverse")
+        return cls(out, nx, ny, h)
+
+    @classmethod
+    def from_inverse(cls, nx, ny, h, G, eps=None, u_boundary=None, w=None, stream=None):
+        """Create from a host inverse G [N, N] (row-major float64)."""
+        G = np.ascontiguousarray(np.asarray(G, dtype=np.float64))
+        n = (nx - 2) * (ny - 2)
+        if G.shape != (n, n):
+            raise ValueError(f"G must be ({n}, {n})")
+        g = Grid(nx, ny, h)
+        e = _host_nodal(eps, nx, ny)
+        ub = _host_nodal(u_boundary, nx, ny)
+        wv = None if w is None else np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(n))
+        out = ctypes.c_void_p()
+        _check(lib.pinv_import_inverse(ctypes.byref(g), _ptr(G), n, _ptr(e), _ptr(ub), _ptr(wv), _stream(stream),
+                                       ctypes.byref(out)), "pinv_import_inverse")
+        return cls(out, nx, ny, h)
+
+    # -- representations ------------------------------------------------------
+    def quantize(self, bits, keep_fp64=True, stream=None):
+        _check(lib.pinv_quantize_inverse(self._h, int(bits), SCALE_ROW, int(bool(keep_fp64)), _stream(stream)),
+               "pinv_quantize_inverse")
+        return self
+
+    def prepare_split(self, mode, stream=None):
+        _check(lib.pinv_prepare_split(self._h, _mode(mode), _stream(stream)), "pinv_prepare_split")
+        return self
+
+    def export_inverse(self, stream=None):
+        G = np.empty((self.n, self.n), dtype=np.float64)
+        w = np.empty(self.n, dtype=np.float64)
+        _check(lib.pinv_export_inverse(self._h, _ptr(G), self.n, _ptr(w), _stream(stream)), "pinv_export_inverse")
+        return G, w
+
+    def export_quantized(self, stream=None):
+        S = self.info()["int8_slices"]
+        if S == 0:
+            raise PinvError(E_STATE, "export_quantized")
+        Q = np.empty((S, self.n, self.n), dtype=np.int8)
+        e = np.empty(self.n, dtype=np.int32)
+        _check(lib.pinv_export_quantized(self._h, _ptr(Q), _ptr(e), _stream(stream)), "pinv_export_quantized")
+        return Q, e
+
+    # -- the solve and its derivatives ----------------------------------------
+    def apply(self, rho, mode="fp64", rho_bits=16, out=None, stream=None):
+        """u = L^{-1} rho for rho [nrhs, N] (float64, CUDA)."""
+        import torch
+        p_rho, ld_rho, nrhs = _vectors(rho, self.n, "rho")
+        if out is None:
+            out = torch.empty((nrhs, self.n), dtype=torch.float64, device=rho.device)
+        p_u, ld_u, nu = _vectors(out, self.n, "out")
+        if nu != nrhs:
+            raise ValueError("out must have as many rows as rho")
+        _check(lib.pinv_apply_inverse(self._h, _mode(mode), int(rho_bits), p_rho, ld_rho, nrhs, p_u, ld_u,
+                                      _stream(stream)), "pinv_apply_inverse")
+        return out
+
+    def apply_adjoint(self, g, mode="fp64", g_bits=16, out=None, stream=None):
+        """lambda = dLoss/drho = -h^2 G^T g."""
+        import torch
+        p_g, ld_g, nrhs = _vectors(g, self.n, "g")
+        if out is None:
+            out = torch.empty((nrhs, self.n), dtype=torch.float64, device=g.device)
+        p_l, ld_l, nl = _vectors(out, self.n, "out")
+        if nl != nrhs:
+            raise ValueError("out must have as many rows as g")
+        _check(lib.pinv_apply_inverse_adjoint(self._h, _mode(mode), int(g_bits), p_g, ld_g, nrhs, p_l, ld_l,
+                                              _stream(stream)), "pinv_apply_inverse_adjoint")
+        return out
+
+    def grad_eps(self, u, lam, out=None, stream=None):
+        """Nodal dLoss/deps [n_y, n_x] from forward solutions and adjoint outputs."""
+        import torch
+        p_u, ld_u, nu = _vectors(u, self.n, "u")
+        p_l, ld_l, nl = _vectors(lam, self.n, "lambda")
+        if nu != nl:
+            raise ValueError("u and lambda must have the same number of rows")
+        if out is None:
+            out = torch.empty((self.ny, self.nx), dtype=torch.float64, device=u.device)
+        if out.dtype != torch.float64 or not out.is_contiguous() or tuple(out.shape) != (self.ny, self.nx):
+            raise ValueError("out must be a contiguous float64 [ny, nx] tensor")
+        _check(lib.pinv_grad_eps(self._h, p_u, ld_u, p_l, ld_l, nu, ctypes.c_void_p(out.data_ptr()),
+                                 _stream(stream)), "pinv_grad_eps")
+        return out
+
+    def info(self):
+        i = Info()
+        _check(lib.pinv_get_info(self._h, ctypes.byref(i)), "pinv_get_info")
+        return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    def close(self):
+        if self._h:
+            lib.pinv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def apply_batched(requests, mode="int8", rho_bits=16, stream=None):
+    """requests: list of (PoissonInverse, rho [nrhs, N], u [nrhs, N]) with the
+    same row stride for rho and u."""
+    arr = (Request * len(requests))()
+    for i, (op, rho, u) in enumerate(requests):
+        p_r, ld_r, nr = _vectors(rho, op.n, "rho")
+        p_u, ld_u, nu = _vectors(u, op.n, "u")
+        if ld_r != ld_u or nr != nu:
+            raise ValueError("rho and u of a request must share shape and stride")
+        arr[i] = Request(op._h, p_r, p_u, ld_r, nr, 0)
+    _check(lib.pinv_apply_batched(arr, len(requests), _mode(mode), int(rho_bits), _stream(stream)),
+           "pinv_apply_batched")

@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/pinv.h; host-side argument checks that return before any device call.
+No compute call is made here (runs without a GPU)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pinv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pinv_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def pinv():
+    from paper_1602_00001_amd import pinv as p
+    return p
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("pinv_build_inverse", "pinv_quantize_inverse", "pinv_apply_inverse",
+                     "pinv_apply_inverse_adjoint", "pinv_grad_eps"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(pinv):
+    lib = ctypes.CDLL(pinv.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(pinv.EXPORTED) == set(_declared())
+
+
+def test_status_strings(pinv):
+    for st in (0, -1, -2, -3, -4, -5, -6):
+        assert pinv.status_string(st)
+    assert pinv.status_string(-99) == "unknown status"
+    assert re.match(r"\d+\.\d+\.\d+$", pinv.version())
+
+
+def test_host_side_argument_errors(pinv):
+    lib = pinv.lib
+    out = ctypes.c_void_p()
+    bad = pinv.Grid(2, 10, 0.1)
+    assert lib.pinv_build_inverse(ctypes.byref(bad), None, None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
+    assert not out.value
+    neg_h = pinv.Grid(10, 10, -1.0)
+    assert lib.pinv_build_inverse(ctypes.byref(neg_h), None, None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
+    huge = pinv.Grid(5000, 5000, 0.1)
+    assert lib.pinv_build_inverse(ctypes.byref(huge), None, None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
+    ok = pinv.Grid(10, 10, 0.1)
+    assert lib.pinv_build_inverse(ctypes.byref(ok), None, None, None, None) == pinv.E_INVALID_ARG
+    assert lib.pinv_import_inverse(ctypes.byref(ok), None, 64, None, None, None, None,
+                                   ctypes.byref(out)) == pinv.E_INVALID_ARG
+    assert lib.pinv_destroy(None) == pinv.E_INVALID_ARG
+    assert lib.pinv_apply_inverse(None, 0, 16, None, 0, 1, None, 0, None) == pinv.E_INVALID_ARG
+    assert lib.pinv_apply_inverse_adjoint(None, 0, 16, None, 0, 1, None, 0, None) == pinv.E_INVALID_ARG
+    assert lib.pinv_grad_eps(None, None, 0, None, 0, 1, None, None) == pinv.E_INVALID_ARG
+    assert lib.pinv_quantize_inverse(None, 16, 0, 1, None) == pinv.E_INVALID_ARG
+    assert lib.pinv_get_info(None, None) == pinv.E_INVALID_ARG
+    assert lib.pinv_apply_batched(None, 3, 4, 16, None) == pinv.E_INVALID_ARG
+    assert lib.pinv_apply_batched(None, 0, 4, 16, None) == pinv.OK
+
+
+def test_binding_rejects_missing_library(tmp_path, monkeypatch, pinv):
+    """The product path fails loudly when the HIP library is absent."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("pinv_copy", pinv.__file__)
+    mod = importlib.util.module_from_spec(spec)
+    monkeypatch.setattr(os.path, "exists", lambda p: False)
+    with pytest.raises(ImportError):
+        spec.loader.exec_module(mod)

@@ -1,0 +1,101 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times: 128x128 grid (15876 unknowns), 1024 uniform[-1,1] right-hand sides,
+24-bit inverse entries x 16-bit rho.  The oracle's inverse for eps = 1 is the
+closed-form DST one (itself pinned to LU); outputs are compared on a sample of
+right-hand sides the oracle computes in full, bit for bit for the integer
+path."""
+
+import numpy as np
+import pytest
+
+from oracle import apply, inverse, metrics, quant
+from paper_1602_00001_amd import workloads
+from tests.gpu_util import announce, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+N_GRID = 128
+SAMPLE = 16
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def pinv():
+    from paper_1602_00001_amd import pinv as p
+    return p
+
+
+@pytest.fixture(scope="module")
+def case():
+    wl = workloads.quant_128()
+    G = inverse.dst_inverse(N_GRID, N_GRID)
+    return wl, G
+
+
+def test_quant_128_int8_bit_exact_and_accuracy(torch, pinv, case):
+    wl, G = case
+    n, h, rho = wl["n"], wl["h"], wl["rho"]
+    announce(f"full size int8 n={n} nrhs={rho.shape[0]} bits=24 rho_bits=16")
+    R = rho.shape[0]
+    pick = np.random.default_rng(0).choice(R, SAMPLE, replace=False)
+    with pinv.PoissonInverse.from_inverse(n, n, h, G) as op:
+        op.quantize(24)
+        u_int8 = host(op.apply(dev(rho), "int8", 16))
+        u_fp64 = host(op.apply(dev(rho), "fp64"))
+    # integer path: bit-exact on the sampled right-hand sides
+    qG, e = quant.quantize_rows(G, 3)
+    qR, f = quant.quantize_cols(rho[pick].T, 2)
+    ref_int, _ = apply.integer_apply(qG, e, 3, qR, f, 2, h)
+    assert np.array_equal(u_int8[pick].T, ref_int)
+    # FP64 path: within 1e-12 of the oracle's FP64 product
+    ref64 = apply.plain_apply(G, rho[pick].T, h)
+    assert np.max(metrics.rel_l2_per_rhs(u_fp64[pick].T, ref64)) <= 1e-12
+    # accuracy of the quantised solve against FP64 on every right-hand side
+    err = metrics.rel_l2_per_rhs(u_int8.T, u_fp64.T)
+    print(f"[full-size] int8 24x16-bit vs fp64: max rel L2 {err.max():.3e}, median {np.median(err):.3e}", flush=True)
+    assert err.max() <= 1e-4
+
+
+def test_quant_128_build_inverse_matches_dst(torch, pinv, case):
+    wl, G = case
+    n, h = wl["n"], wl["h"]
+    announce(f"full size build_inverse n={n}")
+    with pinv.PoissonInverse.build(n, n, h) as op:
+        Gg, _ = op.export_inverse()
+    rel = np.linalg.norm(Gg - G) / np.linalg.norm(G)
+    print(f"[full-size] build_inverse vs DST closed form: rel Frobenius {rel:.3e}", flush=True)
+    assert rel <= 1e-12
+
+
+def test_plain_32_and_vareps_64(torch, pinv):
+    """The small workloads at their own sizes: 32x32 with one RHS (FP64 GEMV
+    path) and 64x64 variable eps with 256 drifting-blob RHS (FP64 and split
+    modes), against the oracle's LU inverse."""
+    from tests.gpu_util import oracle_inverse
+    from oracle import split
+    wl = workloads.plain_32()
+    announce("plain_32 fp64 nrhs=1")
+    G, _, _ = oracle_inverse(wl["n"], wl["n"])
+    with pinv.PoissonInverse.build(wl["n"], wl["n"], wl["h"]) as op:
+        u = host(op.apply(dev(wl["rho"]), "fp64"))
+    assert np.max(metrics.rel_l2_per_rhs(u.T, apply.plain_apply(G, wl["rho"].T, wl["h"]))) <= 1e-12
+
+    wl = workloads.vareps_64()
+    announce("vareps_64 fp64/fp32/bf16x3/bf16x6 nrhs=256")
+    G, _, _ = oracle_inverse(wl["n"], wl["n"], wl["eps"])
+    ref = apply.plain_apply(G, wl["rho"].T, wl["h"])
+    with pinv.PoissonInverse.build(wl["n"], wl["n"], wl["h"], wl["eps"]) as op:
+        u = host(op.apply(dev(wl["rho"]), "fp64"))
+        assert np.max(metrics.rel_l2_per_rhs(u.T, ref)) <= 1e-12
+        for mode, tol in (("fp32", 2e-6), ("bf16x3", 4e-5), ("bf16x6", 2e-6)):
+            op.prepare_split(mode)
+            um = host(op.apply(dev(wl["rho"]), mode))
+            err = np.max(metrics.rel_l2_per_rhs(um.T, ref))
+            emu = split.split_apply(G, wl["rho"][:8].T, wl["h"], mode)
+            print(f"[vareps_64] {mode}: max rel L2 vs fp64 {err:.3e}", flush=True)
+            assert err <= tol
+            assert np.max(metrics.rel_l2_per_rhs(um[:8].T, emu)) <= 2.0 ** -24 * 64 * 8
