@@ -1,0 +1,219 @@
+"""Benchmark: solves/s of the quantised (int8 digit-slice matrix-core) form
+against the plain FP64 GEMM form of the dense-inverse Poisson solve, on one
+MI355X, at 128x128 grid points (126^2 = 15876 unknowns) with 1024 uniform[-1,1]
+right-hand sides.
+
+One step = one apply of the precomputed inverse to the 1024-RHS batch: the
+int8 form quantises rho to 16-bit fixed point, runs the 6 slice-pair products
+of the 24-bit inverse on the int8 matrix cores and recombines them exactly;
+the FP64 form is one FP64 matrix-core GEMM.  Inputs are resident in HBM when
+the timed region starts; setup (GPU Cholesky inversion, quantisation of G) is
+timed separately and never folded into solves/s.
+
+Prints one JSON line.  `value` is the int8 form's solves/s.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_INT8_TOPS = 5000.0     # MI355X dense int8 matrix peak, TOP/s
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 matrix peak, TFLOP/s
+PEAK_HBM_GBS = 8000.0
+
+
+def _src_hash(rel):
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(summary, kernel_src):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        if d.get("kernel_source_sha256_16") != _src_hash(kernel_src):
+            return None
+        return float(d["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def _cpu_baseline(wl, bits, rho_bits, nsample, u_gpu):
+    """The oracle's integer apply (quantise rho, exact int64 product, scaling)
+    on a sample of the right-hand sides, on the host; also checks the GPU's
+    output on that sample bit for bit."""
+    import numpy as np
+    from oracle import apply, inverse, quant
+    n, h, rho = wl["n"], wl["h"], wl["rho"]
+    G = inverse.dst_inverse(n, n)
+    S, Sr = bits // 8, rho_bits // 8
+    qG, e = quant.quantize_rows(G, S)
+    del G
+    sample = np.ascontiguousarray(rho[:nsample].T)
+    t0 = time.perf_counter()
+    qR, f = quant.quantize_cols(sample, Sr)
+    u, _ = apply.integer_apply(qG, e, S, qR, f, Sr, h)
+    dt = time.perf_counter() - t0
+    exact = bool(np.array_equal(u, u_gpu[:nsample].T))
+    return dict(value=nsample / dt, unit="solves/s", cores=1, kind="oracle",
+                sample=f"{nsample} of {rho.shape[0]} right-hand sides of the same batch; integer apply "
+                       f"(quantise rho to {rho_bits}-bit, exact int64 product with the {bits}-bit inverse, "
+                       f"scaling) in numpy int64 matmul, single-threaded; {dt:.2f} s",
+                seconds=dt), exact
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nrhs", type=int, default=1024)
+    ap.add_argument("--bits", type=int, default=24)
+    ap.add_argument("--rho-bits", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the dense-inverse apply is measured on a single MI355X "
+              "(multi-GPU row-block sharding is a design note, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1602_00001_amd import pinv, workloads
+
+    torch.cuda.set_device(0)
+    wl = workloads.quant_128(args.nrhs)
+    n, h = wl["n"], wl["h"]
+    N = (n - 2) * (n - 2)
+    R = args.nrhs
+    S, Sr = args.bits // 8, args.rho_bits // 8
+
+    t0 = time.perf_counter()
+    op = pinv.PoissonInverse.build(n, n, h)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    op.quantize(args.bits)
+    torch.cuda.synchronize()
+    t_quant = time.perf_counter() - t0
+
+    rho = torch.from_numpy(wl["rho"]).cuda()
+    u8 = torch.empty_like(rho)
+    u64 = torch.empty_like(rho)
+    for _ in range(args.warmup):
+        op.apply(rho, "int8", args.rho_bits, out=u8)
+        op.apply(rho, "fp64", out=u64)
+    torch.cuda.synchronize()
+    for k in ("gemm_i8", "quantize_cols", "gemm_f64"):
+        pinv.trace_read(k)
+
+    # ---- timed: int8 form (the metric) ----
+    pinv.trace_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        op.apply(rho, "int8", args.rho_bits, out=u8)
+    torch.cuda.synchronize()
+    t_int8 = time.perf_counter() - t0
+    # ---- timed: FP64 GEMM form (the comparison) ----
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        op.apply(rho, "fp64", out=u64)
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t0
+    pinv.trace_enable(False)
+    gi8_ms, gi8_n = pinv.trace_read("gemm_i8")
+    qc_ms, qc_n = pinv.trace_read("quantize_cols")
+    gf_ms, gf_n = pinv.trace_read("gemm_f64")
+
+    # accuracy of the quantised form against FP64 on this batch
+    diff = torch.linalg.vector_norm(u8 - u64, dim=1) / torch.linalg.vector_norm(u64, dim=1)
+    rel_l2_max = float(diff.max())
+    rel_l2_med = float(diff.median())
+
+    ms_step = 1e3 * t_int8 / args.steps
+    int8_sps = R * args.steps / t_int8
+    fp64_sps = R * args.steps / t_fp64
+
+    gi8_avg = gi8_ms / max(gi8_n, 1)
+    ops = 2.0 * S * Sr * N * N * R
+    ach_i8 = ops / (gi8_avg * 1e-3) / 1e12
+    gf_avg = gf_ms / max(gf_n, 1)
+    flops = 2.0 * N * N * R
+    ach_f64 = flops / (gf_avg * 1e-3) / 1e12
+
+    line = {
+        "metric": "solves/sec at 126^2 unknowns: int8-slice MFMA vs FP64 GEMM at <=1e-4 rel L2",
+        "value": int8_sps,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"quant_128: 128x128 grid, {N} interior unknowns, eps=1, {R} uniform[-1,1] RHS, "
+                        f"{args.bits}-bit per-row inverse x {args.rho_bits}-bit rho ({S * Sr} int8 slice pairs)",
+            "n_unknowns": N, "nrhs": R, "inverse_bits": args.bits, "rho_bits": args.rho_bits,
+        },
+        "fp64_gemm": {"value": fp64_sps, "unit": "solves/s", "ms_per_step": 1e3 * t_fp64 / args.steps},
+        "int8_over_fp64": int8_sps / fp64_sps,
+        "rel_l2_vs_fp64": {"max": rel_l2_max, "median": rel_l2_med, "bound": 1e-4, "ok": rel_l2_max <= 1e-4},
+        "roofline": {
+            "kernel": f"gemm_i8_kernel<{S},{Sr}>",
+            "bound": "mfma", "achieved": ach_i8, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
+            "frac": ach_i8 / PEAK_INT8_TOPS,
+            "traffic": _traffic("gemm_i8_quant_128.traffic.json", "paper_1602_00001_amd/csrc/gemm_i8.hip"),
+            "algorithmic_ops_per_launch": ops, "avg_launch_ms": gi8_avg, "launches": gi8_n,
+        },
+        "roofline_fp64": {
+            "kernel": "gemm_f64_kernel<1,1>",
+            "bound": "mfma", "achieved": ach_f64, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach_f64 / PEAK_FP64_TFLOPS,
+            "traffic": _traffic("gemm_f64_quant_128.traffic.json", "paper_1602_00001_amd/csrc/gemm_f64.hip"),
+            "algorithmic_flops_per_launch": flops, "avg_launch_ms": gf_avg, "launches": gf_n,
+        },
+        "quantize_rho_avg_ms": qc_ms / max(qc_n, 1),
+        "setup_s": {"build_inverse": t_build, "quantize_inverse": t_quant},
+    }
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = nbytes
+        del src, dst
+    if not args.no_cpu_baseline:
+        u_host = u8.cpu().numpy()
+        cb, exact = _cpu_baseline(wl, args.bits, args.rho_bits, args.cpu_sample, u_host)
+        line["cpu_baseline"] = cb
+        line["bit_exact_vs_oracle_on_cpu_sample"] = exact
+    else:
+        line["cpu_baseline"] = None
+    op.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

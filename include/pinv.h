@@ -196,6 +196,16 @@ int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
 
 int32_t pinv_get_info(pinv_op op, pinv_info* info);
 
+/* Kernel tracing (profiling aid).  While enabled, every kernel launched by the
+ * library is bracketed by a pair of HIP events recorded on the same stream.
+ * pinv_trace_read sums the elapsed times of the recorded launches of one
+ * kernel family -- "gemm_i8", "quantize_cols", "gemm_f64", "gemv_f64",
+ * "gemm_split", "pack_split", "grad_eps" -- waiting for their events, and
+ * forgets them; total_ms and launches may be NULL.  pinv_trace_enable(0)
+ * stops recording (recorded launches stay readable).  Thread-safe. */
+int32_t pinv_trace_enable(int32_t on);
+int32_t pinv_trace_read(const char* kernel, double* total_ms, int64_t* launches);
+
 /* Free the op and all of its device memory (waits for the device first). */
 int32_t pinv_destroy(pinv_op op);
 

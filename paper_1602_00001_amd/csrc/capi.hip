@@ -6,8 +6,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <cmath>
+#include <atomic>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "common.h"
 
@@ -33,6 +35,43 @@ void pinv_log(const char* fmt, ...) {
   std::vfprintf(stderr, fmt, ap);
   std::fprintf(stderr, "\n");
   va_end(ap);
+}
+
+namespace {
+
+struct TraceRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::atomic<int> g_trace_on{0};
+std::mutex g_trace_mu;
+std::vector<TraceRec> g_trace;
+
+}  // namespace
+
+TraceScope::TraceScope(const char* name, hipStream_t s) : name_(name), s_(s) {
+  if (!g_trace_on.load(std::memory_order_relaxed)) return;
+  if (hipEventCreate(&a_) != hipSuccess) return;
+  if (hipEventCreate(&b_) != hipSuccess) {
+    (void)hipEventDestroy(a_);
+    return;
+  }
+  on_ = hipEventRecord(a_, s_) == hipSuccess;
+  if (!on_) {
+    (void)hipEventDestroy(a_);
+    (void)hipEventDestroy(b_);
+  }
+}
+
+TraceScope::~TraceScope() {
+  if (!on_) return;
+  if (hipEventRecord(b_, s_) != hipSuccess) {
+    (void)hipEventDestroy(a_);
+    (void)hipEventDestroy(b_);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  g_trace.push_back({name_, a_, b_});
 }
 
 namespace {
@@ -145,8 +184,13 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
   PINV_HIP_TRY(hipMallocAsync(&scratch, xq_bytes + f_bytes, s));
   int8_t* Xq = (int8_t*)scratch;
   int32_t* f = (int32_t*)((char*)scratch + xq_bytes);
-  hipError_t e = launch_quantize_cols(X, ldx, op->n, nrhs, Rpad, SR, op->P, pre_exp, Xq, f, s);
+  hipError_t e;
+  {
+    TraceScope ts("quantize_cols", s);
+    e = launch_quantize_cols(X, ldx, op->n, nrhs, Rpad, SR, op->P, pre_exp, Xq, f, s);
+  }
   if (e == hipSuccess) {
+    TraceScope ts("gemm_i8", s);
     GemmI8Args a{};
     a.Q = Q; a.S = op->S;
     a.X = Xq; a.SR = SR;
@@ -168,6 +212,7 @@ int32_t fp64_apply(pinv_op op, bool transpose, const double* X, int64_t ldx, int
                    double* U, int64_t ldu, hipStream_t s) {
   const double alpha = -(op->h * op->h);
   if (!transpose && nrhs <= 4) {
+    TraceScope ts("gemv_f64", s);
     PINV_HIP_TRY(launch_gemv_f64(op->G, op->ldg, op->n, X, ldx, nrhs, alpha, bias, U, ldu, s));
     return PINV_OK;
   }
@@ -177,6 +222,7 @@ int32_t fp64_apply(pinv_op op, bool transpose, const double* X, int64_t ldx, int
   a.C = U; a.csm = 1; a.csn = ldu;
   a.M = op->n; a.N = nrhs; a.K = op->n;
   a.alpha = alpha; a.beta = 0.0; a.bias = bias;
+  TraceScope ts("gemm_f64", s);
   PINV_HIP_TRY(launch_gemm_f64(a, s));
   return PINV_OK;
 }
@@ -440,7 +486,11 @@ int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits, const dou
       const size_t sb = split_scratch_bytes(mode, op, nrhs);
       void* scratch = nullptr;
       PINV_HIP_TRY(hipMallocAsync(&scratch, sb ? sb : 256, s));
-      hipError_t e = launch_gemm_split(mode, op, rho, ld_rho, nrhs, -(op->h * op->h), u, ld_u, s, scratch, sb);
+      hipError_t e;
+      {
+        TraceScope ts("gemm_split", s);
+        e = launch_gemm_split(mode, op, rho, ld_rho, nrhs, -(op->h * op->h), u, ld_u, s, scratch, sb);
+      }
       hipError_t e2 = hipFreeAsync(scratch, s);
       if (e != hipSuccess) return pinv_hip_status(e);
       return pinv_hip_status(e2);
@@ -475,6 +525,7 @@ int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u, const double* l
                       int32_t nrhs, double* grad_nodes, void* stream) {
   if (!op || !grad_nodes || nrhs < 0) return PINV_E_INVALID_ARG;
   if (nrhs > 0 && (!u || !lambda || ld_u < op->n || ld_lambda < op->n)) return PINV_E_INVALID_ARG;
+  TraceScope ts("grad_eps", as_stream(stream));
   PINV_HIP_TRY(launch_grad_eps(op->nx, op->ny, op->h, u, ld_u, lambda, ld_lambda, nrhs, op->ub, grad_nodes,
                                as_stream(stream)));
   return PINV_OK;
@@ -503,6 +554,39 @@ int32_t pinv_get_info(pinv_op op, pinv_info* info) {
   info->has_lift = op->w != nullptr;
   info->device_bytes = op->bytes;
   return PINV_OK;
+}
+
+int32_t pinv_trace_enable(int32_t on) {
+  g_trace_on.store(on ? 1 : 0);
+  return PINV_OK;
+}
+
+int32_t pinv_trace_read(const char* kernel, double* total_ms, int64_t* launches) {
+  if (!kernel) return PINV_E_INVALID_ARG;
+  double tot = 0.0;
+  int64_t cnt = 0;
+  int32_t st = PINV_OK;
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  std::vector<TraceRec> keep;
+  keep.reserve(g_trace.size());
+  for (const TraceRec& r : g_trace) {
+    if (std::strcmp(r.name, kernel) != 0) {
+      keep.push_back(r);
+      continue;
+    }
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) st = pinv_hip_status(e);
+    tot += ms;
+    ++cnt;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_trace.swap(keep);
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  return st;
 }
 
 int32_t pinv_destroy(pinv_op op) {

@@ -56,6 +56,22 @@ struct pinv_op_s {
 int32_t pinv_hip_status(hipError_t e);
 void pinv_log(const char* fmt, ...);
 
+// Records a pair of events around the launches in its scope when tracing is
+// enabled (pinv_trace_enable); a no-op otherwise.
+class TraceScope {
+ public:
+  TraceScope(const char* name, hipStream_t s);
+  ~TraceScope();
+  TraceScope(const TraceScope&) = delete;
+  TraceScope& operator=(const TraceScope&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+  bool on_ = false;
+};
+
 // ---- FP64 MFMA GEMM -----------------------------------------------------------
 // C(m,n) = alpha * sum_{k in [kbeg, K)} A(m,k) B(k,n) + beta * C(m,n) + bias[m]
 // A(m,k) = A[m*lda + k] if a_kcontig else A[k*lda + m]

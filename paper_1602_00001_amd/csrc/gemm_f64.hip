@@ -150,6 +150,135 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_kernel(GemmF64Args a, in
   }
 }
 
+// Both operands k-contiguous (A(m,k) = A[m*lda + k], B(k,n) = B[n*ldb + k]):
+// the plain FP64 apply and the Cholesky panel / trailing updates.
+// LDS holds each 128 x 16 operand tile row-major (128 bytes per row) with its
+// eight 16-byte chunks XOR-swizzled by (row >> 1) & 7: the 128-bit stores of a
+// half-wave (two rows) and the 128-bit fragment reads (16 rows, one chunk) both
+// cover all 64 banks exactly once.  The k index of the 16x16x4 instruction is
+// permuted: on MFMA step s (0..3) lane group g = l/16 supplies k = 4g + s, so a
+// lane reads its four k values of a row with two 128-bit reads per tile.
+template <bool VEC>
+__global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_nt_kernel(GemmF64Args a, int tilesM, int tilesN) {
+  __shared__ __attribute__((aligned(16))) double As[2][BM * BKK];
+  __shared__ __attribute__((aligned(16))) double Bs[2][BN * BKK];
+
+  int mt, nt;
+  bool valid;
+  tile_of(blockIdx.x, tilesM, tilesN, mt, nt, valid);
+  if (!valid) return;
+  const int m0 = mt * BM, n0 = nt * BN;
+  if (a.tri == 1 && n0 > m0 + BM - 1) return;
+  const int K = a.K;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // loads: item it covers row (it*256 + tid) >> 3, 16-byte chunk (tid & 7)
+  const int lchunk = tid & 7;
+  double2 ra[4], rb[4];
+  auto load = [&](int k0) {
+    const int gk = k0 + 2 * lchunk;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int row = (it * NTHREADS + tid) >> 3;
+      const int gm = m0 + row, gn = n0 + row;
+      double2 va = {0.0, 0.0}, vb = {0.0, 0.0};
+      if (VEC) {
+        if (gm < a.M && gk + 1 < K) va = *(const double2*)(a.A + (int64_t)gm * a.lda + gk);
+        else if (gm < a.M && gk < K) va.x = a.A[(int64_t)gm * a.lda + gk];
+        if (gn < a.N && gk + 1 < K) vb = *(const double2*)(a.B + (int64_t)gn * a.ldb + gk);
+        else if (gn < a.N && gk < K) vb.x = a.B[(int64_t)gn * a.ldb + gk];
+      } else {
+        if (gm < a.M) {
+          if (gk < K) va.x = a.A[(int64_t)gm * a.lda + gk];
+          if (gk + 1 < K) va.y = a.A[(int64_t)gm * a.lda + gk + 1];
+        }
+        if (gn < a.N) {
+          if (gk < K) vb.x = a.B[(int64_t)gn * a.ldb + gk];
+          if (gk + 1 < K) vb.y = a.B[(int64_t)gn * a.ldb + gk + 1];
+        }
+      }
+      ra[it] = va;
+      rb[it] = vb;
+    }
+  };
+  auto store = [&](int st) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int row = (it * NTHREADS + tid) >> 3;
+      const int pc = lchunk ^ ((row >> 1) & 7);
+      *(double2*)(&As[st][row * BKK + pc * 2]) = ra[it];
+      *(double2*)(&Bs[st][row * BKK + pc * 2]) = rb[it];
+    }
+  };
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  const int fr = lane & 15, g = lane >> 4;
+  int st = 0;
+  if (K > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += BKK) {
+    const bool has_next = k0 + BKK < K;
+    if (has_next) load(k0 + BKK);
+    double fa[4][4], fb[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wm * 64 + i * 16 + fr;
+      const int sw = (row >> 1) & 7;
+      const double2 lo = *(const double2*)(&As[st][row * BKK + ((2 * g) ^ sw) * 2]);
+      const double2 hi = *(const double2*)(&As[st][row * BKK + ((2 * g + 1) ^ sw) * 2]);
+      fa[i][0] = lo.x; fa[i][1] = lo.y; fa[i][2] = hi.x; fa[i][3] = hi.y;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = wn * 64 + j * 16 + fr;
+      const int sw = (row >> 1) & 7;
+      const double2 lo = *(const double2*)(&Bs[st][row * BKK + ((2 * g) ^ sw) * 2]);
+      const double2 hi = *(const double2*)(&Bs[st][row * BKK + ((2 * g + 1) ^ sw) * 2]);
+      fb[j][0] = lo.x; fb[j][1] = lo.y; fb[j][2] = hi.x; fb[j][3] = hi.y;
+    }
+#pragma unroll
+    for (int sk = 0; sk < 4; ++sk)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][sk], fb[j][sk], acc[i][j], 0, 0, 0);
+    if (has_next) store(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * r;
+        if (m < a.M && n < a.N) {
+          double* c = a.C + (int64_t)m * a.csm + (int64_t)n * a.csn;
+          double v = a.alpha * acc[i][j][r];
+          if (a.beta != 0.0) v += a.beta * *c;
+          if (a.bias) v += a.bias[m];
+          *c = v;
+        }
+      }
+    }
+  }
+}
+
 // One wave per row of G; lanes stride over k; up to 8 right-hand sides.
 template <int NR>
 __global__ __launch_bounds__(256) void gemv_f64_kernel(const double* __restrict__ G, int64_t ldg, int n,
@@ -193,7 +322,13 @@ hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t s) {
   const int tilesM = (a.M + BM - 1) / BM, tilesN = (a.N + BN - 1) / BN;
   const int T = tilesM * tilesN;
   const int grid = ((T + 7) / 8) * 8;
-  if (a.a_kcontig && a.b_kcontig)
+  if (a.a_kcontig && a.b_kcontig && !a.kdiag) {
+    const bool vec = (a.lda % 2 == 0) && (a.ldb % 2 == 0) && ((uintptr_t)a.A % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
+    if (vec)
+      hipLaunchKernelGGL((gemm_f64_nt_kernel<true>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);
+    else
+      hipLaunchKernelGGL((gemm_f64_nt_kernel<false>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);
+  } else if (a.a_kcontig && a.b_kcontig)
     hipLaunchKernelGGL((gemm_f64_kernel<true, true>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);
   else if (a.a_kcontig && !a.b_kcontig)
     hipLaunchKernelGGL((gemm_f64_kernel<true, false>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);

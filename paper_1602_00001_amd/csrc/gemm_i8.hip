@@ -7,16 +7,24 @@
 // (v_mfma_i32_16x16x64_i8); the host checks that no class can overflow.  The
 // epilogue recombines the classes exactly in int64 (Horner in base 256),
 // converts once to double, multiplies by c * 2^(e_i + f_r) (c = -h^2/(M_S M_SR))
-// and adds the lift w_i: two roundings, no fused multiply-add (the file is
+// and adds the lift w_i: two roundings, no fused multiply-add (the library is
 // compiled with contraction off).
 //
 // Tiling: 128 (rows of G) x 128 (right-hand sides) per 256-thread workgroup,
-// 4 waves in 2x2, each 64x64 = 4x4 MFMA blocks per class; k step 64 bytes;
-// two LDS stages (one per k step) fed through registers, one barrier per step.
-// LDS rows are 64 data bytes + 16 pad bytes: the 16 lanes of a 128-bit read
-// (16 consecutive rows, same k chunk) then start on 16 distinct 4-bank groups.
-// The digit planes and the quantised right-hand sides are zero-padded to the
-// tile grid, so the main loop has no bounds checks.
+// 4 waves in 2x2, each 64x64 = 4x4 MFMA blocks per class; k step 64 bytes.
+// Operand tiles move global -> LDS with global_load_lds_dwordx4 (no staging
+// registers): one instruction fills 1 KB of LDS (16 rows x 64 bytes) per wave.
+// LDS rows are unpadded; the four 16-byte chunks of row r are stored at chunk
+// position c ^ ((r >> 2) & 3), so the 16 lanes of a 128-bit fragment read
+// (16 consecutive rows, same logical chunk) hit 16 distinct 4-bank groups.  A
+// lane of the DMA loads the global chunk that belongs at its own LDS slot.
+// NST LDS stages (4 when they fit in the 160 KB of a CU, else 3) keep NST-1 k
+// steps of loads in flight.  Each wave waits for its own DMA group (vmcnt),
+// then a plain s_barrier (no fence: a fence would drain all in-flight stages)
+// makes the stage visible to all waves and frees the stage read one step
+// earlier.
+// The digit planes and quantised right-hand sides are zero-padded to the tile
+// grid, so the main loop has no bounds checks.
 //
 // v_mfma_i32_16x16x64_i8 layout (lane l, result register r):
 //   A(i = l%16, k = 16*(l/16) + b), B(k = 16*(l/16) + b, j = l%16),
@@ -24,10 +32,13 @@
 
 #include "common.h"
 
+#define PINV_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 64, ROWB = 80;  // bytes per LDS row (64 + 16 pad)
+constexpr int BM = 128, BN = 128;
 constexpr int NT = 256;
+constexpr int LDS_BYTES = 163840;
 
 __device__ inline void tile_of(int bid, int tilesM, int tilesN, int& mt, int& nt, bool& valid) {
   const int T = tilesM * tilesN;
@@ -38,12 +49,47 @@ __device__ inline void tile_of(int bid, int tilesM, int tilesN, int& mt, int& nt
   nt = valid ? tile % tilesN : 0;
 }
 
+// s_waitcnt with only the vector-memory counter constrained (<= V)
+template <int V>
+__device__ inline void wait_vm() {
+  static_assert(V >= 0 && V < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((V & 15) | (((V >> 4) & 3) << 14) | (7 << 4) | (15 << 8));
+}
+
+__device__ inline void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// BK = k bytes per stage: 128 (full 128-byte cache lines per row) when two
+// stages of all planes fit in LDS, else 64.
+template <int S, int SR>
+struct Cfg {
+  static constexpr int C = S + SR - 1;
+  static constexpr int BK = (2 * (S + SR) * 128 * 128 <= LDS_BYTES) ? 128 : 64;
+  static constexpr int CH = BK / 16;                       // 16-byte chunks per row
+  static constexpr int PLANE = 128 * BK;                   // bytes of one plane per stage
+  static constexpr int STAGE = (S + SR) * PLANE;
+  static constexpr int NST_ = LDS_BYTES / STAGE;
+  static constexpr int NST = NST_ > 4 ? 4 : NST_;
+  static constexpr int RPI = 1024 / BK;                    // rows filled by one DMA instruction
+  static constexpr int IPP = 32 / RPI;                     // DMA instructions per plane per wave
+  static constexpr int L = (S + SR) * IPP;                 // DMA instructions per thread per stage
+  static_assert(NST >= 2, "two LDS stages must fit");
+};
+
+// Swizzle: the 16-byte chunk c of tile row r sits at chunk position
+// c ^ ((r >> 1) & 7) (128-byte rows) or c ^ ((r >> 2) & 3) (64-byte rows), so
+// the 16 lanes of a fragment read (16 consecutive rows, one chunk) hit 16
+// distinct 4-bank groups.
+template <int CH>
+__device__ inline int swz(int row, int c) {
+  return CH == 8 ? (c ^ ((row >> 1) & 7)) : (c ^ ((row >> 2) & 3));
+}
+
 template <int S, int SR>
 __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM, int tilesN) {
-  constexpr int C = S + SR - 1;
-  constexpr int PLANE = BM * ROWB;                // bytes of one digit plane in LDS
-  constexpr int STAGE = (S + SR) * PLANE;
-  __shared__ __attribute__((aligned(16))) int8_t sm[2 * STAGE];
+  using K = Cfg<S, SR>;
+  constexpr int C = K::C, BK = K::BK, CH = K::CH, PLANE = K::PLANE, STAGE = K::STAGE, NST = K::NST;
+  constexpr int RPI = K::RPI, IPP = K::IPP, L = K::L;
+  __shared__ __attribute__((aligned(1024))) int8_t sm[NST * STAGE];
 
   int mt, nt;
   bool valid;
@@ -51,48 +97,53 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
   if (!valid) return;
   const int m0 = mt * BM, n0 = nt * BN;
   const int64_t P = a.P;
+  const int nsteps = (int)(P / BK);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
 
-  // global -> register prefetch: 2 chunks of 16 bytes per plane per thread
-  const int lrow0 = tid >> 2, lch = tid & 3;     // rows lrow0 and lrow0 + 64
-  const int8_t* gq[S];
-  const int8_t* gx[SR];
+  // DMA: instruction j of wave w fills tile rows w*32 + j*RPI .. + RPI-1; lane l
+  // lands at LDS byte l*16 of that block = row l / CH, chunk position l % CH,
+  // so it loads the logical chunk whose swizzled position is l % CH.  The
+  // address is a wave-uniform plane base (scalar registers) plus a 32-bit
+  // per-lane offset (the saddr form of the load).
+  uint32_t off[IPP];
 #pragma unroll
-  for (int s = 0; s < S; ++s) gq[s] = a.Q + (int64_t)s * P * P + (int64_t)(m0 + lrow0) * P + lch * 16;
-#pragma unroll
-  for (int t = 0; t < SR; ++t) gx[t] = a.X + ((int64_t)t * a.Rpad + n0 + lrow0) * P + lch * 16;
-  const int64_t step64 = 64 * P;                  // 64 rows further
+  for (int j = 0; j < IPP; ++j) {
+    const int row = wave * 32 + j * RPI + lane / CH;
+    off[j] = (uint32_t)row * (uint32_t)P + (uint32_t)(swz<CH>(row, lane % CH) * 16);  // swizzle is an involution
+  }
+  const int8_t* tileA = a.Q + (int64_t)m0 * P;
+  const int8_t* tileB = a.X + (int64_t)n0 * P;
+  const int64_t planeA = P * P, planeB = (int64_t)a.Rpad * P;
 
-  v4i pq[S][2], px[SR][2];
-  auto load = [&](int64_t k0) {
+  auto issue = [&](int step) {
+    int8_t* dst = sm + (step % NST) * STAGE + wave * 32 * BK;
+    const int64_t k0 = (int64_t)step * BK;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      pq[s][0] = *(const v4i*)(gq[s] + k0);
-      pq[s][1] = *(const v4i*)(gq[s] + step64 + k0);
+      const int8_t* b = tileA + s * planeA + k0;
+#pragma unroll
+      for (int j = 0; j < IPP; ++j)
+        __builtin_amdgcn_global_load_lds((const void*)(b + off[j]), PINV_LDS(dst + s * PLANE + j * 1024), 16, 0, 0);
     }
 #pragma unroll
     for (int t = 0; t < SR; ++t) {
-      px[t][0] = *(const v4i*)(gx[t] + k0);
-      px[t][1] = *(const v4i*)(gx[t] + step64 + k0);
+      const int8_t* b = tileB + t * planeB + k0;
+#pragma unroll
+      for (int j = 0; j < IPP; ++j)
+        __builtin_amdgcn_global_load_lds((const void*)(b + off[j]), PINV_LDS(dst + (S + t) * PLANE + j * 1024), 16, 0, 0);
     }
   };
-  auto store = [&](int st) {
-    int8_t* base = sm + st * STAGE;
+
+  // fragment read offsets (bytes within a plane) for k half h: rows
+  // (16-row block base) + lane%16, logical chunk 4h + lane/16
+  const int frow = lane & 15;
+  int foff[BK / 64];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      *(v4i*)(base + s * PLANE + lrow0 * ROWB + lch * 16) = pq[s][0];
-      *(v4i*)(base + s * PLANE + (lrow0 + 64) * ROWB + lch * 16) = pq[s][1];
-    }
-#pragma unroll
-    for (int t = 0; t < SR; ++t) {
-      *(v4i*)(base + (S + t) * PLANE + lrow0 * ROWB + lch * 16) = px[t][0];
-      *(v4i*)(base + (S + t) * PLANE + (lrow0 + 64) * ROWB + lch * 16) = px[t][1];
-    }
-  };
+  for (int h = 0; h < BK / 64; ++h) foff[h] = frow * BK + swz<CH>(frow, 4 * h + (lane >> 4)) * 16;
 
   v4i acc[C][4][4];
 #pragma unroll
@@ -102,36 +153,47 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[c][i][j] = v4i{0, 0, 0, 0};
 
-  const int frag_off = (lane & 15) * ROWB + (lane >> 4) * 16;
-  int st = 0;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int64_t k0 = 0; k0 < P; k0 += BK) {
-    const bool has_next = k0 + BK < P;
-    if (has_next) load(k0 + BK);
-    const int8_t* base = sm + st * STAGE;
-    v4i fa[S][4], fb[SR][4];
+  // Every step issues one DMA group; past the last k step the group re-loads
+  // the last step into the stage freed one step earlier (never read again),
+  // so the number of groups in flight after group k is always NST-2.
 #pragma unroll
-    for (int s = 0; s < S; ++s)
+  for (int p = 0; p < NST - 1; ++p) issue(min(p, nsteps - 1));
+
+  for (int k = 0; k < nsteps; ++k) {
+    wait_vm<(NST - 2) * L>();
+    lds_barrier();
+    // (an explicit branch, not min(): it keeps the DMA issue in its own
+    // scheduling region, away from the matrix-core block)
+    if (k + NST - 1 < nsteps)
+      issue(k + NST - 1);
+    else
+      issue(nsteps - 1);
+
+    const int8_t* base = sm + (k % NST) * STAGE;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) fa[s][i] = *(const v4i*)(base + s * PLANE + (wm * 64 + i * 16) * ROWB + frag_off);
-#pragma unroll
-    for (int t = 0; t < SR; ++t)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) fb[t][j] = *(const v4i*)(base + (S + t) * PLANE + (wn * 64 + j * 16) * ROWB + frag_off);
-#pragma unroll
-    for (int s = 0; s < S; ++s)
+    for (int h = 0; h < BK / 64; ++h) {
+      // 16-row blocks start at multiples of 16, where the swizzle of the block
+      // base is zero, so one lane offset serves every block
+      v4i fb[SR][4];
 #pragma unroll
       for (int t = 0; t < SR; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+          fb[t][j] = *(const v4i*)(base + (S + t) * PLANE + (wn * 64 + j * 16) * BK + foff[h]);
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s][i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
-    if (has_next) store(st ^ 1);
-    __syncthreads();
-    st ^= 1;
+      for (int s = 0; s < S; ++s) {
+        v4i fa[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fa[i] = *(const v4i*)(base + s * PLANE + (wm * 64 + i * 16) * BK + foff[h]);
+#pragma unroll
+        for (int t = 0; t < SR; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
+      }
+    }
   }
 
   // exact recombination and the single scaling
@@ -172,7 +234,7 @@ hipError_t launch_t(const GemmI8Args& a, hipStream_t s) {
 
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s) {
   if (a.nrhs <= 0) return hipSuccess;
-  if (a.P % BM != 0 || a.Rpad % BN != 0) return hipErrorInvalidValue;
+  if (a.P % 256 != 0 || a.Rpad % BN != 0) return hipErrorInvalidValue;
   switch (a.S * 4 + a.SR) {
     case 1 * 4 + 1: return launch_t<1, 1>(a, s);
     case 1 * 4 + 2: return launch_t<1, 2>(a, s);

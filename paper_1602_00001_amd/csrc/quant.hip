@@ -115,7 +115,9 @@ __global__ __launch_bounds__(256) void transpose_planes_kernel(const int8_t* __r
 }
 
 // One workgroup per column r of X (column-major n x nrhs, stride ldx); rows of
-// the output [SR][Rpad][P]; columns r >= nrhs are written as zeros.
+// the output [SR][Rpad][P]; columns r >= nrhs are written as zeros.  Each
+// thread handles 4 consecutive k per pass (32-byte reads, 4-byte writes per
+// digit plane), so both the reads and the writes of a wave are contiguous.
 template <int SR>
 __global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __restrict__ X, int64_t ldx, int n,
                                                            int nrhs, int Rpad, int64_t P,
@@ -135,10 +137,10 @@ __global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __rest
   const int fr = frexp_exp(m);
   if (live && threadIdx.x == 0) f[r] = fr;
   const double M = (double)(127LL * ((1LL << (8 * SR)) - 1) / 255);
-  for (int64_t k0 = (int64_t)threadIdx.x * 16; k0 < P; k0 += 256 * 16) {
-    int8_t d[SR][16];
+  for (int64_t k0 = (int64_t)threadIdx.x * 4; k0 < P; k0 += 256 * 4) {
+    int8_t d[SR][4];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
+    for (int t = 0; t < 4; ++t) {
       const int64_t k = k0 + t;
       int q = 0;
       if (live && k < n) {
@@ -152,9 +154,9 @@ __global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __rest
     }
 #pragma unroll
     for (int s = 0; s < SR; ++s) {
-      v4i v;
-      __builtin_memcpy(&v, d[s], 16);
-      *(v4i*)(Xq + ((int64_t)s * Rpad + r) * P + k0) = v;
+      int v;
+      __builtin_memcpy(&v, d[s], 4);
+      *(int*)(Xq + ((int64_t)s * Rpad + r) * P + k0) = v;
     }
   }
 }

@@ -63,6 +63,8 @@ def _load():
         "pinv_apply_batched": ([P(Request), i32, i32, i32, vp], i32),
         "pinv_get_info": ([vp, P(Info)], i32),
         "pinv_destroy": ([vp], i32),
+        "pinv_trace_enable": ([i32], i32),
+        "pinv_trace_read": ([ctypes.c_char_p, P(ctypes.c_double), P(i64)], i32),
         "pinv_status_string": ([i32], ctypes.c_char_p),
         "pinv_version": ([], ctypes.c_char_p),
     }
@@ -78,7 +80,7 @@ lib = _load()
 EXPORTED = ("pinv_build_inverse", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
             "pinv_prepare_split", "pinv_export_quantized", "pinv_apply_inverse", "pinv_apply_inverse_adjoint",
             "pinv_grad_eps", "pinv_apply_batched", "pinv_get_info", "pinv_destroy", "pinv_status_string",
-            "pinv_version")
+            "pinv_version", "pinv_trace_enable", "pinv_trace_read")
 
 
 def status_string(st):
@@ -87,6 +89,19 @@ def status_string(st):
 
 def version():
     return lib.pinv_version().decode()
+
+
+def trace_enable(on=True):
+    """Record HIP events around every kernel the library launches."""
+    _check(lib.pinv_trace_enable(int(bool(on))), "pinv_trace_enable")
+
+
+def trace_read(kernel):
+    """(total milliseconds, launches) of the recorded launches of one kernel family."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(lib.pinv_trace_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "pinv_trace_read")
+    return ms.value, cnt.value
 
 
 def _check(st, what):

@@ -75,7 +75,7 @@ def test_plain_32_and_vareps_64(torch, pinv):
     """The small workloads at their own sizes: 32x32 with one RHS (FP64 GEMV
     path) and 64x64 variable eps with 256 drifting-blob RHS (FP64 and split
     modes), against the oracle's LU inverse."""
-    from tests.gpu_util import oracle_inverse
+    from tests.gpu_util import oracle_inverse, split_tolerances
     from oracle import split
     wl = workloads.plain_32()
     announce("plain_32 fp64 nrhs=1")
@@ -91,11 +91,12 @@ def test_plain_32_and_vareps_64(torch, pinv):
     with pinv.PoissonInverse.build(wl["n"], wl["n"], wl["h"], wl["eps"]) as op:
         u = host(op.apply(dev(wl["rho"]), "fp64"))
         assert np.max(metrics.rel_l2_per_rhs(u.T, ref)) <= 1e-12
-        for mode, tol in (("fp32", 2e-6), ("bf16x3", 4e-5), ("bf16x6", 2e-6)):
+        for mode in ("fp32", "bf16x3", "bf16x6"):
             op.prepare_split(mode)
             um = host(op.apply(dev(wl["rho"]), mode))
-            err = np.max(metrics.rel_l2_per_rhs(um.T, ref))
-            emu = split.split_apply(G, wl["rho"][:8].T, wl["h"], mode)
-            print(f"[vareps_64] {mode}: max rel L2 vs fp64 {err:.3e}", flush=True)
-            assert err <= tol
-            assert np.max(metrics.rel_l2_per_rhs(um[:8].T, emu)) <= 2.0 ** -24 * 64 * 8
+            err = metrics.rel_l2_per_rhs(um.T, ref)
+            tol64, tol_emu = split_tolerances(G, wl["rho"].T, mode)
+            emu = split.split_apply(G, wl["rho"].T, wl["h"], mode)
+            print(f"[vareps_64] {mode}: rel L2 vs fp64 max {err.max():.3e} median {np.median(err):.3e}", flush=True)
+            assert np.all(err <= tol64)
+            assert np.all(metrics.rel_l2_per_rhs(um.T, emu) <= tol_emu)
