@@ -8,6 +8,7 @@
 #include "pinv.h"
 
 typedef int    v4i  __attribute__((ext_vector_type(4)));
+typedef int    v16i __attribute__((ext_vector_type(16)));
 typedef double v4d  __attribute__((ext_vector_type(4)));
 typedef float  v4f  __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));

@@ -10,10 +10,12 @@
 // and adds the lift w_i: two roundings, no fused multiply-add (the library is
 // compiled with contraction off).
 //
-// Tiling: 128 (rows of G) x 128 (right-hand sides) per 256-thread workgroup,
-// 4 waves in 2x2, each 64x64 = 4x4 MFMA blocks per class; k step 64 bytes.
+// Tiling: 128 (rows of G) x 128 (right-hand sides) per 512-thread workgroup,
+// 8 waves in 4x2 (two per SIMD, so one wave's waits are covered by the other's
+// matrix-core work), each 32x64 = 2x4 blocks of v_mfma_i32_16x16x64_i8 per
+// class (128 accumulator registers per wave).
 // Operand tiles move global -> LDS with global_load_lds_dwordx4 (no staging
-// registers): one instruction fills 1 KB of LDS (16 rows x 64 bytes) per wave.
+// registers): one instruction fills 1 KB of LDS (one block of rows) per wave.
 // LDS rows are unpadded; the four 16-byte chunks of row r are stored at chunk
 // position c ^ ((r >> 2) & 3), so the 16 lanes of a 128-bit fragment read
 // (16 consecutive rows, same logical chunk) hit 16 distinct 4-bank groups.  A
@@ -37,7 +39,8 @@
 namespace {
 
 constexpr int BM = 128, BN = 128;
-constexpr int NT = 256;
+constexpr int NW = 8;                 // waves per workgroup (two per SIMD)
+constexpr int NT = NW * 64;
 constexpr int LDS_BYTES = 163840;
 
 __device__ inline void tile_of(int bid, int tilesM, int tilesN, int& mt, int& nt, bool& valid) {
@@ -70,14 +73,16 @@ struct Cfg {
   static constexpr int NST_ = LDS_BYTES / STAGE;
   static constexpr int NST = NST_ > 4 ? 4 : NST_;
   static constexpr int RPI = 1024 / BK;                    // rows filled by one DMA instruction
-  static constexpr int IPP = 32 / RPI;                     // DMA instructions per plane per wave
+  static constexpr int RPW = 128 / NW;                     // rows of a plane filled by one wave
+  static constexpr int IPP = RPW / RPI;                    // DMA instructions per plane per wave
   static constexpr int L = (S + SR) * IPP;                 // DMA instructions per thread per stage
   static_assert(NST >= 2, "two LDS stages must fit");
+  static_assert(IPP >= 1, "a wave fills at least one DMA block per plane");
 };
 
 // Swizzle: the 16-byte chunk c of tile row r sits at chunk position
 // c ^ ((r >> 1) & 7) (128-byte rows) or c ^ ((r >> 2) & 3) (64-byte rows), so
-// the 16 lanes of a fragment read (16 consecutive rows, one chunk) hit 16
+// each 16 lanes of a fragment read (16 consecutive rows, one chunk) hit 16
 // distinct 4-bank groups.
 template <int CH>
 __device__ inline int swz(int row, int c) {
@@ -88,7 +93,7 @@ template <int S, int SR>
 __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM, int tilesN) {
   using K = Cfg<S, SR>;
   constexpr int C = K::C, BK = K::BK, CH = K::CH, PLANE = K::PLANE, STAGE = K::STAGE, NST = K::NST;
-  constexpr int RPI = K::RPI, IPP = K::IPP, L = K::L;
+  constexpr int RPI = K::RPI, RPW = K::RPW, IPP = K::IPP, L = K::L;
   __shared__ __attribute__((aligned(1024))) int8_t sm[NST * STAGE];
 
   int mt, nt;
@@ -102,17 +107,16 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave >> 1, wn = wave & 1;     // 4 x 2 waves, each 32 rows x 64 right-hand sides
 
-  // DMA: instruction j of wave w fills tile rows w*32 + j*RPI .. + RPI-1; lane l
+  // DMA: instruction j of wave w fills plane rows w*RPW + j*RPI .. + RPI-1; lane l
   // lands at LDS byte l*16 of that block = row l / CH, chunk position l % CH,
   // so it loads the logical chunk whose swizzled position is l % CH.  The
-  // address is a wave-uniform plane base (scalar registers) plus a 32-bit
-  // per-lane offset (the saddr form of the load).
+  // address is a wave-uniform plane base plus a 32-bit per-lane offset.
   uint32_t off[IPP];
 #pragma unroll
   for (int j = 0; j < IPP; ++j) {
-    const int row = wave * 32 + j * RPI + lane / CH;
+    const int row = wave * RPW + j * RPI + lane / CH;
     off[j] = (uint32_t)row * (uint32_t)P + (uint32_t)(swz<CH>(row, lane % CH) * 16);  // swizzle is an involution
   }
   const int8_t* tileA = a.Q + (int64_t)m0 * P;
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
   const int64_t planeA = P * P, planeB = (int64_t)a.Rpad * P;
 
   auto issue = [&](int step) {
-    int8_t* dst = sm + (step % NST) * STAGE + wave * 32 * BK;
+    int8_t* dst = sm + (step % NST) * STAGE + wave * RPW * BK;
     const int64_t k0 = (int64_t)step * BK;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -145,11 +149,11 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
 #pragma unroll
   for (int h = 0; h < BK / 64; ++h) foff[h] = frow * BK + swz<CH>(frow, 4 * h + (lane >> 4)) * 16;
 
-  v4i acc[C][4][4];
+  v4i acc[C][2][4];
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[c][i][j] = v4i{0, 0, 0, 0};
 
@@ -182,13 +186,13 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
           fb[t][j] = *(const v4i*)(base + (S + t) * PLANE + (wn * 64 + j * 16) * BK + foff[h]);
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        v4i fa[4];
+        v4i fa[2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) fa[i] = *(const v4i*)(base + s * PLANE + (wm * 64 + i * 16) * BK + foff[h]);
+        for (int i = 0; i < 2; ++i) fa[i] = *(const v4i*)(base + s * PLANE + (wm * 32 + i * 16) * BK + foff[h]);
 #pragma unroll
         for (int t = 0; t < SR; ++t)
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
               acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
@@ -198,7 +202,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
 
   // exact recombination and the single scaling
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 2; ++i) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int n = n0 + wn * 64 + j * 16 + (lane & 15);
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
       const int fn = a.col_exp[n];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
         if (m >= a.n) continue;
         int64_t v = acc[0][i][j][r];
 #pragma unroll
