@@ -180,8 +180,15 @@ int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u,
                       double* grad_nodes, void* stream);
 
 /* Many solves against many ops in one call (batched uneven requests).
- * Requests naming the same op are grouped; each group runs as one product.
- * All ops must hold the mode's representation.  Asynchronous. */
+ * In PINV_INT8 mode the requests naming the same op are grouped and each group
+ * runs as one product over all of its right-hand sides: one rho quantisation
+ * reading the columns through a device pointer table and one slice GEMM whose
+ * epilogue writes every column straight into its request's u (bit-identical
+ * to one pinv_apply_inverse call per request).  Other modes run the requests
+ * one by one.  Every request is checked before anything is launched; requests
+ * must not write into each other's rho or u.  The call waits for work already
+ * queued on the stream once, to upload its column table; the products
+ * themselves are asynchronous. */
 typedef struct {
   pinv_op        op;
   const double*  rho;     /* device, column-major N x nrhs, stride ld        */

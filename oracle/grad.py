@@ -71,6 +71,43 @@ def banded_solve(nx, ny, h, eps_nodes, rho, ub_nodes=None):
     return sla.solveh_banded(ab, rhs, lower=True)
 
 
+def apply_operator_extended(nx, ny, eps_nodes, u_int):
+    """K u for interior values u (columns), accumulated in numpy longdouble
+    (80-bit extended on x86): K's entries are formed in float64 exactly as in
+    :func:`grid.conservative_operator`, then every product and sum is carried in
+    extended precision."""
+    my, mx = ny - 2, nx - 2
+    eps = np.asarray(eps_nodes, dtype=np.float64)
+    ex = (0.5 * (eps[:, :-1] + eps[:, 1:])).astype(np.longdouble)     # face (i, j)-(i, j+1)
+    ey = (0.5 * (eps[:-1, :] + eps[1:, :])).astype(np.longdouble)     # face (i, j)-(i+1, j)
+    u = np.asarray(u_int).astype(np.longdouble).reshape(my, mx, -1)
+    U = np.zeros((ny, nx, u.shape[2]), dtype=np.longdouble)
+    U[1:-1, 1:-1] = u
+    c = U[1:-1, 1:-1]
+    out = (ex[1:-1, :-1, None] * (c - U[1:-1, :-2]) + ex[1:-1, 1:, None] * (c - U[1:-1, 2:])
+           + ey[:-1, 1:-1, None] * (c - U[:-2, 1:-1]) + ey[1:, 1:-1, None] * (c - U[2:, 1:-1]))
+    return out.reshape(my * mx, -1)
+
+
+def banded_solve_refined(nx, ny, h, eps_nodes, rho, ub_nodes=None):
+    """:func:`banded_solve` followed by one step of iterative refinement whose
+    residual b - K u is accumulated in extended precision.  The float64 solve
+    alone is accurate to about cond(K) * eps_mach; the refined solution to about
+    eps_mach, which is what a finite-difference quotient with a small step needs."""
+    rho = np.asarray(rho, dtype=np.float64)
+    vec = rho.ndim == 1
+    R = rho.reshape(rho.shape[0], -1)
+    rhs = (-(h * h)) * R.astype(np.longdouble)
+    if ub_nodes is not None:
+        rhs = rhs + _grid.boundary_term(nx, ny, eps_nodes, ub_nodes).astype(np.longdouble)[:, None]
+    ab = _grid.conservative_operator_banded(nx, ny, eps_nodes)
+    u0 = sla.solveh_banded(ab, rhs.astype(np.float64), lower=True)
+    r = rhs - apply_operator_extended(nx, ny, eps_nodes, u0)
+    du = sla.solveh_banded(ab, r.astype(np.float64), lower=True)
+    u = (u0.astype(np.longdouble) + du).astype(np.float64)
+    return u[:, 0] if vec else u
+
+
 def sampling_loss(nx, ny, h, eps_nodes, rho, sample_idx, d, ub_nodes=None):
     """Source-reconstruction loss sum_r ||C u_r - d_r||^2 with C selecting the
     interior unknowns ``sample_idx``; u from a fresh float64 banded solve."""
@@ -89,3 +126,26 @@ def sampling_loss_grad_u(u, sample_idx, d):
 def central_difference(fun, x, v, delta):
     """[fun(x + delta v) - fun(x - delta v)] / (2 delta)."""
     return (fun(x + delta * v) - fun(x - delta * v)) / (2.0 * delta)
+
+
+def sampling_loss_central_difference(nx, ny, h, eps_nodes, rho, sample, d, v_eps=None, v_rho=None,
+                                     delta=1e-6, ub_nodes=None):
+    """Central difference of :func:`sampling_loss` along (v_eps, v_rho) with step
+    delta, each side re-solved from scratch in float64.
+
+    Same quantity as [L(+) - L(-)] / (2 delta), evaluated as
+    sum (r+ - r-)(r+ + r-) / (2 delta) with r = C u - d: the difference of the two
+    squared-residual sums is formed term by term instead of subtracting two
+    large sums, which removes the cancellation that otherwise limits the
+    difference quotient to about eps_mach * L / delta.  Each side is solved with
+    :func:`banded_solve_refined`, so the solver's own error (about
+    cond(K) * eps_mach) does not enter the quotient either.
+    """
+    e_p = eps_nodes if v_eps is None else eps_nodes + delta * v_eps
+    e_m = eps_nodes if v_eps is None else eps_nodes - delta * v_eps
+    r_p_src = rho if v_rho is None else rho + delta * v_rho
+    r_m_src = rho if v_rho is None else rho - delta * v_rho
+    idx = np.asarray(sample)
+    rp = banded_solve_refined(nx, ny, h, e_p, r_p_src, ub_nodes)[idx] - d
+    rm = banded_solve_refined(nx, ny, h, e_m, r_m_src, ub_nodes)[idx] - d
+    return float(np.sum((rp - rm) * (rp + rm))) / (2.0 * delta)

@@ -9,6 +9,7 @@
 #include <atomic>
 #include <mutex>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -187,7 +188,7 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
   hipError_t e;
   {
     TraceScope ts("quantize_cols", s);
-    e = launch_quantize_cols(X, ldx, op->n, nrhs, Rpad, SR, op->P, pre_exp, Xq, f, s);
+    e = launch_quantize_cols(X, ldx, nullptr, op->n, nrhs, Rpad, SR, op->P, pre_exp, Xq, f, s);
   }
   if (e == hipSuccess) {
     TraceScope ts("gemm_i8", s);
@@ -533,12 +534,95 @@ int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u, const double* l
 
 int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode, int32_t rho_bits, void* stream) {
   if (nreq < 0 || (nreq > 0 && !reqs)) return PINV_E_INVALID_ARG;
+  // every request is checked before anything is launched
   for (int i = 0; i < nreq; ++i) {
-    int32_t st = pinv_apply_inverse(reqs[i].op, mode, rho_bits, reqs[i].rho, reqs[i].ld, reqs[i].nrhs, reqs[i].u,
-                                    reqs[i].ld, stream);
+    const pinv_request& r = reqs[i];
+    if (!r.op) return PINV_E_INVALID_ARG;
+    const int32_t st = check_vectors(r.op, r.rho, r.ld, r.nrhs, r.u, r.ld);
     if (st != PINV_OK) return st;
   }
-  return PINV_OK;
+  if (mode != PINV_INT8) {
+    for (int i = 0; i < nreq; ++i) {
+      const int32_t st = pinv_apply_inverse(reqs[i].op, mode, rho_bits, reqs[i].rho, reqs[i].ld, reqs[i].nrhs,
+                                            reqs[i].u, reqs[i].ld, stream);
+      if (st != PINV_OK) return st;
+    }
+    return PINV_OK;
+  }
+  const int SR = slices_of_bits(rho_bits);
+  if (!SR) return PINV_E_INVALID_ARG;
+  // group the requests by operator, in order of first appearance
+  std::vector<pinv_op> ops;
+  std::unordered_map<pinv_op, std::vector<int>> members;
+  for (int i = 0; i < nreq; ++i) {
+    if (reqs[i].nrhs == 0) continue;
+    pinv_op op = reqs[i].op;
+    if (!op->S) return PINV_E_STATE;
+    if (!int8_headroom_ok(op->n, op->S, SR)) return PINV_E_UNSUPPORTED;
+    auto it = members.find(op);
+    if (it == members.end()) {
+      ops.push_back(op);
+      members[op] = {i};
+    } else {
+      it->second.push_back(i);
+    }
+  }
+  if (ops.empty()) return PINV_OK;
+  // column tables of all groups: input column pointers then output column pointers
+  std::vector<int64_t> first(ops.size()), count(ops.size());
+  std::vector<const void*> table;
+  for (size_t g = 0; g < ops.size(); ++g) {
+    first[g] = (int64_t)table.size();
+    for (int i : members[ops[g]])
+      for (int j = 0; j < reqs[i].nrhs; ++j) table.push_back(reqs[i].rho + (int64_t)j * reqs[i].ld);
+    count[g] = (int64_t)table.size() - first[g];
+    for (int i : members[ops[g]])
+      for (int j = 0; j < reqs[i].nrhs; ++j) table.push_back(reqs[i].u + (int64_t)j * reqs[i].ld);
+  }
+  hipStream_t s = as_stream(stream);
+  configure_pool_once();
+  void* dtable = nullptr;
+  PINV_HIP_TRY(hipMallocAsync(&dtable, table.size() * sizeof(void*), s));
+  hipError_t e = hipMemcpyAsync(dtable, table.data(), table.size() * sizeof(void*), hipMemcpyHostToDevice, s);
+  // the host table must outlive the copy
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (size_t g = 0; g < ops.size() && e == hipSuccess; ++g) {
+    pinv_op op = ops[g];
+    const int R = (int)count[g];
+    const int Rpad = (R + 127) / 128 * 128;
+    const size_t xq_bytes = (size_t)SR * Rpad * op->P;
+    void* scratch = nullptr;
+    e = hipMallocAsync(&scratch, xq_bytes + (size_t)Rpad * sizeof(int32_t), s);
+    if (e != hipSuccess) break;
+    int8_t* Xq = (int8_t*)scratch;
+    int32_t* f = (int32_t*)((char*)scratch + xq_bytes);
+    const void* const* dt = (const void* const*)dtable;
+    {
+      TraceScope ts("quantize_cols", s);
+      e = launch_quantize_cols(nullptr, 0, (const double* const*)(dt + first[g]), op->n, R, Rpad, SR, op->P, nullptr,
+                               Xq, f, s);
+    }
+    if (e == hipSuccess) {
+      TraceScope ts("gemm_i8", s);
+      GemmI8Args a{};
+      a.Q = op->Q; a.S = op->S;
+      a.X = Xq; a.SR = SR;
+      a.P = op->P; a.Rpad = Rpad;
+      a.n = op->n; a.nrhs = R;
+      a.row_exp = op->e;
+      a.col_exp = f;
+      a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
+      a.w = op->w;
+      a.U = nullptr; a.ldu = 0;
+      a.ucols = (double* const*)(dt + first[g] + count[g]);
+      e = launch_gemm_i8(a, s);
+    }
+    const hipError_t e2 = hipFreeAsync(scratch, s);
+    if (e == hipSuccess) e = e2;
+  }
+  const hipError_t e3 = hipFreeAsync(dtable, s);
+  if (e != hipSuccess) return pinv_hip_status(e);
+  return pinv_hip_status(e3);
 }
 
 int32_t pinv_get_info(pinv_op op, pinv_info* info) {

@@ -110,9 +110,10 @@ hipError_t launch_quantize_rows(const double* G, int64_t ldg, int n, int S, int6
                                 int8_t* Q, int32_t* e, hipStream_t s);
 hipError_t launch_transpose_planes(const int8_t* Q, int8_t* QT, int S, int64_t P, hipStream_t s);
 // digits of X (column-major n x nrhs, stride ldx) per column into [SR][Rpad][P];
-// pre_exp (may be null) multiplies row k by 2^pre_exp[k] first.
-hipError_t launch_quantize_cols(const double* X, int64_t ldx, int n, int nrhs, int Rpad, int SR,
-                                int64_t P, const int32_t* pre_exp, int8_t* Xq, int32_t* f,
+// pre_exp (may be null) multiplies row k by 2^pre_exp[k] first.  If xcols is
+// not null, column r is read from xcols[r] instead (X, ldx ignored).
+hipError_t launch_quantize_cols(const double* X, int64_t ldx, const double* const* xcols, int n, int nrhs,
+                                int Rpad, int SR, int64_t P, const int32_t* pre_exp, int8_t* Xq, int32_t* f,
                                 hipStream_t s);
 
 // ---- int8 digit-slice GEMM ------------------------------------------------------
@@ -126,6 +127,7 @@ struct GemmI8Args {
   double c;                        // -h^2 / (M_S M_SR)
   const double* w;                 // [n] or null
   double* U; int64_t ldu;
+  double* const* ucols;            // if not null, column r of the output is ucols[r]
 };
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s);
 

@@ -208,6 +208,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
       const int n = n0 + wn * 64 + j * 16 + (lane & 15);
       if (n >= a.nrhs) continue;
       const int fn = a.col_exp[n];
+      double* ucol = a.ucols ? a.ucols[n] : a.U + (int64_t)n * a.ldu;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
         const double scale = ldexp(a.c, em + fn);
         double u = (double)v * scale;
         if (a.w) u = u + a.w[m];
-        a.U[(int64_t)n * a.ldu + m] = u;
+        ucol[m] = u;
       }
     }
   }

@@ -119,14 +119,15 @@ __global__ __launch_bounds__(256) void transpose_planes_kernel(const int8_t* __r
 // thread handles 4 consecutive k per pass (32-byte reads, 4-byte writes per
 // digit plane), so both the reads and the writes of a wave are contiguous.
 template <int SR>
-__global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __restrict__ X, int64_t ldx, int n,
+__global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __restrict__ X, int64_t ldx,
+                                                           const double* const* __restrict__ xcols, int n,
                                                            int nrhs, int Rpad, int64_t P,
                                                            const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
                                                            int32_t* __restrict__ f) {
   __shared__ double red[4];
   const int r = blockIdx.x;
   const bool live = r < nrhs;
-  const double* x = X + (int64_t)r * ldx;
+  const double* x = live ? (xcols ? xcols[r] : X + (int64_t)r * ldx) : X;
   double m = 0.0;
   if (live)
     for (int k = threadIdx.x; k < n; k += 256) {
@@ -187,13 +188,13 @@ hipError_t launch_transpose_planes(const int8_t* Q, int8_t* QT, int S, int64_t P
   return hipGetLastError();
 }
 
-hipError_t launch_quantize_cols(const double* X, int64_t ldx, int n, int nrhs, int Rpad, int SR, int64_t P,
-                                const int32_t* pre_exp, int8_t* Xq, int32_t* f, hipStream_t s) {
+hipError_t launch_quantize_cols(const double* X, int64_t ldx, const double* const* xcols, int n, int nrhs, int Rpad,
+                                int SR, int64_t P, const int32_t* pre_exp, int8_t* Xq, int32_t* f, hipStream_t s) {
   const dim3 grid((unsigned)Rpad);
   switch (SR) {
-    case 1: hipLaunchKernelGGL(quantize_cols_kernel<1>, grid, dim3(256), 0, s, X, ldx, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
-    case 2: hipLaunchKernelGGL(quantize_cols_kernel<2>, grid, dim3(256), 0, s, X, ldx, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
-    case 3: hipLaunchKernelGGL(quantize_cols_kernel<3>, grid, dim3(256), 0, s, X, ldx, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
+    case 1: hipLaunchKernelGGL(quantize_cols_kernel<1>, grid, dim3(256), 0, s, X, ldx, xcols, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
+    case 2: hipLaunchKernelGGL(quantize_cols_kernel<2>, grid, dim3(256), 0, s, X, ldx, xcols, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
+    case 3: hipLaunchKernelGGL(quantize_cols_kernel<3>, grid, dim3(256), 0, s, X, ldx, xcols, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -142,6 +142,8 @@ def _vectors(t, n, name):
         raise TypeError(f"{name} must be a float64 CUDA tensor")
     if t.dim() == 1:
         t = t.view(1, -1)
+    if t.dim() == 2 and t.shape[1] == n and t.shape[0] == 0:
+        return ctypes.c_void_p(t.data_ptr()), n, 0     # empty block: torch reports zero strides
     if t.dim() != 2 or t.shape[1] != n or (n > 1 and t.stride(1) != 1):
         raise ValueError(f"{name} must have shape [nrhs, {n}] with contiguous rows")
     ld = t.stride(0) if t.shape[0] > 1 else n

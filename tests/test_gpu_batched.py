@@ -1,0 +1,104 @@
+"""Batched uneven requests: pinv_apply_batched equals one pinv_apply_inverse per
+request, bit for bit in INT8 mode (the grouping only changes which columns share
+a launch; every column's quantisation and integer product are independent),
+and the per-request results match the oracle."""
+
+import numpy as np
+import pytest
+
+from oracle import apply, quant
+from paper_1602_00001_amd import workloads
+from tests.gpu_util import announce, dev, host, oracle_inverse, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def pinv():
+    from paper_1602_00001_amd import pinv as p
+    return p
+
+
+GRIDS = [(12, 9), (20, 20), (33, 17), (40, 40)]
+
+
+@pytest.fixture(scope="module")
+def ops(torch, pinv):
+    g = np.random.default_rng(40)
+    out = []
+    for (nx, ny) in GRIDS:
+        eps = workloads.random_eps(nx, ny, g)
+        ub = g.standard_normal((ny, nx)) if nx == 20 else None
+        h = 1.0 / (max(nx, ny) - 1)
+        G, w, _ = oracle_inverse(nx, ny, eps, ub)
+        op = pinv.PoissonInverse.from_inverse(nx, ny, h, G, eps, ub, w)
+        op.quantize(16)
+        out.append(dict(op=op, G=G, w=w, h=h))
+    yield out
+    for o in out:
+        o["op"].close()
+
+
+def _requests(torch, ops, seed, nreq=40):
+    g = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(nreq):
+        k = int(g.integers(0, len(ops)))
+        n = ops[k]["op"].n
+        nrhs = int(g.integers(0, 71))
+        pad = int(g.integers(0, 5))
+        rho_h = g.uniform(-1, 1, (nrhs, n + pad))
+        rho = dev(rho_h)[:, :n]
+        u = torch.full((nrhs, n + pad), float("nan"), dtype=torch.float64, device="cuda")[:, :n]
+        reqs.append((k, rho, u, rho_h[:, :n]))
+    return reqs
+
+
+@pytest.mark.parametrize("rho_bits", [8, 16, 24])
+def test_batched_int8_equals_per_request(torch, pinv, ops, rho_bits):
+    announce(f"apply_batched int8 rho_bits={rho_bits} 40 requests over {len(GRIDS)} ops")
+    reqs = _requests(torch, ops, 100 + rho_bits)
+    pinv.apply_batched([(ops[k]["op"], rho, u) for (k, rho, u, _) in reqs], "int8", rho_bits)
+    for (k, rho, u, rho_h) in reqs:
+        if rho.shape[0] == 0:
+            continue
+        single = host(ops[k]["op"].apply(rho, "int8", rho_bits))
+        assert np.array_equal(host(u), single)
+    # and one request per operator against the oracle
+    for k, o in enumerate(ops):
+        mine = [r for r in reqs if r[0] == k and r[1].shape[0] > 0]
+        if not mine:
+            continue
+        _, _, u, rho_h = mine[0]
+        qG, e = quant.quantize_rows(o["G"], 2)
+        qR, f = quant.quantize_cols(rho_h.T, rho_bits // 8)
+        ref, _ = apply.integer_apply(qG, e, 2, qR, f, rho_bits // 8, o["h"], o["w"])
+        assert np.array_equal(host(u).T, ref)
+
+
+def test_batched_fp64_equals_per_request(torch, pinv, ops):
+    announce("apply_batched fp64 40 requests")
+    reqs = _requests(torch, ops, 7)
+    pinv.apply_batched([(ops[k]["op"], rho, u) for (k, rho, u, _) in reqs], "fp64")
+    for (k, rho, u, rho_h) in reqs:
+        if rho.shape[0] == 0:
+            continue
+        assert np.array_equal(host(u), host(ops[k]["op"].apply(rho, "fp64")))
+
+
+def test_batched_rejects_unquantised_op(torch, pinv):
+    announce("apply_batched with an unquantised op -> E_STATE, nothing launched")
+    nx = ny = 10
+    G, _, _ = oracle_inverse(nx, ny)
+    with pinv.PoissonInverse.from_inverse(nx, ny, 0.1, G) as op:
+        rho = dev(np.ones((2, op.n)))
+        u = torch.zeros_like(rho)
+        with pytest.raises(pinv.PinvError) as ei:
+            pinv.apply_batched([(op, rho, u)], "int8", 16)
+        assert ei.value.status == pinv.E_STATE
+        assert float(u.abs().sum()) == 0.0

@@ -83,3 +83,52 @@ def test_grad_eps_faces_between_boundary_nodes_do_not_count():
     ge = grad.grad_eps_nodes(nx, ny, h, u, lam, g.standard_normal((ny, nx)))
     for (i, j) in ((0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1)):
         assert ge[i, j] == 0.0
+
+
+def test_cancellation_free_central_difference_matches_plain_form():
+    """The term-by-term central difference equals [L(+) - L(-)]/(2 delta) (the
+    same number up to the rounding of the plain form) along eps and rho."""
+    g = np.random.default_rng(13)
+    nx, ny = 11, 9
+    h = 1.0 / (nx - 1)
+    N = (nx - 2) * (ny - 2)
+    eps = 1.0 + g.uniform(0, 1, (ny, nx))
+    rho = g.standard_normal((N, 2))
+    sample = np.sort(g.choice(N, 12, replace=False))
+    d = 0.01 * g.standard_normal((12, 2))
+    v = g.standard_normal((ny, nx))
+    a = grad.sampling_loss_central_difference(nx, ny, h, eps, rho, sample, d, v_eps=v, delta=1e-4)
+    b = grad.central_difference(lambda e: grad.sampling_loss(nx, ny, h, e, rho, sample, d), eps, v, 1e-4)
+    assert abs(a - b) <= 1e-9 * abs(b)
+    w = g.standard_normal(rho.shape)
+    a = grad.sampling_loss_central_difference(nx, ny, h, eps, rho, sample, d, v_rho=w, delta=1e-4)
+    b = grad.central_difference(lambda r: grad.sampling_loss(nx, ny, h, eps, r, sample, d), rho, w, 1e-4)
+    assert abs(a - b) <= 1e-9 * abs(b)
+
+
+def test_extended_operator_matches_dense_K():
+    g = np.random.default_rng(14)
+    nx, ny = 10, 8
+    eps = workloads.random_eps(nx, ny, g)
+    K, _ = grid.conservative_operator(nx, ny, eps)
+    u = g.standard_normal((K.shape[0], 3))
+    assert np.allclose(grad.apply_operator_extended(nx, ny, eps, u).astype(np.float64), K @ u, rtol=0, atol=1e-13)
+
+
+def test_refined_banded_solve_is_more_accurate():
+    """Against an exact rational-free reference: the dense solve refined with the
+    same extended residual, and the residual norms before and after."""
+    g = np.random.default_rng(15)
+    nx, ny = 41, 37
+    h = 1.0 / (nx - 1)
+    eps = 1.0 + 0.5 * g.uniform(0, 1, (ny, nx))
+    ub = g.standard_normal((ny, nx))
+    rho = g.standard_normal(((nx - 2) * (ny - 2), 2))
+    K, bB = grid.conservative_operator(nx, ny, eps, ub)
+    u_plain = grad.banded_solve(nx, ny, h, eps, rho, ub)
+    u_ref = grad.banded_solve_refined(nx, ny, h, eps, rho, ub)
+    rhs = (-(h * h)) * rho.astype(np.longdouble) + bB.astype(np.longdouble)[:, None]
+    res_plain = np.abs(rhs - grad.apply_operator_extended(nx, ny, eps, u_plain)).max()
+    res_ref = np.abs(rhs - grad.apply_operator_extended(nx, ny, eps, u_ref)).max()
+    assert res_ref <= res_plain
+    assert np.max(np.abs(u_ref - u_plain)) <= 1e-12 * np.max(np.abs(u_plain))
