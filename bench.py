@@ -86,6 +86,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM byte counters)")
+    ap.add_argument("--workload", default="quant_128",
+                    choices=["quant_128", "plain_32", "vareps_64", "grad_192", "batched"],
+                    help="quant_128 is the headline metric; the others measure the remaining paths")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the dense-inverse apply is measured on a single MI355X "
@@ -97,6 +100,9 @@ def main():
     from paper_1602_00001_amd import pinv, workloads
 
     torch.cuda.set_device(0)
+    if args.workload != "quant_128":
+        print(json.dumps(OTHER[args.workload](args)), flush=True)
+        return
     wl = workloads.quant_128(args.nrhs)
     n, h = wl["n"], wl["h"]
     N = (n - 2) * (n - 2)
@@ -213,6 +219,206 @@ def main():
         line["cpu_baseline"] = None
     op.close()
     print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# the other paths (one JSON line each; not the headline metric)
+
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _base(metric, value, unit, args, ms, dtype, config):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def bench_plain_32(args):
+    """One right-hand side on a 32x32 grid: latency of the FP64 GEMV apply."""
+    import torch
+    from paper_1602_00001_amd import pinv, workloads
+    wl = workloads.plain_32()
+    n, h = wl["n"], wl["h"]
+    N = (n - 2) ** 2
+    op = pinv.PoissonInverse.build(n, n, h)
+    rho = torch.from_numpy(wl["rho"]).cuda()
+    u = torch.empty_like(rho)
+    pinv.trace_read("gemv_f64")
+    pinv.trace_enable(True)
+    dt = _timed(lambda: op.apply(rho, "fp64", out=u), args.steps, args.warmup)
+    pinv.trace_enable(False)
+    ms, cnt = pinv.trace_read("gemv_f64")
+    kms = ms / max(cnt, 1)
+    gbs = 8.0 * N * N / (kms * 1e-3) / 1e9
+    op.close()
+    line = _base("solves/sec, 30x30 interior unknowns, one right-hand side, FP64 apply", 1.0 / dt, "solves/s", args,
+                 dt * 1e3, "f64", {"workload": "plain_32: 32x32 grid, 900 unknowns, eps=1, 1 blob RHS"})
+    line["us_per_solve"] = dt * 1e6
+    line["roofline"] = {"kernel": "gemv_f64_kernel<1>", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None, "avg_launch_us": kms * 1e3,
+                        "note": "the 6.5 MB inverse is cache-resident across steps; launch latency dominates"}
+    return line
+
+
+def bench_vareps_64(args):
+    """64x64 grid, variable eps, 256 drifting-blob time steps: FP64 against the
+    FP32 and BF16 split forms."""
+    import torch
+    from paper_1602_00001_amd import pinv, workloads
+    wl = workloads.vareps_64()
+    n, h = wl["n"], wl["h"]
+    N = (n - 2) ** 2
+    R = wl["rho"].shape[0]
+    op = pinv.PoissonInverse.build(n, n, h, wl["eps"])
+    rho = torch.from_numpy(wl["rho"]).cuda()
+    ref = op.apply(rho, "fp64")
+    modes = {}
+    for mode, kern, prods, peak, unit in (("fp64", "gemm_f64", 1, PEAK_FP64_TFLOPS, "TFLOP/s"),
+                                          ("fp32", "gemm_split", 1, PEAK_FP32_TFLOPS, "TFLOP/s"),
+                                          ("bf16x3", "gemm_split", 3, PEAK_BF16_TFLOPS, "TFLOP/s"),
+                                          ("bf16x6", "gemm_split", 6, PEAK_BF16_TFLOPS, "TFLOP/s")):
+        if mode != "fp64":
+            op.prepare_split(mode)
+        u = torch.empty_like(rho)
+        pinv.trace_read(kern)
+        pinv.trace_enable(True)
+        dt = _timed(lambda: op.apply(rho, mode, out=u), args.steps, args.warmup)
+        pinv.trace_enable(False)
+        ms, cnt = pinv.trace_read(kern)
+        kms = ms / max(cnt, 1)
+        ach = 2.0 * prods * N * N * R / (kms * 1e-3) / 1e12
+        err = torch.linalg.vector_norm(u - ref, dim=1) / torch.linalg.vector_norm(ref, dim=1)
+        modes[mode] = {"solves_per_s": R / dt, "ms_per_step": dt * 1e3, "kernel_ms": kms,
+                       "rel_l2_vs_fp64_max": float(err.max()), "rel_l2_vs_fp64_median": float(err.median()),
+                       "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak}}
+    op.close()
+    best = max(modes, key=lambda m: modes[m]["solves_per_s"])
+    line = _base("solves/sec at 62^2 unknowns, variable eps: FP64 vs FP32 / BF16x3 / BF16x6 split precision",
+                 modes["bf16x3"]["solves_per_s"], "solves/s", args, modes["bf16x3"]["ms_per_step"], "bf16",
+                 {"workload": f"vareps_64: 64x64 grid, {N} unknowns, eps=1+0.5 sin(2 pi x) cos(2 pi y), {R} drifting-blob RHS"})
+    line["modes"] = modes
+    line["fastest_mode"] = best
+    line["roofline"] = dict(modes["bf16x3"]["roofline"], kernel="gemm_bf16_kernel<2>", traffic=None)
+    line["note"] = "the 118 MB FP64 inverse (30 MB per bf16 part) fits the 256 MB Infinity Cache: warm-cache rates"
+    return line
+
+
+def bench_grad_192(args):
+    """192x192 grid: forward (16-bit quantised) + adjoint + eps-gradient of the
+    sampled-point loss, 256 right-hand sides per step."""
+    import torch
+    from paper_1602_00001_amd import pinv, workloads
+    wl = workloads.grad_192()
+    n, h = wl["n"], wl["h"]
+    N = (n - 2) ** 2
+    R = wl["rho"].shape[0]
+    t0 = time.perf_counter()
+    op = pinv.PoissonInverse.build(n, n, h, wl["eps"])
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    op.quantize(16, keep_fp64=False)
+    rho = torch.from_numpy(wl["rho"]).cuda()
+    idx = torch.from_numpy(wl["sample"]).cuda()
+    d = torch.randn(R, idx.numel(), dtype=torch.float64, device="cuda") * 1e-3
+    u = torch.empty_like(rho)
+    gu = torch.zeros_like(rho)
+    lam = torch.empty_like(rho)
+    ge = torch.empty((n, n), dtype=torch.float64, device="cuda")
+
+    def step():
+        op.apply(rho, "int8", 16, out=u)
+        gu[:, idx] = 2.0 * (u[:, idx] - d)
+        op.apply_adjoint(gu, "int8", 16, out=lam)
+        op.grad_eps(u, lam, out=ge)
+
+    for k in ("gemm_i8", "grad_eps", "quantize_cols"):
+        pinv.trace_read(k)
+    pinv.trace_enable(True)
+    dt = _timed(step, args.steps, args.warmup)
+    pinv.trace_enable(False)
+    gms, gcnt = pinv.trace_read("gemm_i8")
+    ems, ecnt = pinv.trace_read("grad_eps")
+    qms, qcnt = pinv.trace_read("quantize_cols")
+    kms = gms / max(gcnt, 1)
+    ops = 2.0 * 4 * N * N * R
+    ach = ops / (kms * 1e-3) / 1e12
+    op.close()
+    line = _base("right-hand sides/sec through forward + adjoint + eps-gradient at 190^2 unknowns (16-bit)",
+                 R / dt, "rhs/s", args, dt * 1e3, "i8",
+                 {"workload": f"grad_192: 192x192 grid, {N} unknowns, eps=1+0.5 sin cos, {R} blob RHS, 512 sampled points, 16-bit inverse x 16-bit rho/g"})
+    line["roofline"] = {"kernel": "gemm_i8_kernel<2,2>", "bound": "mfma", "achieved": ach, "peak": PEAK_INT8_TOPS,
+                        "unit": "TOP/s", "frac": ach / PEAK_INT8_TOPS, "traffic": None, "avg_launch_ms": kms}
+    line["grad_eps_avg_ms"] = ems / max(ecnt, 1)
+    line["quantize_avg_ms"] = qms / max(qcnt, 1)
+    line["setup_s"] = {"build_inverse": t_build}
+    return line
+
+
+def bench_batched(args):
+    """4096 requests over 20 operators (grids 32^2..160^2, 4 log-normal eps fields
+    per size), 1-64 blob right-hand sides each, 16-bit quantised, one batched call."""
+    import numpy as np
+    import torch
+    from paper_1602_00001_amd import pinv, workloads
+    opdefs, reqs = workloads.batched_requests()
+    t0 = time.perf_counter()
+    ops = []
+    for od in opdefs:
+        n = od["n"]
+        op = pinv.PoissonInverse.build(n, n, 1.0 / (n - 1), od["eps"])
+        op.quantize(16, keep_fp64=False)
+        ops.append(op)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    batch = []
+    total_rhs = 0
+    ops_count = 0.0
+    for r in reqs:
+        op = ops[r["op"]]
+        n = opdefs[r["op"]]["n"]
+        par = workloads.blob_params_batch(np.random.default_rng(r["seed"]), r["nrhs"])
+        rho = workloads.blob_rhs_device(n, par)
+        batch.append((op, rho, torch.empty_like(rho)))
+        total_rhs += r["nrhs"]
+        ops_count += 2.0 * 4 * op.n * op.n * r["nrhs"]
+    for k in ("gemm_i8", "quantize_cols"):
+        pinv.trace_read(k)
+    pinv.trace_enable(True)
+    dt = _timed(lambda: pinv.apply_batched(batch, "int8", 16), args.steps, args.warmup)
+    pinv.trace_enable(False)
+    gms, gcnt = pinv.trace_read("gemm_i8")
+    qms, qcnt = pinv.trace_read("quantize_cols")
+    steps_traced = args.steps + args.warmup
+    gemm_ms_per_step = gms / steps_traced
+    ach = ops_count / (gemm_ms_per_step * 1e-3) / 1e12
+    for op in ops:
+        op.close()
+    line = _base("solves/sec over 4096 uneven requests (grids 32^2..160^2, 1-64 RHS each), 16-bit quantised, grouped by operator",
+                 total_rhs / dt, "solves/s", args, dt * 1e3, "i8",
+                 {"workload": f"batched: {len(reqs)} requests, {len(opdefs)} operators, {total_rhs} right-hand sides"})
+    line["roofline"] = {"kernel": "gemm_i8_kernel<2,2> (all groups)", "bound": "mfma", "achieved": ach,
+                        "peak": PEAK_INT8_TOPS, "unit": "TOP/s", "frac": ach / PEAK_INT8_TOPS, "traffic": None,
+                        "gemm_ms_per_step": gemm_ms_per_step, "gemm_launches_per_step": gcnt / steps_traced}
+    line["quantize_ms_per_step"] = qms / steps_traced
+    line["setup_s"] = {"build_and_quantize_20_operators": t_setup}
+    return line
+
+
+OTHER = {"plain_32": bench_plain_32, "vareps_64": bench_vareps_64, "grad_192": bench_grad_192,
+         "batched": bench_batched}
 
 
 if __name__ == "__main__":

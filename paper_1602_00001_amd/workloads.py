@@ -168,3 +168,23 @@ def grad_192(nrhs=256, nsample=512):
 def random_eps(nx, ny, g, lo=0.5, hi=2.0):
     """Generic positive eps field for tests: iid uniform in [lo, hi], [n_y][n_x]."""
     return g.uniform(lo, hi, (ny, nx))
+
+
+def blob_params_batch(g, nrhs, count=4):
+    """Blob parameters for nrhs independent right-hand sides: arrays [nrhs, count]."""
+    return (g.standard_normal((nrhs, count)), g.uniform(0.05, 0.15, (nrhs, count)),
+            g.uniform(0.1, 0.9, (nrhs, count)), g.uniform(0.1, 0.9, (nrhs, count)))
+
+
+def blob_rhs_device(n, params, device="cuda"):
+    """The blob fields of :func:`blob_rhs` evaluated with torch on a device, for
+    workloads too large to draw on the host: params from :func:`blob_params_batch`;
+    returns a float64 tensor [nrhs, (n-2)^2]."""
+    import torch
+    amp, width, cx, cy = (torch.as_tensor(a, dtype=torch.float64, device=device) for a in params)
+    t = torch.arange(1, n - 1, dtype=torch.float64, device=device) / (n - 1)
+    Y, X = torch.meshgrid(t, t, indexing="ij")
+    X = X.reshape(1, 1, -1)
+    Y = Y.reshape(1, 1, -1)
+    r2 = (X - cx[:, :, None]) ** 2 + (Y - cy[:, :, None]) ** 2
+    return (amp[:, :, None] * torch.exp(-r2 / (2.0 * width[:, :, None] ** 2))).sum(dim=1)
