@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--rho-bits", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default int8 kernel variant")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--workload", default="quant_128",
@@ -117,8 +118,11 @@ def main():
     op.quantize(args.bits)
     torch.cuda.synchronize()
     t_quant = time.perf_counter() - t0
-
     rho = torch.from_numpy(wl["rho"]).cuda()
+    t0 = time.perf_counter()
+    variant, variant_ms = _autotune(op, args, args.rho_bits, rho)
+    t_tune = time.perf_counter() - t0
+
     u8 = torch.empty_like(rho)
     u64 = torch.empty_like(rho)
     for _ in range(args.warmup):
@@ -185,7 +189,7 @@ def main():
         "int8_over_fp64": int8_sps / fp64_sps,
         "rel_l2_vs_fp64": {"max": rel_l2_max, "median": rel_l2_med, "bound": 1e-4, "ok": rel_l2_max <= 1e-4},
         "roofline": {
-            "kernel": f"gemm_i8_kernel<{S},{Sr}>",
+            "kernel": f"gemm_i8_kernel<{S},{Sr}> variant {variant}",
             "bound": "mfma", "achieved": ach_i8, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
             "frac": ach_i8 / PEAK_INT8_TOPS,
             "traffic": _traffic("gemm_i8_quant_128.traffic.json", "paper_1602_00001_amd/csrc/gemm_i8.hip"),
@@ -199,7 +203,8 @@ def main():
             "algorithmic_flops_per_launch": flops, "avg_launch_ms": gf_avg, "launches": gf_n,
         },
         "quantize_rho_avg_ms": qc_ms / max(qc_n, 1),
-        "setup_s": {"build_inverse": t_build, "quantize_inverse": t_quant},
+        "setup_s": {"build_inverse": t_build, "quantize_inverse": t_quant, "autotune_int8": t_tune},
+        "int8_variant": {"chosen": variant, "ms_per_launch": variant_ms},
     }
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
@@ -226,6 +231,14 @@ def main():
 
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
+
+
+def _autotune(op, args, rho_bits, rho):
+    """Pick the int8 kernel variant for this op on the workload's own right-hand
+    sides (setup, outside the timed region)."""
+    if args.no_autotune:
+        return 0, None
+    return op.autotune_int8(rho_bits, rho=rho, reps=5)
 
 
 def _timed(fn, steps, warmup):
@@ -331,6 +344,7 @@ def bench_grad_192(args):
     t_build = time.perf_counter() - t0
     op.quantize(16, keep_fp64=False)
     rho = torch.from_numpy(wl["rho"]).cuda()
+    variant, _ = _autotune(op, args, 16, rho)
     idx = torch.from_numpy(wl["sample"]).cuda()
     d = torch.randn(R, idx.numel(), dtype=torch.float64, device="cuda") * 1e-3
     u = torch.empty_like(rho)
@@ -359,7 +373,8 @@ def bench_grad_192(args):
     line = _base("right-hand sides/sec through forward + adjoint + eps-gradient at 190^2 unknowns (16-bit)",
                  R / dt, "rhs/s", args, dt * 1e3, "i8",
                  {"workload": f"grad_192: 192x192 grid, {N} unknowns, eps=1+0.5 sin cos, {R} blob RHS, 512 sampled points, 16-bit inverse x 16-bit rho/g"})
-    line["roofline"] = {"kernel": "gemm_i8_kernel<2,2>", "bound": "mfma", "achieved": ach, "peak": PEAK_INT8_TOPS,
+    line["roofline"] = {"kernel": f"gemm_i8_kernel<2,2> variant {variant}", "bound": "mfma", "achieved": ach,
+                        "peak": PEAK_INT8_TOPS,
                         "unit": "TOP/s", "frac": ach / PEAK_INT8_TOPS, "traffic": None, "avg_launch_ms": kms}
     line["grad_eps_avg_ms"] = ems / max(ecnt, 1)
     line["quantize_avg_ms"] = qms / max(qcnt, 1)
@@ -394,6 +409,13 @@ def bench_batched(args):
         batch.append((op, rho, torch.empty_like(rho)))
         total_rhs += r["nrhs"]
         ops_count += 2.0 * 4 * op.n * op.n * r["nrhs"]
+    # each operator's variant is tuned on the right-hand sides of its group
+    group = {}
+    for (op, rho, _) in batch:
+        group.setdefault(id(op), (op, []))[1].append(rho)
+    t0 = time.perf_counter()
+    variants = [_autotune(op, args, 16, torch.cat(rl))[0] for (op, rl) in group.values()]
+    t_tune = time.perf_counter() - t0
     for k in ("gemm_i8", "quantize_cols"):
         pinv.trace_read(k)
     pinv.trace_enable(True)
@@ -413,7 +435,8 @@ def bench_batched(args):
                         "peak": PEAK_INT8_TOPS, "unit": "TOP/s", "frac": ach / PEAK_INT8_TOPS, "traffic": None,
                         "gemm_ms_per_step": gemm_ms_per_step, "gemm_launches_per_step": gcnt / steps_traced}
     line["quantize_ms_per_step"] = qms / steps_traced
-    line["setup_s"] = {"build_and_quantize_20_operators": t_setup}
+    line["setup_s"] = {"build_and_quantize_20_operators": t_setup, "autotune_int8": t_tune}
+    line["int8_variants_chosen"] = variants
     return line
 
 

@@ -174,7 +174,9 @@ int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits,
  * over the faces f = (p, q) of the operator (lambda = 0 and u = u_B on the
  * boundary), and grad_nodes[i][j] = half the sum over the faces touching the
  * node.  grad_nodes: device [n_y][n_x], overwritten (no accumulation).
- * Asynchronous. */
+ * Deterministic (fixed summation order).  For nrhs > 16 a stream-ordered
+ * scratch of ceil(nrhs/16) * n_x * n_y doubles is taken from the device's
+ * memory pool for the duration of the call.  Asynchronous. */
 int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u,
                       const double* lambda, int64_t ld_lambda, int32_t nrhs,
                       double* grad_nodes, void* stream);
@@ -202,6 +204,33 @@ int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
                            int32_t rho_bits, void* stream);
 
 int32_t pinv_get_info(pinv_op op, pinv_info* info);
+
+/* Kernel selection for the int8 slice product (a performance choice only: every
+ * variant computes the same exact integer classes, so results are bit-identical
+ * whichever runs).  Variants differ in the k depth of an LDS stage (128 or 64
+ * bytes, with 2 to 4 stages in flight) and in the order in which workgroups
+ * take output tiles (grouped by the chip's eight L2 domains, or linear).
+ *
+ * pinv_int8_variants: number of variants (ids 0 .. count-1; 0 is the default).
+ * pinv_set_int8_variant: use `variant` for this op's int8 products (forward
+ *   and adjoint) at rho/g precision `rho_bits` (8, 16 or 24).
+ * pinv_autotune_int8: times every variant on this op (which must be
+ *   quantised) for `nrhs` right-hand sides at `rho_bits`: three rounds over
+ *   the variants, `reps` launches each after one warm-up, each variant keeping
+ *   its best round.  The digit planes timed are those of `rho` (device,
+ *   column-major N x nrhs, stride ld_rho >= N: representative right-hand sides
+ *   of the caller's workload; the matrix cores' clock depends on the data) or,
+ *   if rho is NULL, uniformly random digits.  Scratch device memory is
+ *   allocated and freed inside the call; the op's data is only read.  Selects
+ *   the fastest variant for the op and writes its id to *best (may be NULL) and
+ *   the mean milliseconds per launch of variant v to variant_ms[v] for
+ *   v < n_ms (variant_ms may be NULL).  Synchronises the stream.
+ *   E_STATE if the op is not quantised, E_INVALID_ARG for bad sizes. */
+int32_t pinv_int8_variants(void);
+int32_t pinv_set_int8_variant(pinv_op op, int32_t rho_bits, int32_t variant);
+int32_t pinv_autotune_int8(pinv_op op, int32_t rho_bits, const double* rho, int64_t ld_rho,
+                           int32_t nrhs, int32_t reps, double* variant_ms, int32_t n_ms,
+                           int32_t* best, void* stream);
 
 /* Kernel tracing (profiling aid).  While enabled, every kernel launched by the
  * library is bracketed by a pair of HIP events recorded on the same stream.

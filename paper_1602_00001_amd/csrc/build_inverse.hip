@@ -228,7 +228,7 @@ int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub
 
 done:
 #undef PINV_BAIL
-  if (st != PINV_OK) hipStreamSynchronize(s);
+  if (st != PINV_OK) (void)hipStreamSynchronize(s);
   if (Kb) (void)hipFree(Kb);
   if (Wb) (void)hipFree(Wb);
   if (Wd) (void)hipFree(Wd);

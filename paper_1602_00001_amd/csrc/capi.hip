@@ -202,6 +202,7 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
     a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
     a.w = w;
     a.U = U; a.ldu = ldu;
+    a.variant = op->i8_variant[SR];
     e = launch_gemm_i8(a, s);
   }
   hipError_t e2 = hipFreeAsync(scratch, s);
@@ -223,9 +224,24 @@ int32_t fp64_apply(pinv_op op, bool transpose, const double* X, int64_t ldx, int
   a.C = U; a.csm = 1; a.csn = ldu;
   a.M = op->n; a.N = nrhs; a.K = op->n;
   a.alpha = alpha; a.beta = 0.0; a.bias = bias;
-  TraceScope ts("gemm_f64", s);
-  PINV_HIP_TRY(launch_gemm_f64(a, s));
-  return PINV_OK;
+  a.ksplit = 1;
+  // the forward product (both operands k-contiguous) splits k when the tile
+  // grid alone would leave compute units idle
+  if (!transpose) gemm_f64_split_plan(a.M, a.N, a.K, &a.ksplit, &a.kchunk);
+  void* part = nullptr;
+  if (a.ksplit > 1) {
+    configure_pool_once();
+    PINV_HIP_TRY(hipMallocAsync(&part, (size_t)a.ksplit * a.M * a.N * sizeof(double), s));
+    a.part = (double*)part;
+  }
+  hipError_t e;
+  {
+    TraceScope ts("gemm_f64", s);
+    e = launch_gemm_f64(a, s);
+  }
+  const hipError_t e2 = part ? hipFreeAsync(part, s) : hipSuccess;
+  if (e != hipSuccess) return pinv_hip_status(e);
+  return pinv_hip_status(e2);
 }
 
 int32_t check_vectors(pinv_op op, const void* in, int64_t ld_in, int nrhs, const void* out, int64_t ld_out) {
@@ -526,10 +542,22 @@ int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u, const double* l
                       int32_t nrhs, double* grad_nodes, void* stream) {
   if (!op || !grad_nodes || nrhs < 0) return PINV_E_INVALID_ARG;
   if (nrhs > 0 && (!u || !lambda || ld_u < op->n || ld_lambda < op->n)) return PINV_E_INVALID_ARG;
-  TraceScope ts("grad_eps", as_stream(stream));
-  PINV_HIP_TRY(launch_grad_eps(op->nx, op->ny, op->h, u, ld_u, lambda, ld_lambda, nrhs, op->ub, grad_nodes,
-                               as_stream(stream)));
-  return PINV_OK;
+  hipStream_t s = as_stream(stream);
+  const int chunks = grad_eps_chunks(nrhs);
+  void* part = nullptr;
+  if (chunks > 1) {
+    configure_pool_once();
+    PINV_HIP_TRY(hipMallocAsync(&part, (size_t)chunks * op->nx * op->ny * sizeof(double), s));
+  }
+  hipError_t e;
+  {
+    TraceScope ts("grad_eps", s);
+    e = launch_grad_eps(op->nx, op->ny, op->h, u, ld_u, lambda, ld_lambda, nrhs, op->ub, (double*)part, grad_nodes,
+                        s);
+  }
+  const hipError_t e2 = part ? hipFreeAsync(part, s) : hipSuccess;
+  if (e != hipSuccess) return pinv_hip_status(e);
+  return pinv_hip_status(e2);
 }
 
 int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode, int32_t rho_bits, void* stream) {
@@ -615,6 +643,7 @@ int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
       a.w = op->w;
       a.U = nullptr; a.ldu = 0;
       a.ucols = (double* const*)(dt + first[g] + count[g]);
+      a.variant = op->i8_variant[SR];
       e = launch_gemm_i8(a, s);
     }
     const hipError_t e2 = hipFreeAsync(scratch, s);
@@ -637,6 +666,84 @@ int32_t pinv_get_info(pinv_op op, pinv_info* info) {
   info->has_bf16 = op->nbf;
   info->has_lift = op->w != nullptr;
   info->device_bytes = op->bytes;
+  return PINV_OK;
+}
+
+int32_t pinv_int8_variants(void) { return gemm_i8_variants(); }
+
+int32_t pinv_set_int8_variant(pinv_op op, int32_t rho_bits, int32_t variant) {
+  const int SR = slices_of_bits(rho_bits);
+  if (!op || !SR || variant < 0 || variant >= gemm_i8_variants()) return PINV_E_INVALID_ARG;
+  op->i8_variant[SR] = variant;
+  return PINV_OK;
+}
+
+int32_t pinv_autotune_int8(pinv_op op, int32_t rho_bits, const double* rho, int64_t ld_rho, int32_t nrhs,
+                           int32_t reps, double* variant_ms, int32_t n_ms, int32_t* best, void* stream) {
+  const int SR = slices_of_bits(rho_bits);
+  if (!op || !SR || nrhs <= 0 || reps <= 0 || n_ms < 0 || (n_ms > 0 && !variant_ms)) return PINV_E_INVALID_ARG;
+  if (rho && ld_rho < op->n) return PINV_E_INVALID_ARG;
+  if (!op->S) return PINV_E_STATE;
+  hipStream_t s = as_stream(stream);
+  const int Rpad = (nrhs + 127) / 128 * 128;
+  const size_t xq_bytes = (size_t)SR * Rpad * op->P;
+  const size_t f_bytes = (size_t)Rpad * sizeof(int32_t);
+  const size_t u_bytes = (size_t)nrhs * op->n * sizeof(double);
+  char* buf = nullptr;
+  PINV_HIP_TRY(hipMalloc(&buf, xq_bytes + f_bytes + u_bytes));
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipError_t e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  if (rho) {
+    if (e == hipSuccess)
+      e = launch_quantize_cols(rho, ld_rho, nullptr, op->n, nrhs, Rpad, SR, op->P, nullptr, (int8_t*)buf,
+                               (int32_t*)(buf + xq_bytes), s);
+  } else {
+    if (e == hipSuccess) e = launch_fill_random_i8((int8_t*)buf, xq_bytes, 12345u, s);
+    if (e == hipSuccess) e = hipMemsetAsync(buf + xq_bytes, 0, f_bytes, s);
+  }
+  GemmI8Args a{};
+  a.Q = op->Q; a.S = op->S;
+  a.X = (const int8_t*)buf; a.SR = SR;
+  a.P = op->P; a.Rpad = Rpad;
+  a.n = op->n; a.nrhs = nrhs;
+  a.row_exp = op->e;
+  a.col_exp = (const int32_t*)(buf + xq_bytes);
+  a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
+  a.w = nullptr;
+  a.U = (double*)(buf + xq_bytes + f_bytes); a.ldu = op->n;
+  // three rounds over all variants (so that clock drift during the call does
+  // not favour one position); each variant keeps its best round
+  const int nv = gemm_i8_variants();
+  std::vector<double> t(nv, 0.0);
+  for (int round = 0; round < 3 && e == hipSuccess; ++round) {
+    for (int v = 0; v < nv && e == hipSuccess; ++v) {
+      a.variant = v;
+      e = launch_gemm_i8(a, s);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(ev0, s);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_gemm_i8(a, s);
+      if (e == hipSuccess) e = hipEventRecord(ev1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+      if (e != hipSuccess) break;
+      const double avg = (double)ms / reps;
+      if (round == 0 || avg < t[v]) t[v] = avg;
+    }
+  }
+  int pick = 0;
+  for (int v = 0; v < nv; ++v) {
+    if (v < n_ms) variant_ms[v] = t[v];
+    if (t[v] < t[pick]) pick = v;
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) return pinv_hip_status(e);
+  op->i8_variant[SR] = pick;
+  if (best) *best = pick;
   return PINV_OK;
 }
 

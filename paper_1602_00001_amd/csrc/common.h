@@ -38,6 +38,7 @@ struct pinv_op_s {
   int8_t* Q = nullptr;
   int8_t* QT = nullptr;
   int32_t* e = nullptr;
+  int i8_variant[4] = {0, 0, 0, 0};   // int8 GEMM variant per rho slice count (autotuned)
 
   // split-precision copies, zero-padded row-major planes [P][P]
   float* G32 = nullptr;
@@ -90,8 +91,20 @@ struct GemmF64Args {
   double alpha, beta;
   const double* bias;
   int tri, kdiag;
+  // split-K (both operands k-contiguous, no tri/kdiag): ksplit > 1 workgroups
+  // share each output tile, each over k in [z*kchunk, (z+1)*kchunk); their raw
+  // sums go to part[z][n][m] (column-major M x N per z) and a second kernel
+  // adds them in order of z and applies alpha, beta and bias.
+  int ksplit;
+  int kchunk;
+  double* part;
 };
 hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t s);
+// split count and k chunk for an M x N x K product (ksplit = 1: no split)
+void gemm_f64_split_plan(int M, int N, int K, int* ksplit, int* kchunk);
+// C = alpha * sum_z part[z] + beta * C + bias (column-major part, M x N per z)
+hipError_t launch_splitk_reduce(const double* part, int ksplit, int M, int N, double alpha, double beta,
+                                const double* bias, double* C, int64_t csm, int64_t csn, hipStream_t s);
 
 // FP64 GEMV-style apply for few right-hand sides: u = alpha * G x + bias.
 hipError_t launch_gemv_f64(const double* G, int64_t ldg, int n, const double* x, int64_t ldx,
@@ -128,8 +141,11 @@ struct GemmI8Args {
   const double* w;                 // [n] or null
   double* U; int64_t ldu;
   double* const* ucols;            // if not null, column r of the output is ucols[r]
+  int variant;                     // kernel variant (0 .. gemm_i8_variants()-1)
 };
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s);
+int gemm_i8_variants();
+hipError_t launch_fill_random_i8(int8_t* p, size_t n, uint32_t seed, hipStream_t s);
 
 // ---- split precision ----------------------------------------------------------
 hipError_t launch_make_fp32(const double* G, int64_t ldg, int n, float* G32, hipStream_t s);
@@ -141,6 +157,8 @@ hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int
 size_t split_scratch_bytes(int mode, const pinv_op_s* op, int nrhs);
 
 // ---- gradient ------------------------------------------------------------------
+// part: scratch of grad_eps_chunks(nrhs) * nx * ny doubles (unused when that is <= 1)
+int grad_eps_chunks(int nrhs);
 hipError_t launch_grad_eps(int nx, int ny, double h, const double* u, int64_t ldu,
                            const double* lam, int64_t ldl, int nrhs, const double* ub,
-                           double* grad, hipStream_t s);
+                           double* part, double* grad, hipStream_t s);

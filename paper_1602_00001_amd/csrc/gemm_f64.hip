@@ -169,7 +169,10 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_nt_kernel(GemmF64Args a,
   if (!valid) return;
   const int m0 = mt * BM, n0 = nt * BN;
   if (a.tri == 1 && n0 > m0 + BM - 1) return;
-  const int K = a.K;
+  // k range of this workgroup (the whole of k unless split)
+  const int kz = blockIdx.y;
+  const int kb = a.ksplit > 1 ? kz * a.kchunk : 0;
+  const int K = a.ksplit > 1 ? min(a.K, kb + a.kchunk) : a.K;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -222,12 +225,12 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_nt_kernel(GemmF64Args a,
 
   const int fr = lane & 15, g = lane >> 4;
   int st = 0;
-  if (K > 0) {
-    load(0);
+  if (K > kb) {
+    load(kb);
     store(0);
   }
   __syncthreads();
-  for (int k0 = 0; k0 < K; k0 += BKK) {
+  for (int k0 = kb; k0 < K; k0 += BKK) {
     const bool has_next = k0 + BKK < K;
     if (has_next) load(k0 + BKK);
     double fa[4][4], fb[4][4];
@@ -268,6 +271,10 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_nt_kernel(GemmF64Args a,
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * r;
         if (m < a.M && n < a.N) {
+          if (a.ksplit > 1) {
+            a.part[((int64_t)kz * a.N + n) * a.M + m] = acc[i][j][r];
+            continue;
+          }
           double* c = a.C + (int64_t)m * a.csm + (int64_t)n * a.csn;
           double v = a.alpha * acc[i][j][r];
           if (a.beta != 0.0) v += a.beta * *c;
@@ -315,7 +322,53 @@ __global__ __launch_bounds__(256) void gemv_f64_kernel(const double* __restrict_
   }
 }
 
+// One thread per output element, threads along m (coalesced), the split parts
+// added in order of z.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const double* __restrict__ part, int ksplit, int M, int N,
+                                                           double alpha, double beta, const double* __restrict__ bias,
+                                                           double* __restrict__ C, int64_t csm, int64_t csn) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t MN = (int64_t)M * N;
+  if (idx >= MN) return;
+  const int m = (int)(idx % M), n = (int)(idx / M);
+  double acc = 0.0;
+  for (int z = 0; z < ksplit; ++z) acc += part[(int64_t)z * MN + idx];
+  double* c = C + (int64_t)m * csm + (int64_t)n * csn;
+  double v = alpha * acc;
+  if (beta != 0.0) v += beta * *c;
+  if (bias) v += bias[m];
+  *c = v;
+}
+
 }  // namespace
+
+void gemm_f64_split_plan(int M, int N, int K, int* ksplit, int* kchunk) {
+  // two 128x128 workgroups fit per compute unit: aim for 512 in flight, with at
+  // least 256 of k per split
+  const int T = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int z = 512 / (T > 0 ? T : 1);
+  const int zmax = K / 256;
+  if (z > zmax) z = zmax;
+  if (z > 16) z = 16;
+  if (z < 2) {
+    *ksplit = 1;
+    *kchunk = K;
+    return;
+  }
+  int chunk = (K + z - 1) / z;
+  chunk = (chunk + BKK - 1) / BKK * BKK;
+  *ksplit = (K + chunk - 1) / chunk;
+  *kchunk = chunk;
+}
+
+hipError_t launch_splitk_reduce(const double* part, int ksplit, int M, int N, double alpha, double beta,
+                                const double* bias, double* C, int64_t csm, int64_t csn, hipStream_t s) {
+  const int64_t MN = (int64_t)M * N;
+  if (MN == 0) return hipSuccess;
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, part, ksplit, M, N,
+                     alpha, beta, bias, C, csm, csn);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0) return hipSuccess;
@@ -324,10 +377,22 @@ hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t s) {
   const int grid = ((T + 7) / 8) * 8;
   if (a.a_kcontig && a.b_kcontig && !a.kdiag) {
     const bool vec = (a.lda % 2 == 0) && (a.ldb % 2 == 0) && ((uintptr_t)a.A % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
+    const bool split = a.ksplit > 1;
+    if (split && (a.tri || !a.part || a.kchunk <= 0 || a.kchunk % BKK != 0 ||
+                  (int64_t)a.kchunk * (a.ksplit - 1) >= a.K))
+      return hipErrorInvalidValue;
+    const dim3 g3(grid, split ? a.ksplit : 1);
     if (vec)
-      hipLaunchKernelGGL((gemm_f64_nt_kernel<true>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);
+      hipLaunchKernelGGL((gemm_f64_nt_kernel<true>), g3, dim3(NTHREADS), 0, s, a, tilesM, tilesN);
     else
-      hipLaunchKernelGGL((gemm_f64_nt_kernel<false>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);
+      hipLaunchKernelGGL((gemm_f64_nt_kernel<false>), g3, dim3(NTHREADS), 0, s, a, tilesM, tilesN);
+    if (split) {
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      return launch_splitk_reduce(a.part, a.ksplit, a.M, a.N, a.alpha, a.beta, a.bias, a.C, a.csm, a.csn, s);
+    }
+  } else if (a.ksplit > 1) {
+    return hipErrorInvalidValue;
   } else if (a.a_kcontig && a.b_kcontig)
     hipLaunchKernelGGL((gemm_f64_kernel<true, true>), dim3(grid), dim3(NTHREADS), 0, s, a, tilesM, tilesN);
   else if (a.a_kcontig && !a.b_kcontig)

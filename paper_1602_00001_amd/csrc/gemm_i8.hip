@@ -43,10 +43,11 @@ constexpr int NW = 8;                 // waves per workgroup (two per SIMD)
 constexpr int NT = NW * 64;
 constexpr int LDS_BYTES = 163840;
 
+template <int MAP>
 __device__ inline void tile_of(int bid, int tilesM, int tilesN, int& mt, int& nt, bool& valid) {
   const int T = tilesM * tilesN;
   const int per = (T + 7) / 8;
-  const int tile = (bid % 8) * per + bid / 8;
+  const int tile = MAP == 0 ? (bid % 8) * per + bid / 8 : bid;
   valid = tile < T;
   mt = valid ? tile / tilesN : 0;
   nt = valid ? tile % tilesN : 0;
@@ -61,12 +62,14 @@ __device__ inline void wait_vm() {
 
 __device__ inline void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
-// BK = k bytes per stage: 128 (full 128-byte cache lines per row) when two
-// stages of all planes fit in LDS, else 64.
-template <int S, int SR>
+// Kernel variants (picked per operator by pinv_autotune_int8): BK = k bytes
+// per stage, 128 (full 128-byte cache lines per row, two stages) or 64 (as many
+// stages as fit, at most 4); MAP 0 = XCD-aware tile order, 1 = linear; PF =
+// read all operand fragments of a k half before its matrix-core work.
+template <int S, int SR, int BK_>
 struct Cfg {
   static constexpr int C = S + SR - 1;
-  static constexpr int BK = (2 * (S + SR) * 128 * 128 <= LDS_BYTES) ? 128 : 64;
+  static constexpr int BK = BK_;
   static constexpr int CH = BK / 16;                       // 16-byte chunks per row
   static constexpr int PLANE = 128 * BK;                   // bytes of one plane per stage
   static constexpr int STAGE = (S + SR) * PLANE;
@@ -89,16 +92,16 @@ __device__ inline int swz(int row, int c) {
   return CH == 8 ? (c ^ ((row >> 1) & 7)) : (c ^ ((row >> 2) & 3));
 }
 
-template <int S, int SR>
+template <int S, int SR, int BKV, int MAP, bool PF>
 __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM, int tilesN) {
-  using K = Cfg<S, SR>;
+  using K = Cfg<S, SR, BKV>;
   constexpr int C = K::C, BK = K::BK, CH = K::CH, PLANE = K::PLANE, STAGE = K::STAGE, NST = K::NST;
   constexpr int RPI = K::RPI, RPW = K::RPW, IPP = K::IPP, L = K::L;
   __shared__ __attribute__((aligned(1024))) int8_t sm[NST * STAGE];
 
   int mt, nt;
   bool valid;
-  tile_of(blockIdx.x, tilesM, tilesN, mt, nt, valid);
+  tile_of<MAP>(blockIdx.x, tilesM, tilesN, mt, nt, valid);
   if (!valid) return;
   const int m0 = mt * BM, n0 = nt * BN;
   const int64_t P = a.P;
@@ -184,18 +187,42 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           fb[t][j] = *(const v4i*)(base + (S + t) * PLANE + (wn * 64 + j * 16) * BK + foff[h]);
+      if constexpr (PF) {
+        // all fragments of this k half first: the reads complete in order, so
+        // the matrix-core work of digit s waits only for its own reads
+        v4i fa[S][2];
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        v4i fa[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) fa[i] = *(const v4i*)(base + s * PLANE + (wm * 32 + i * 16) * BK + foff[h]);
-#pragma unroll
-        for (int t = 0; t < SR; ++t)
+        for (int s = 0; s < S; ++s)
 #pragma unroll
           for (int i = 0; i < 2; ++i)
+            fa[s][i] = *(const v4i*)(base + s * PLANE + (wm * 32 + i * 16) * BK + foff[h]);
+        // keep the scheduler from sinking the reads back between the products
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-              acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int t = 0; t < SR; ++t)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                acc[s + t][i][j] =
+                    __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s][i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          v4i fa[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+            fa[i] = *(const v4i*)(base + s * PLANE + (wm * 32 + i * 16) * BK + foff[h]);
+#pragma unroll
+          for (int t = 0; t < SR; ++t)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
+        }
       }
     }
   }
@@ -226,16 +253,42 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
   }
 }
 
+// variant v: BK = 128 if v % 2 == 0 (falls back to 64 when two 128-byte stages
+// do not fit), else 64; MAP = (v / 2) % 2; PF = v >= 4
 template <int S, int SR>
-hipError_t launch_t(const GemmI8Args& a, hipStream_t s) {
+constexpr int bk_of(int v) {
+  return (v % 2 == 0 && 2 * (S + SR) * 128 * 128 <= LDS_BYTES) ? 128 : 64;
+}
+
+template <int S, int SR, int V>
+hipError_t launch_v(const GemmI8Args& a, hipStream_t s) {
+  constexpr int BKV = bk_of<S, SR>(V);
+  constexpr int MAP = (V / 2) % 2;
+  constexpr bool PF = V >= 4;
   const int tilesM = (int)(a.P / BM), tilesN = a.Rpad / BN;
   const int T = tilesM * tilesN;
-  const int grid = ((T + 7) / 8) * 8;
-  hipLaunchKernelGGL((gemm_i8_kernel<S, SR>), dim3(grid), dim3(NT), 0, s, a, tilesM, tilesN);
+  const int grid = MAP == 0 ? ((T + 7) / 8) * 8 : T;
+  hipLaunchKernelGGL((gemm_i8_kernel<S, SR, BKV, MAP, PF>), dim3(grid), dim3(NT), 0, s, a, tilesM, tilesN);
   return hipGetLastError();
 }
 
+template <int S, int SR>
+hipError_t launch_t(const GemmI8Args& a, hipStream_t s) {
+  switch (a.variant) {
+    case 1: return launch_v<S, SR, 1>(a, s);
+    case 2: return launch_v<S, SR, 2>(a, s);
+    case 3: return launch_v<S, SR, 3>(a, s);
+    case 4: return launch_v<S, SR, 4>(a, s);
+    case 5: return launch_v<S, SR, 5>(a, s);
+    case 6: return launch_v<S, SR, 6>(a, s);
+    case 7: return launch_v<S, SR, 7>(a, s);
+    default: return launch_v<S, SR, 0>(a, s);
+  }
+}
+
 }  // namespace
+
+int gemm_i8_variants() { return 8; }
 
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s) {
   if (a.nrhs <= 0) return hipSuccess;

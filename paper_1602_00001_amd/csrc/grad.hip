@@ -7,54 +7,98 @@
 // values, so a node receives half of the gradient of each face it touches.
 // Faces that join two boundary nodes are not part of the operator.
 //
-// One thread per node; for each right-hand side the threads of a wave read
-// consecutive nodes, so the loads are coalesced.  Each node sums its own
-// faces in a fixed order (deterministic).
+// The right-hand sides are split into chunks of RC; workgroup (b, c) takes 256
+// nodes and chunk c, one thread per node: for each of its right-hand sides the
+// thread reads its own (u, lambda) and those of its four neighbours (the
+// threads of a wave read consecutive nodes, so the loads are coalesced and the
+// neighbours' come from cache) and adds the four face products.  Each chunk's
+// partial sums go to scratch; a second kernel adds the chunks in order and
+// scales.  Every sum has a fixed order, so the result is deterministic.
 
 #include "common.h"
 
 namespace {
 
-__global__ __launch_bounds__(256) void grad_eps_kernel(int nx, int ny, double h, const double* __restrict__ u,
-                                                      int64_t ldu, const double* __restrict__ lam, int64_t ldl,
-                                                      int nrhs, const double* __restrict__ ub,
-                                                      double* __restrict__ grad) {
+constexpr int RC = 16;
+
+__global__ __launch_bounds__(256) void grad_eps_partial_kernel(int nx, int ny, double h, const double* __restrict__ u,
+                                                              int64_t ldu, const double* __restrict__ lam,
+                                                              int64_t ldl, int nrhs, const double* __restrict__ ub,
+                                                              double* __restrict__ out, int final_scale) {
   const int node = blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= nx * ny) return;
+  const int nodes = nx * ny;
+  if (node >= nodes) return;
+  const int r0 = blockIdx.y * RC;
+  const int r1 = min(nrhs, r0 + RC);
   const int i = node / nx, j = node % nx;
   const int mx = nx - 2;
   const bool bp = (i == 0 || i == ny - 1 || j == 0 || j == nx - 1);
   const int ni[4] = {i - 1, i + 1, i, i};
   const int nj[4] = {j, j, j - 1, j + 1};
-  const int64_t pp = bp ? -1 : (int64_t)(i - 1) * mx + (j - 1);
+  const int64_t pp = bp ? 0 : (int64_t)(i - 1) * mx + (j - 1);
   const double ubp = (bp && ub) ? ub[node] : 0.0;
-  double total = 0.0;
+  bool use[4], bq[4];
+  int64_t qq[4];
+  double ubq[4];
+#pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int k = ni[t], l = nj[t];
-    if (k < 0 || k >= ny || l < 0 || l >= nx) continue;
-    const bool bq = (k == 0 || k == ny - 1 || l == 0 || l == nx - 1);
-    if (bp && bq) continue;
-    const int64_t qq = bq ? -1 : (int64_t)(k - 1) * mx + (l - 1);
-    const double ubq = (bq && ub) ? ub[(int64_t)k * nx + l] : 0.0;
-    double sf = 0.0;
-    for (int r = 0; r < nrhs; ++r) {
-      const double up = bp ? ubp : u[(int64_t)r * ldu + pp];
-      const double uq = bq ? ubq : u[(int64_t)r * ldu + qq];
-      const double lp = bp ? 0.0 : lam[(int64_t)r * ldl + pp];
-      const double lq = bq ? 0.0 : lam[(int64_t)r * ldl + qq];
-      sf += (lp - lq) * (up - uq);
-    }
-    total += sf;
+    const bool inside = k >= 0 && k < ny && l >= 0 && l < nx;
+    bq[t] = !inside || k == 0 || k == ny - 1 || l == 0 || l == nx - 1;
+    use[t] = inside && !(bp && bq[t]);
+    qq[t] = bq[t] ? 0 : (int64_t)(k - 1) * mx + (l - 1);
+    ubq[t] = (use[t] && bq[t] && ub) ? ub[(int64_t)k * nx + l] : 0.0;
   }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = r0; r < r1; ++r) {
+    const double* ur = u + (int64_t)r * ldu;
+    const double* lr = lam + (int64_t)r * ldl;
+    const double up = bp ? ubp : ur[pp];
+    const double lp = bp ? 0.0 : lr[pp];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (!use[t]) continue;
+      const double uq = bq[t] ? ubq[t] : ur[qq[t]];
+      const double lq = bq[t] ? 0.0 : lr[qq[t]];
+      acc[t] += (lp - lq) * (up - uq);
+    }
+  }
+  const double total = ((acc[0] + acc[1]) + acc[2]) + acc[3];
+  if (final_scale)
+    out[node] = 0.5 * total / (h * h);
+  else
+    out[(int64_t)blockIdx.y * nodes + node] = total;
+}
+
+__global__ __launch_bounds__(256) void grad_eps_reduce_kernel(int nodes, int chunks, double h,
+                                                             const double* __restrict__ part,
+                                                             double* __restrict__ grad) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nodes) return;
+  double total = 0.0;
+  for (int c = 0; c < chunks; ++c) total += part[(int64_t)c * nodes + node];
   grad[node] = 0.5 * total / (h * h);
 }
 
 }  // namespace
 
+int grad_eps_chunks(int nrhs) { return (nrhs + RC - 1) / RC; }
+
 hipError_t launch_grad_eps(int nx, int ny, double h, const double* u, int64_t ldu, const double* lam, int64_t ldl,
-                           int nrhs, const double* ub, double* grad, hipStream_t s) {
+                           int nrhs, const double* ub, double* part, double* grad, hipStream_t s) {
   const int nodes = nx * ny;
-  hipLaunchKernelGGL(grad_eps_kernel, dim3((nodes + 255) / 256), dim3(256), 0, s, nx, ny, h, u, ldu, lam, ldl, nrhs,
-                     ub, grad);
+  const int chunks = grad_eps_chunks(nrhs);
+  const dim3 blocks((nodes + 255) / 256);
+  if (chunks <= 1) {
+    // zero or one chunk: the partial kernel writes the scaled result directly
+    hipLaunchKernelGGL(grad_eps_partial_kernel, dim3(blocks.x, 1), dim3(256), 0, s, nx, ny, h, u, ldu, lam, ldl,
+                       nrhs, ub, grad, 1);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(grad_eps_partial_kernel, dim3(blocks.x, chunks), dim3(256), 0, s, nx, ny, h, u, ldu, lam, ldl,
+                     nrhs, ub, part, 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(grad_eps_reduce_kernel, blocks, dim3(256), 0, s, nodes, chunks, h, part, grad);
   return hipGetLastError();
 }

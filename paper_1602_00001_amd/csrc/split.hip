@@ -95,6 +95,11 @@ struct SplitArgs {
   const double* w;
   double* U;
   int64_t ldu;
+  // split-K: ksplit > 1 workgroups per tile, each over k in
+  // [z*kchunk, (z+1)*kchunk); raw sums (FP64) to part[z][r][m] (n x nrhs per z)
+  int ksplit;
+  int64_t kchunk;
+  double* part;
 };
 
 constexpr int BM = 128, BN = 128, ROWB = 80;
@@ -147,12 +152,14 @@ __global__ __launch_bounds__(256, 1) void gemm_bf16_kernel(SplitArgs a, int tile
 #pragma unroll
     for (int j = 0; j < 4; ++j) big[i][j] = small[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const int frag_off = (lane & 15) * ROWB + (lane >> 4) * 16;
-  const int64_t KB = P * 2;  // bytes along k
+  const int kz = blockIdx.y;
+  const int64_t KB0 = a.ksplit > 1 ? kz * a.kchunk * 2 : 0;                  // bytes along k
+  const int64_t KB = a.ksplit > 1 ? min(P, (kz + 1) * a.kchunk) * 2 : P * 2;
   int st = 0;
-  load(0);
+  load(KB0);
   store(0);
   __syncthreads();
-  for (int64_t kb = 0; kb < KB; kb += 64) {
+  for (int64_t kb = KB0; kb < KB; kb += 64) {
     const bool has_next = kb + 64 < KB;
     if (has_next) load(kb + 64);
     const int8_t* base = sm + st * STAGE;
@@ -191,7 +198,12 @@ __global__ __launch_bounds__(256, 1) void gemm_bf16_kernel(SplitArgs a, int tile
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
         if (m >= a.n) continue;
-        double v = a.alpha * ((double)big[i][j][r] + (double)small[i][j][r]);
+        const double sum = (double)big[i][j][r] + (double)small[i][j][r];
+        if (a.ksplit > 1) {
+          a.part[((int64_t)kz * a.nrhs + n) * a.n + m] = sum;
+          continue;
+        }
+        double v = a.alpha * sum;
         if (a.w) v += a.w[m];
         a.U[(int64_t)n * a.ldu + m] = v;
       }
@@ -245,12 +257,15 @@ __global__ __launch_bounds__(256, 2) void gemm_fp32_kernel(SplitArgs a, int tile
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int kz = blockIdx.y;
+  const int64_t K0 = a.ksplit > 1 ? kz * a.kchunk : 0;
+  const int64_t K1 = a.ksplit > 1 ? min(P, (kz + 1) * a.kchunk) : P;
   int st = 0;
-  load(0);
+  load(K0);
   store(0);
   __syncthreads();
-  for (int64_t k0 = 0; k0 < P; k0 += BKK) {
-    const bool has_next = k0 + BKK < P;
+  for (int64_t k0 = K0; k0 < K1; k0 += BKK) {
+    const bool has_next = k0 + BKK < K1;
     if (has_next) load(k0 + BKK);
 #pragma unroll
     for (int k4 = 0; k4 < BKK / 4; ++k4) {
@@ -279,6 +294,10 @@ __global__ __launch_bounds__(256, 2) void gemm_fp32_kernel(SplitArgs a, int tile
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
         if (m >= a.n) continue;
+        if (a.ksplit > 1) {
+          a.part[((int64_t)kz * a.nrhs + n) * a.n + m] = (double)acc[i][j][r];
+          continue;
+        }
         double v = a.alpha * (double)acc[i][j][r];
         if (a.w) v += a.w[m];
         a.U[(int64_t)n * a.ldu + m] = v;
@@ -301,12 +320,44 @@ hipError_t launch_make_bf16_parts(const double* G, int64_t ldg, int n, int parts
   return hipGetLastError();
 }
 
+namespace {
+
+// split-K plan: enough workgroups for `target` in flight, at least 512 of k per
+// split (kchunk a multiple of 256, so every split covers whole k steps of the
+// zero-padded operands)
+void split_plan(int64_t P, int Rpad, int target, int* ksplit, int64_t* kchunk) {
+  const int T = (int)(P / BM) * (Rpad / BN);
+  int z = target / (T > 0 ? T : 1);
+  const int zmax = (int)(P / 512);
+  if (z > zmax) z = zmax;
+  if (z > 16) z = 16;
+  if (z < 2) {
+    *ksplit = 1;
+    *kchunk = P;
+    return;
+  }
+  int64_t chunk = (P + z - 1) / z;
+  chunk = (chunk + 255) / 256 * 256;
+  *ksplit = (int)((P + chunk - 1) / chunk);
+  *kchunk = chunk;
+}
+
+int split_target(int mode) { return mode == PINV_FP32 ? 512 : 256; }
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
 size_t split_scratch_bytes(int mode, const pinv_op_s* op, int nrhs) {
   const int64_t P = pinv_pad_dim(op->n);
   const int Rpad = (nrhs + 127) / 128 * 128;
-  if (mode == PINV_FP32) return (size_t)Rpad * P * sizeof(float);
+  int ksplit;
+  int64_t kchunk;
+  split_plan(P, Rpad, split_target(mode), &ksplit, &kchunk);
+  const size_t part = ksplit > 1 ? (size_t)ksplit * op->n * nrhs * sizeof(double) : 0;
+  if (mode == PINV_FP32) return align256((size_t)Rpad * P * sizeof(float)) + part;
   const int parts = mode == PINV_BF16X3 ? 2 : 3;
-  return (size_t)parts * Rpad * P * sizeof(__bf16);
+  return align256((size_t)parts * Rpad * P * sizeof(__bf16)) + part;
 }
 
 hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int64_t ldx, int nrhs, double alpha,
@@ -321,10 +372,15 @@ hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int
   SplitArgs a{};
   a.P = P; a.Rpad = Rpad; a.n = op->n; a.nrhs = nrhs; a.alpha = alpha; a.w = op->w; a.U = U; a.ldu = ldu;
   a.B = scratch;
+  split_plan(P, Rpad, split_target(mode), &a.ksplit, &a.kchunk);
+  const size_t packed = mode == PINV_FP32 ? align256((size_t)Rpad * P * sizeof(float))
+                                          : align256((size_t)(mode == PINV_BF16X3 ? 2 : 3) * Rpad * P * sizeof(__bf16));
+  a.part = a.ksplit > 1 ? (double*)((char*)scratch + packed) : nullptr;
+  const dim3 g3(grid, a.ksplit);
   if (mode == PINV_FP32) {
     hipLaunchKernelGGL(pack_fp32_kernel, dim3(pgrid), dim3(256), 0, s, X, ldx, op->n, nrhs, Rpad, P, (float*)scratch);
     a.A = op->G32;
-    hipLaunchKernelGGL(gemm_fp32_kernel, dim3(grid), dim3(256), 0, s, a, tilesM, tilesN);
+    hipLaunchKernelGGL(gemm_fp32_kernel, g3, dim3(256), 0, s, a, tilesM, tilesN);
   } else {
     const int parts = mode == PINV_BF16X3 ? 2 : 3;
     hipLaunchKernelGGL(pack_bf16_kernel, dim3(pgrid), dim3(256), 0, s, X, ldx, op->n, nrhs, Rpad, P, parts,
@@ -332,9 +388,11 @@ hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int
     a.A = op->Gb;
     // G's parts are stored with op->nbf planes; the kernel reads the first `parts`
     if (parts == 2)
-      hipLaunchKernelGGL(gemm_bf16_kernel<2>, dim3(grid), dim3(256), 0, s, a, tilesM, tilesN);
+      hipLaunchKernelGGL(gemm_bf16_kernel<2>, g3, dim3(256), 0, s, a, tilesM, tilesN);
     else
-      hipLaunchKernelGGL(gemm_bf16_kernel<3>, dim3(grid), dim3(256), 0, s, a, tilesM, tilesN);
+      hipLaunchKernelGGL(gemm_bf16_kernel<3>, g3, dim3(256), 0, s, a, tilesM, tilesN);
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.ksplit <= 1) return e;
+  return launch_splitk_reduce(a.part, a.ksplit, op->n, nrhs, alpha, 0.0, op->w, U, 1, ldu, s);
 }

@@ -65,6 +65,9 @@ def _load():
         "pinv_destroy": ([vp], i32),
         "pinv_trace_enable": ([i32], i32),
         "pinv_trace_read": ([ctypes.c_char_p, P(ctypes.c_double), P(i64)], i32),
+        "pinv_int8_variants": ([], i32),
+        "pinv_set_int8_variant": ([vp, i32, i32], i32),
+        "pinv_autotune_int8": ([vp, i32, dp, i64, i32, i32, P(ctypes.c_double), i32, P(i32), vp], i32),
         "pinv_status_string": ([i32], ctypes.c_char_p),
         "pinv_version": ([], ctypes.c_char_p),
     }
@@ -80,7 +83,8 @@ lib = _load()
 EXPORTED = ("pinv_build_inverse", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
             "pinv_prepare_split", "pinv_export_quantized", "pinv_apply_inverse", "pinv_apply_inverse_adjoint",
             "pinv_grad_eps", "pinv_apply_batched", "pinv_get_info", "pinv_destroy", "pinv_status_string",
-            "pinv_version", "pinv_trace_enable", "pinv_trace_read")
+            "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_int8_variants",
+            "pinv_set_int8_variant", "pinv_autotune_int8")
 
 
 def status_string(st):
@@ -89,6 +93,10 @@ def status_string(st):
 
 def version():
     return lib.pinv_version().decode()
+
+
+def int8_variants():
+    return int(lib.pinv_int8_variants())
 
 
 def trace_enable(on=True):
@@ -254,6 +262,25 @@ class PoissonInverse:
         _check(lib.pinv_grad_eps(self._h, p_u, ld_u, p_l, ld_l, nu, ctypes.c_void_p(out.data_ptr()),
                                  _stream(stream)), "pinv_grad_eps")
         return out
+
+    def set_int8_variant(self, rho_bits, variant):
+        _check(lib.pinv_set_int8_variant(self._h, int(rho_bits), int(variant)), "pinv_set_int8_variant")
+
+    def autotune_int8(self, rho_bits=16, rho=None, nrhs=None, reps=10, stream=None):
+        """Time every int8 kernel variant on this op and keep the fastest.
+        rho: representative right-hand sides ([nrhs, N] float64 CUDA tensor),
+        or None for random digits of ``nrhs`` columns.
+        Returns (best variant id, list of mean ms per launch)."""
+        if rho is not None:
+            p, ld, R = _vectors(rho, self.n, "rho")
+        else:
+            p, ld, R = None, 0, int(nrhs if nrhs is not None else 1024)
+        nv = lib.pinv_int8_variants()
+        ms = (ctypes.c_double * nv)()
+        best = ctypes.c_int32(-1)
+        _check(lib.pinv_autotune_int8(self._h, int(rho_bits), p, ld, R, int(reps), ms, nv, ctypes.byref(best),
+                                      _stream(stream)), "pinv_autotune_int8")
+        return best.value, list(ms)
 
     def info(self):
         i = Info()

@@ -66,6 +66,9 @@ def test_host_side_argument_errors(pinv):
     assert lib.pinv_get_info(None, None) == pinv.E_INVALID_ARG
     assert lib.pinv_apply_batched(None, 3, 4, 16, None) == pinv.E_INVALID_ARG
     assert lib.pinv_apply_batched(None, 0, 4, 16, None) == pinv.OK
+    assert lib.pinv_int8_variants() >= 1
+    assert lib.pinv_set_int8_variant(None, 16, 0) == pinv.E_INVALID_ARG
+    assert lib.pinv_autotune_int8(None, 16, None, 0, 128, 1, None, 0, None, None) == pinv.E_INVALID_ARG
 
 
 def test_binding_rejects_missing_library(tmp_path, monkeypatch, pinv):

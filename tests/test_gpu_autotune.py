@@ -1,0 +1,83 @@
+"""Int8 kernel variants: every variant gives the oracle's integer result bit for
+bit (forward and adjoint, several slice counts, a grid whose tile count is not a
+multiple of eight), and autotuning picks a valid variant, reports a time for
+each, and leaves the results unchanged."""
+
+import numpy as np
+import pytest
+
+from oracle import apply, quant
+from paper_1602_00001_amd import workloads
+from tests.gpu_util import announce, dev, host, oracle_inverse, oracle_int8, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def pinv():
+    from paper_1602_00001_amd import pinv as p
+    return p
+
+
+@pytest.mark.parametrize("nx,ny,bits,rho_bits", [(40, 31, 24, 16), (33, 20, 16, 24), (12, 9, 8, 8)])
+def test_every_variant_bit_exact(torch, pinv, nx, ny, bits, rho_bits):
+    g = np.random.default_rng(nx * ny + bits)
+    ub = g.standard_normal((ny, nx))
+    h = 1.0 / (max(nx, ny) - 1)
+    G, w, _ = oracle_inverse(nx, ny, workloads.random_eps(nx, ny, g), ub)
+    N = G.shape[0]
+    rho = g.uniform(-1, 1, (300, N))
+    ref, _, _ = oracle_int8(G, bits // 8, rho.T, rho_bits // 8, h, w)
+    gv = g.standard_normal((70, N))
+    S, Sg = bits // 8, rho_bits // 8
+    qG, e = quant.quantize_rows(G, S)
+    qg, f = quant.quantize_cols(gv.T, Sg, pre_exponent=e)
+    ref_adj, _ = apply.integer_apply(qG.T, e, S, qg, f, Sg, h, None, row_exponent=False)
+    with pinv.PoissonInverse.from_inverse(nx, ny, h, G, None, ub, w) as op:
+        op.quantize(bits)
+        for v in range(pinv.int8_variants()):
+            announce(f"int8 variant {v} nx={nx} ny={ny} bits={bits} rho_bits={rho_bits}")
+            op.set_int8_variant(rho_bits, v)
+            u = host(op.apply(dev(rho), "int8", rho_bits))
+            assert np.array_equal(u.T, ref), v
+            lam = host(op.apply_adjoint(dev(gv), "int8", rho_bits))
+            assert np.array_equal(lam.T, ref_adj), v
+
+
+def test_autotune_picks_a_variant_and_keeps_results(torch, pinv):
+    nx = ny = 50
+    g = np.random.default_rng(77)
+    h = 1.0 / (nx - 1)
+    G, _, _ = oracle_inverse(nx, ny)
+    rho = g.uniform(-1, 1, (200, G.shape[0]))
+    ref, _, _ = oracle_int8(G, 3, rho.T, 2, h)
+    with pinv.PoissonInverse.from_inverse(nx, ny, h, G) as op:
+        with pytest.raises(pinv.PinvError) as ei:
+            op.autotune_int8(16, nrhs=256, reps=2)
+        assert ei.value.status == pinv.E_STATE
+        op.quantize(24)
+        for src in ("random digits", "caller rho"):
+            announce(f"autotune int8 50x50 on {src}, 3 reps")
+            if src == "caller rho":
+                best, ms = op.autotune_int8(16, rho=dev(rho), reps=3)
+            else:
+                best, ms = op.autotune_int8(16, nrhs=256, reps=3)
+            print(f"[autotune] {src}: best {best} ms {ms}", flush=True)
+            assert 0 <= best < pinv.int8_variants()
+            assert len(ms) == pinv.int8_variants() and all(t > 0 for t in ms)
+            assert ms[best] == min(ms)
+            u = host(op.apply(dev(rho), "int8", 16))
+            assert np.array_equal(u.T, ref)
+        for bad in [dict(nrhs=0), dict(nrhs=10, reps=0), dict(rho_bits=12, nrhs=10)]:
+            kw = dict(rho_bits=16, reps=1)
+            kw.update(bad)
+            with pytest.raises(pinv.PinvError) as ei:
+                op.autotune_int8(**kw)
+            assert ei.value.status == pinv.E_INVALID_ARG
+        with pytest.raises(pinv.PinvError):
+            op.set_int8_variant(16, pinv.int8_variants())

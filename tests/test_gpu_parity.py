@@ -171,17 +171,19 @@ def test_split_modes_against_emulation(torch, pinv, mode, nx, ny):
 
 # ---------------------------------------------------------------- derivatives
 
-@pytest.mark.parametrize("nx,ny", [(12, 9), (40, 33)])
-def test_fp64_adjoint_and_grad_eps(torch, pinv, nx, ny):
-    announce(f"adjoint fp64 + grad_eps nx={nx} ny={ny}")
+@pytest.mark.parametrize("nx,ny,R", [(12, 9, 6), (40, 33, 6), (40, 33, 53), (17, 23, 16)])
+def test_fp64_adjoint_and_grad_eps(torch, pinv, nx, ny, R):
+    """R > 16 runs the chunked two-kernel path (53 = three full chunks and a
+    ragged one); R <= 16 the single-kernel path."""
+    announce(f"adjoint fp64 + grad_eps nx={nx} ny={ny} nrhs={R}")
     g = np.random.default_rng(21)
     h = 1.0 / (max(nx, ny) - 1)
     eps = workloads.random_eps(nx, ny, g)
     ub = g.standard_normal((ny, nx))
     G, w, _ = oracle_inverse(nx, ny, eps, ub)
     N = G.shape[0]
-    rho = g.standard_normal((6, N))
-    gv = g.standard_normal((6, N))
+    rho = g.standard_normal((R, N))
+    gv = g.standard_normal((R, N))
     u_ref = apply.plain_apply(G, rho.T, h, w)
     lam_ref = grad.adjoint(G, gv.T, h)
     ge_ref = grad.grad_eps_nodes(nx, ny, h, u_ref, lam_ref, ub)
@@ -192,6 +194,17 @@ def test_fp64_adjoint_and_grad_eps(torch, pinv, nx, ny):
         lam = host(lam)
     assert np.max(metrics.rel_l2_per_rhs(lam.T, lam_ref)) <= 1e-12
     assert np.linalg.norm(ge - ge_ref) <= 1e-12 * np.linalg.norm(ge_ref)
+
+
+def test_grad_eps_without_right_hand_sides_is_zero(torch, pinv):
+    announce("grad_eps nrhs=0")
+    nx, ny = 10, 8
+    G, _, _ = oracle_inverse(nx, ny)
+    with pinv.PoissonInverse.from_inverse(nx, ny, 0.1, G) as op:
+        empty = torch.empty((0, op.n), dtype=torch.float64, device="cuda")
+        out = torch.full((ny, nx), float("nan"), dtype=torch.float64, device="cuda")
+        op.grad_eps(empty, empty, out=out)
+        assert float(out.abs().sum()) == 0.0
 
 
 def test_autograd_matches_finite_differences(torch, pinv):
