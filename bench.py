@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="use the default int8 kernel variant")
+    ap.add_argument("--int8-variant", type=int, default=None,
+                    help="use this int8 kernel variant instead of autotuning (profiling runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--workload", default="quant_128",
@@ -236,6 +238,9 @@ PEAK_BF16_TFLOPS = 2500.0
 def _autotune(op, args, rho_bits, rho):
     """Pick the int8 kernel variant for this op on the workload's own right-hand
     sides (setup, outside the timed region)."""
+    if args.int8_variant is not None:
+        op.set_int8_variant(rho_bits, args.int8_variant)
+        return args.int8_variant, None
     if args.no_autotune:
         return 0, None
     return op.autotune_int8(rho_bits, rho=rho, reps=5)

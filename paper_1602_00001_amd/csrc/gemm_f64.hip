@@ -57,42 +57,41 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_kernel(GemmF64Args a, in
 
   double ra[8], rb[8];
 
+  // Loads are unconditional, from indices clamped into the operands; values
+  // outside them are zeroed when written to LDS (a load under a per-lane
+  // condition would make later writes of its register wait for it).
   auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int idx = i * NTHREADS + tid;
       int kk, mm;
       if (AK) { kk = idx & 15; mm = idx >> 4; } else { kk = idx >> 7; mm = idx & 127; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < a.M && gk < K) v = AK ? a.A[(int64_t)gm * a.lda + gk] : a.A[(int64_t)gk * a.lda + gm];
-      ra[i] = v;
+      const int gm = min(m0 + mm, a.M - 1), gk = min(k0 + kk, K - 1);
+      ra[i] = AK ? a.A[(int64_t)gm * a.lda + gk] : a.A[(int64_t)gk * a.lda + gm];
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int idx = i * NTHREADS + tid;
       int kk, nn;
       if (BKc) { kk = idx & 15; nn = idx >> 4; } else { kk = idx >> 7; nn = idx & 127; }
-      const int gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < a.N && gk < K) v = BKc ? a.B[(int64_t)gn * a.ldb + gk] : a.B[(int64_t)gk * a.ldb + gn];
-      rb[i] = v;
+      const int gn = min(n0 + nn, a.N - 1), gk = min(k0 + kk, K - 1);
+      rb[i] = BKc ? a.B[(int64_t)gn * a.ldb + gk] : a.B[(int64_t)gk * a.ldb + gn];
     }
   };
-  auto store = [&](int st) {
+  auto store = [&](int st, int k0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int idx = i * NTHREADS + tid;
       int kk, mm;
       if (AK) { kk = idx & 15; mm = idx >> 4; } else { kk = idx >> 7; mm = idx & 127; }
-      As[st][kk][mm] = ra[i];
+      As[st][kk][mm] = (m0 + mm < a.M && k0 + kk < K) ? ra[i] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int idx = i * NTHREADS + tid;
       int kk, nn;
       if (BKc) { kk = idx & 15; nn = idx >> 4; } else { kk = idx >> 7; nn = idx & 127; }
-      Bs[st][kk][nn] = rb[i];
+      Bs[st][kk][nn] = (n0 + nn < a.N && k0 + kk < K) ? rb[i] : 0.0;
     }
   };
 
@@ -105,7 +104,7 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_kernel(GemmF64Args a, in
   int st = 0;
   if (kbeg < K) {
     load(kbeg);
-    store(0);
+    store(0, kbeg);
   }
   __syncthreads();
   for (int k0 = kbeg; k0 < K; k0 += BKK) {
@@ -124,7 +123,7 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_kernel(GemmF64Args a, in
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
-    if (has_next) store(st ^ 1);
+    if (has_next) store(st ^ 1, k0 + BKK);
     __syncthreads();
     st ^= 1;
   }
@@ -178,42 +177,60 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_nt_kernel(GemmF64Args a,
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  // loads: item it covers row (it*256 + tid) >> 3, 16-byte chunk (tid & 7)
+  // loads: item it covers row (it*256 + tid) >> 3, 16-byte chunk (tid & 7).
+  // The loads themselves are unconditional, from addresses clamped into the
+  // operands; rows and k beyond the operands are zeroed when the registers are
+  // written to LDS.  (Loads under per-lane conditions would make every later
+  // write of the same registers wait for the load, serialising the loads.)
   const int lchunk = tid & 7;
   double2 ra[4], rb[4];
+  // row offsets (elements) from the tile's first row, rows clamped into the
+  // operand; 32-bit, since a tile spans 128 rows
+  const double* Ab = a.A + (int64_t)m0 * a.lda;
+  const double* Bb = a.B + (int64_t)n0 * a.ldb;
+  uint32_t oa[4], ob[4];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int row = (it * NTHREADS + tid) >> 3;
+    oa[it] = (uint32_t)(min(m0 + row, a.M - 1) - m0) * (uint32_t)a.lda;
+    ob[it] = (uint32_t)(min(n0 + row, a.N - 1) - n0) * (uint32_t)a.ldb;
+  }
   auto load = [&](int k0) {
     const int gk = k0 + 2 * lchunk;
+    // one uniform branch around all the loads of the step (a branch per load
+    // would make each join wait for the loads before it)
+    if (VEC && k0 + BKK <= K) {  // the whole k step lies inside the operands
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int row = (it * NTHREADS + tid) >> 3;
-      const int gm = m0 + row, gn = n0 + row;
-      double2 va = {0.0, 0.0}, vb = {0.0, 0.0};
-      if (VEC) {
-        if (gm < a.M && gk + 1 < K) va = *(const double2*)(a.A + (int64_t)gm * a.lda + gk);
-        else if (gm < a.M && gk < K) va.x = a.A[(int64_t)gm * a.lda + gk];
-        if (gn < a.N && gk + 1 < K) vb = *(const double2*)(a.B + (int64_t)gn * a.ldb + gk);
-        else if (gn < a.N && gk < K) vb.x = a.B[(int64_t)gn * a.ldb + gk];
-      } else {
-        if (gm < a.M) {
-          if (gk < K) va.x = a.A[(int64_t)gm * a.lda + gk];
-          if (gk + 1 < K) va.y = a.A[(int64_t)gm * a.lda + gk + 1];
-        }
-        if (gn < a.N) {
-          if (gk < K) vb.x = a.B[(int64_t)gn * a.ldb + gk];
-          if (gk + 1 < K) vb.y = a.B[(int64_t)gn * a.ldb + gk + 1];
-        }
+      for (int it = 0; it < 4; ++it) {
+        ra[it] = *(const double2*)(Ab + (oa[it] + (uint32_t)gk));
+        rb[it] = *(const double2*)(Bb + (ob[it] + (uint32_t)gk));
       }
-      ra[it] = va;
-      rb[it] = vb;
+    } else {
+      const uint32_t k0c = (uint32_t)min(gk, K - 1), k1c = (uint32_t)min(gk + 1, K - 1);
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        ra[it].x = Ab[oa[it] + k0c];
+        ra[it].y = Ab[oa[it] + k1c];
+        rb[it].x = Bb[ob[it] + k0c];
+        rb[it].y = Bb[ob[it] + k1c];
+      }
     }
   };
-  auto store = [&](int st) {
+  auto store = [&](int st, int k0) {
+    const int gk = k0 + 2 * lchunk;
+    const bool in0 = gk < K, in1 = gk + 1 < K;
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const int row = (it * NTHREADS + tid) >> 3;
       const int pc = lchunk ^ ((row >> 1) & 7);
-      *(double2*)(&As[st][row * BKK + pc * 2]) = ra[it];
-      *(double2*)(&Bs[st][row * BKK + pc * 2]) = rb[it];
+      const bool okm = m0 + row < a.M, okn = n0 + row < a.N;
+      double2 va, vb;
+      va.x = (okm && in0) ? ra[it].x : 0.0;
+      va.y = (okm && in1) ? ra[it].y : 0.0;
+      vb.x = (okn && in0) ? rb[it].x : 0.0;
+      vb.y = (okn && in1) ? rb[it].y : 0.0;
+      *(double2*)(&As[st][row * BKK + pc * 2]) = va;
+      *(double2*)(&Bs[st][row * BKK + pc * 2]) = vb;
     }
   };
 
@@ -227,7 +244,7 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_nt_kernel(GemmF64Args a,
   int st = 0;
   if (K > kb) {
     load(kb);
-    store(0);
+    store(0, kb);
   }
   __syncthreads();
   for (int k0 = kb; k0 < K; k0 += BKK) {
@@ -257,7 +274,7 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_nt_kernel(GemmF64Args a,
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][sk], fb[j][sk], acc[i][j], 0, 0, 0);
-    if (has_next) store(st ^ 1);
+    if (has_next) store(st ^ 1, k0 + BKK);
     __syncthreads();
     st ^= 1;
   }
