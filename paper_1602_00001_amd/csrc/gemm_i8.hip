@@ -38,10 +38,8 @@
 
 namespace {
 
-constexpr int BM = 128, BN = 128;
-constexpr int NW = 8;                 // waves per workgroup (two per SIMD)
-constexpr int NT = NW * 64;
-constexpr int LDS_BYTES = 163840;
+constexpr int BN = 128;               // right-hand sides per tile
+constexpr int LDS_BYTES = 163840;     // per compute unit
 
 template <int MAP>
 __device__ inline void tile_of(int bid, int tilesM, int tilesN, int& mt, int& nt, bool& valid) {
@@ -62,26 +60,43 @@ __device__ inline void wait_vm() {
 
 __device__ inline void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
+// s_waitcnt lgkmcnt(0) only (vector-memory and export counters unconstrained)
+__device__ inline void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4)); }
+
 // Kernel variants (picked per operator by pinv_autotune_int8): BK = k bytes
 // per stage, 128 (full 128-byte cache lines per row, two stages) or 64 (as many
 // stages as fit, at most 4); MAP 0 = XCD-aware tile order, 1 = linear; PF =
 // read all operand fragments of a k half before its matrix-core work.
-template <int S, int SR, int BK_>
+template <int S, int SR, int BK_, int NW_>
 struct Cfg {
+  static constexpr int NW = NW_;                           // waves per workgroup
+  static constexpr int NT = NW * 64;
+  static constexpr int BM = NW * 16;                       // rows per tile: waves in (BM/32) x 2
+  static constexpr int WGS = NW == 8 ? 1 : 2;              // workgroups per compute unit
   static constexpr int C = S + SR - 1;
   static constexpr int BK = BK_;
   static constexpr int CH = BK / 16;                       // 16-byte chunks per row
-  static constexpr int PLANE = 128 * BK;                   // bytes of one plane per stage
-  static constexpr int STAGE = (S + SR) * PLANE;
-  static constexpr int NST_ = LDS_BYTES / STAGE;
+  static constexpr int PLANE_A = BM * BK;                  // bytes of one G plane per stage
+  static constexpr int PLANE_B = BN * BK;                  // bytes of one rho plane per stage
+  static constexpr int STAGE = S * PLANE_A + SR * PLANE_B;
+  static constexpr int NST_ = LDS_BYTES / WGS / STAGE;
   static constexpr int NST = NST_ > 4 ? 4 : NST_;
   static constexpr int RPI = 1024 / BK;                    // rows filled by one DMA instruction
-  static constexpr int RPW = 128 / NW;                     // rows of a plane filled by one wave
-  static constexpr int IPP = RPW / RPI;                    // DMA instructions per plane per wave
-  static constexpr int L = (S + SR) * IPP;                 // DMA instructions per thread per stage
+  static constexpr int IPA = BM / NW / RPI;                // DMA instructions per G plane per wave
+  static constexpr int IPB = BN / NW / RPI;                // DMA instructions per rho plane per wave
+  static constexpr int L = S * IPA + SR * IPB;             // DMA instructions per thread per stage
   static_assert(NST >= 2, "two LDS stages must fit");
-  static_assert(IPP >= 1, "a wave fills at least one DMA block per plane");
+  static_assert(IPA >= 1 && IPB >= 1, "a wave fills at least one DMA block per plane");
 };
+
+// rho digits whose half-step products are deferred past the barrier in the
+// split-step pipeline: registers per lane ~ 32 C (accumulators) + 4 (2S + 4SR)
+// (fragments being read) + 4 (2S + 4DT) (fragments held) + 24 <= 256
+constexpr int dt_of(int S, int SR) {
+  int dt = SR;
+  while (dt > 1 && 32 * (S + SR - 1) + 4 * (2 * S + 4 * SR) + 4 * (2 * S + 4 * dt) + 24 > 256) --dt;
+  return dt;
+}
 
 // Swizzle: the 16-byte chunk c of tile row r sits at chunk position
 // c ^ ((r >> 1) & 7) (128-byte rows) or c ^ ((r >> 2) & 3) (64-byte rows), so
@@ -92,11 +107,13 @@ __device__ inline int swz(int row, int c) {
   return CH == 8 ? (c ^ ((row >> 1) & 7)) : (c ^ ((row >> 2) & 3));
 }
 
-template <int S, int SR, int BKV, int MAP, bool PF>
-__global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM, int tilesN) {
-  using K = Cfg<S, SR, BKV>;
-  constexpr int C = K::C, BK = K::BK, CH = K::CH, PLANE = K::PLANE, STAGE = K::STAGE, NST = K::NST;
-  constexpr int RPI = K::RPI, RPW = K::RPW, IPP = K::IPP, L = K::L;
+template <int S, int SR, int BKV, int MAP, int PF, int NWV>
+__global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(GemmI8Args a, int tilesM,
+                                                                         int tilesN) {
+  using K = Cfg<S, SR, BKV, NWV>;
+  constexpr int C = K::C, BK = K::BK, CH = K::CH, STAGE = K::STAGE, NST = K::NST;
+  constexpr int BM = K::BM, NW = K::NW, PLANE_A = K::PLANE_A, PLANE_B = K::PLANE_B;
+  constexpr int RPI = K::RPI, IPA = K::IPA, IPB = K::IPB, L = K::L;
   __shared__ __attribute__((aligned(1024))) int8_t sm[NST * STAGE];
 
   int mt, nt;
@@ -110,38 +127,45 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave >> 1, wn = wave & 1;     // 4 x 2 waves, each 32 rows x 64 right-hand sides
+  const int wm = wave >> 1, wn = wave & 1;     // (BM/32) x 2 waves, each 32 rows x 64 right-hand sides
 
-  // DMA: instruction j of wave w fills plane rows w*RPW + j*RPI .. + RPI-1; lane l
-  // lands at LDS byte l*16 of that block = row l / CH, chunk position l % CH,
-  // so it loads the logical chunk whose swizzled position is l % CH.  The
-  // address is a wave-uniform plane base plus a 32-bit per-lane offset.
-  uint32_t off[IPP];
+  // DMA: instruction j of wave w fills plane rows w*(rows/NW) + j*RPI .. + RPI-1;
+  // lane l lands at LDS byte l*16 of that block = row l / CH, chunk position
+  // l % CH, so it loads the logical chunk whose swizzled position is l % CH.
+  // The address is a wave-uniform plane base plus a 32-bit per-lane offset.
+  uint32_t offa[IPA], offb[IPB];
 #pragma unroll
-  for (int j = 0; j < IPP; ++j) {
-    const int row = wave * RPW + j * RPI + lane / CH;
-    off[j] = (uint32_t)row * (uint32_t)P + (uint32_t)(swz<CH>(row, lane % CH) * 16);  // swizzle is an involution
+  for (int j = 0; j < IPA; ++j) {
+    const int row = wave * (BM / NW) + j * RPI + lane / CH;
+    offa[j] = (uint32_t)row * (uint32_t)P + (uint32_t)(swz<CH>(row, lane % CH) * 16);  // swizzle is an involution
+  }
+#pragma unroll
+  for (int j = 0; j < IPB; ++j) {
+    const int row = wave * (BN / NW) + j * RPI + lane / CH;
+    offb[j] = (uint32_t)row * (uint32_t)P + (uint32_t)(swz<CH>(row, lane % CH) * 16);
   }
   const int8_t* tileA = a.Q + (int64_t)m0 * P;
   const int8_t* tileB = a.X + (int64_t)n0 * P;
   const int64_t planeA = P * P, planeB = (int64_t)a.Rpad * P;
 
   auto issue = [&](int step) {
-    int8_t* dst = sm + (step % NST) * STAGE + wave * RPW * BK;
+    int8_t* dst = sm + (step % NST) * STAGE;
     const int64_t k0 = (int64_t)step * BK;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int8_t* b = tileA + s * planeA + k0;
+      int8_t* d = dst + s * PLANE_A + wave * (BM / NW) * BK;
 #pragma unroll
-      for (int j = 0; j < IPP; ++j)
-        __builtin_amdgcn_global_load_lds((const void*)(b + off[j]), PINV_LDS(dst + s * PLANE + j * 1024), 16, 0, 0);
+      for (int j = 0; j < IPA; ++j)
+        __builtin_amdgcn_global_load_lds((const void*)(b + offa[j]), PINV_LDS(d + j * 1024), 16, 0, 0);
     }
 #pragma unroll
     for (int t = 0; t < SR; ++t) {
       const int8_t* b = tileB + t * planeB + k0;
+      int8_t* d = dst + S * PLANE_A + t * PLANE_B + wave * (BN / NW) * BK;
 #pragma unroll
-      for (int j = 0; j < IPP; ++j)
-        __builtin_amdgcn_global_load_lds((const void*)(b + off[j]), PINV_LDS(dst + (S + t) * PLANE + j * 1024), 16, 0, 0);
+      for (int j = 0; j < IPB; ++j)
+        __builtin_amdgcn_global_load_lds((const void*)(b + offb[j]), PINV_LDS(d + j * 1024), 16, 0, 0);
     }
   };
 
@@ -160,68 +184,124 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[c][i][j] = v4i{0, 0, 0, 0};
 
-  // Every step issues one DMA group; past the last k step the group re-loads
-  // the last step into the stage freed one step earlier (never read again),
-  // so the number of groups in flight after group k is always NST-2.
+  // fragment reads of k half h of the stage at `base` and the products of one
+  // k half (16-row blocks start at multiples of 16, where the swizzle of the
+  // block base is zero, so one lane offset serves every block)
+  auto read_a = [&](const int8_t* base, int h, int s, v4i (&fa)[2]) {
 #pragma unroll
-  for (int p = 0; p < NST - 1; ++p) issue(min(p, nsteps - 1));
-
-  for (int k = 0; k < nsteps; ++k) {
-    wait_vm<(NST - 2) * L>();
-    lds_barrier();
-    // (an explicit branch, not min(): it keeps the DMA issue in its own
-    // scheduling region, away from the matrix-core block)
-    if (k + NST - 1 < nsteps)
-      issue(k + NST - 1);
-    else
-      issue(nsteps - 1);
-
-    const int8_t* base = sm + (k % NST) * STAGE;
+    for (int i = 0; i < 2; ++i) fa[i] = *(const v4i*)(base + s * PLANE_A + (wm * 32 + i * 16) * BK + foff[h]);
+  };
+  auto read_b = [&](const int8_t* base, int h, v4i (&fb)[SR][4]) {
 #pragma unroll
-    for (int h = 0; h < BK / 64; ++h) {
-      // 16-row blocks start at multiples of 16, where the swizzle of the block
-      // base is zero, so one lane offset serves every block
-      v4i fb[SR][4];
+    for (int t = 0; t < SR; ++t)
 #pragma unroll
-      for (int t = 0; t < SR; ++t)
+      for (int j = 0; j < 4; ++j)
+        fb[t][j] = *(const v4i*)(base + S * PLANE_A + t * PLANE_B + (wn * 64 + j * 16) * BK + foff[h]);
+  };
+  auto products_t = [&](int s, int t0, int t1, const v4i (&fa)[2], const v4i (&fb)[SR][4]) {
+#pragma unroll
+    for (int t = t0; t < t1; ++t)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          fb[t][j] = *(const v4i*)(base + (S + t) * PLANE + (wn * 64 + j * 16) * BK + foff[h]);
-      if constexpr (PF) {
-        // all fragments of this k half first: the reads complete in order, so
-        // the matrix-core work of digit s waits only for its own reads
-        v4i fa[S][2];
+          acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
+  };
+  auto products = [&](int s, const v4i (&fa)[2], const v4i (&fb)[SR][4]) {
 #pragma unroll
-        for (int s = 0; s < S; ++s)
+    for (int t = 0; t < SR; ++t)
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
-            fa[s][i] = *(const v4i*)(base + s * PLANE + (wm * 32 + i * 16) * BK + foff[h]);
-        // keep the scheduler from sinking the reads back between the products
-        __builtin_amdgcn_sched_barrier(0);
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int s = 0; s < S; ++s)
+        for (int j = 0; j < 4; ++j)
+          acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
+  };
+
+  if constexpr (PF == 2 && NST == 2 && BK == 128) {
+    // Split-step pipeline: the barrier sits inside the second k half of a
+    // step.  Before it a wave multiplies half 0 while reading half 1, then the
+    // first SR - DT rho digits of half 1; after it the wave multiplies the last
+    // DT rho digits of half 1 (fragments already in registers) while reading
+    // half 0 of the next stage, so the matrix cores have work while the fresh
+    // stage's first fragments are in flight.  DT is as large as the registers
+    // allow (the fragments held across the barrier are 2S + 4DT registers of
+    // 128 bits).
+    constexpr int DT = dt_of(S, SR);
+    v4i xa[S][2], xb[SR][4], ya[S][2], yb[SR][4];
+    issue(0);
+    wait_vm<0>();
+    lds_barrier();
+    if (nsteps > 1) issue(1);
+    read_b(sm, 0, xb);
 #pragma unroll
-          for (int t = 0; t < SR; ++t)
+    for (int s = 0; s < S; ++s) read_a(sm, 0, s, xa[s]);
+    for (int k = 0; k < nsteps; ++k) {
+      const int8_t* base = sm + (k & 1) * STAGE;
+      read_b(base, 1, yb);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+      for (int s = 0; s < S; ++s) read_a(base, 1, s, ya[s]);
 #pragma unroll
-              for (int j = 0; j < 4; ++j)
-                acc[s + t][i][j] =
-                    __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s][i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
-      } else {
+      for (int s = 0; s < S; ++s) products(s, xa[s], xb);
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          v4i fa[2];
+      for (int s = 0; s < S; ++s) products_t(s, 0, SR - DT, ya[s], yb);
+      // this wave's reads of stage k are complete before any wave may
+      // overwrite it; its own DMA of stage k + 1 has landed
+      wait_lgkm0();
+      wait_vm<0>();
+      lds_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      if (k + 2 < nsteps) issue(k + 2);
+      {
+        // (unconditional: after the last step this re-reads a stage that no
+        // DMA writes any more, and the values go unused; a branch here would
+        // stretch the fragments' live ranges over both paths)
+        const int8_t* next = sm + ((k + 1) & 1) * STAGE;
+        read_b(next, 0, xb);
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
-            fa[i] = *(const v4i*)(base + s * PLANE + (wm * 32 + i * 16) * BK + foff[h]);
+        for (int s = 0; s < S; ++s) read_a(next, 0, s, xa[s]);
+      }
 #pragma unroll
-          for (int t = 0; t < SR; ++t)
+      for (int s = 0; s < S; ++s) products_t(s, SR - DT, SR, ya[s], yb);
+    }
+  } else {
+    // Every step issues one DMA group; past the last k step the group re-loads
+    // the last step into the stage freed one step earlier (never read again),
+    // so the number of groups in flight after group k is always NST-2.
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+    for (int p = 0; p < NST - 1; ++p) issue(min(p, nsteps - 1));
+
+    for (int k = 0; k < nsteps; ++k) {
+      wait_vm<(NST - 2) * L>();
+      lds_barrier();
+      // (an explicit branch, not min(): it keeps the DMA issue in its own
+      // scheduling region, away from the matrix-core block)
+      if (k + NST - 1 < nsteps)
+        issue(k + NST - 1);
+      else
+        issue(nsteps - 1);
+
+      const int8_t* base = sm + (k % NST) * STAGE;
 #pragma unroll
-              for (int j = 0; j < 4; ++j)
-                acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
+      for (int h = 0; h < BK / 64; ++h) {
+        v4i fb[SR][4];
+        read_b(base, h, fb);
+        if constexpr (PF != 0) {
+          // all fragments of this k half first: the reads complete in order,
+          // so the matrix-core work of digit s waits only for its own reads
+          v4i fa[S][2];
+#pragma unroll
+          for (int s = 0; s < S; ++s) read_a(base, h, s, fa[s]);
+          // keep the scheduler from sinking the reads back between the products
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int s = 0; s < S; ++s) products(s, fa[s], fb);
+        } else {
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            v4i fa[2];
+            read_a(base, h, s, fa);
+            products(s, fa, fb);
+          }
         }
       }
     }
@@ -253,22 +333,32 @@ __global__ __launch_bounds__(NT, 1) void gemm_i8_kernel(GemmI8Args a, int tilesM
   }
 }
 
-// variant v: BK = 128 if v % 2 == 0 (falls back to 64 when two 128-byte stages
-// do not fit), else 64; MAP = (v / 2) % 2; PF = v >= 4
+// Variants 0-7 (8-wave workgroups, 128 x 128 tiles, one per compute unit):
+// BK = 128 if v % 2 == 0 (falls back to 64 when two 128-byte stages do not
+// fit), else 64; MAP = (v / 2) % 2; PF = v / 4 (fragment reads per digit, or all
+// up front).  Variants 8-9: split-step pipeline (PF = 2, BK = 128 where two
+// such stages fit, else as variant 4), MAP = v - 8.  Variants 10-11: 4-wave
+// workgroups with 64 x 128 tiles, two per compute unit (their barriers are
+// independent, so one workgroup's waits are covered by the other's products),
+// all fragments up front, BK = 128 where two stages fit in half the LDS, else
+// 64; MAP = v - 10.
 template <int S, int SR>
 constexpr int bk_of(int v) {
-  return (v % 2 == 0 && 2 * (S + SR) * 128 * 128 <= LDS_BYTES) ? 128 : 64;
+  if (v >= 10) return 2 * ((S * 64 + SR * 128) * 128) <= LDS_BYTES / 2 ? 128 : 64;
+  return ((v >= 8 || v % 2 == 0) && 2 * (S + SR) * 128 * 128 <= LDS_BYTES) ? 128 : 64;
 }
 
 template <int S, int SR, int V>
 hipError_t launch_v(const GemmI8Args& a, hipStream_t s) {
+  constexpr int NWV = V >= 10 ? 4 : 8;
   constexpr int BKV = bk_of<S, SR>(V);
-  constexpr int MAP = (V / 2) % 2;
-  constexpr bool PF = V >= 4;
-  const int tilesM = (int)(a.P / BM), tilesN = a.Rpad / BN;
+  constexpr int MAP = V >= 10 ? V - 10 : V >= 8 ? V - 8 : (V / 2) % 2;
+  constexpr int PF = V >= 10 ? 1 : V >= 8 ? 2 : V / 4;
+  using K = Cfg<S, SR, BKV, NWV>;
+  const int tilesM = (int)(a.P / K::BM), tilesN = a.Rpad / BN;
   const int T = tilesM * tilesN;
   const int grid = MAP == 0 ? ((T + 7) / 8) * 8 : T;
-  hipLaunchKernelGGL((gemm_i8_kernel<S, SR, BKV, MAP, PF>), dim3(grid), dim3(NT), 0, s, a, tilesM, tilesN);
+  hipLaunchKernelGGL((gemm_i8_kernel<S, SR, BKV, MAP, PF, NWV>), dim3(grid), dim3(K::NT), 0, s, a, tilesM, tilesN);
   return hipGetLastError();
 }
 
@@ -282,17 +372,21 @@ hipError_t launch_t(const GemmI8Args& a, hipStream_t s) {
     case 5: return launch_v<S, SR, 5>(a, s);
     case 6: return launch_v<S, SR, 6>(a, s);
     case 7: return launch_v<S, SR, 7>(a, s);
+    case 8: return launch_v<S, SR, 8>(a, s);
+    case 9: return launch_v<S, SR, 9>(a, s);
+    case 10: return launch_v<S, SR, 10>(a, s);
+    case 11: return launch_v<S, SR, 11>(a, s);
     default: return launch_v<S, SR, 0>(a, s);
   }
 }
 
 }  // namespace
 
-int gemm_i8_variants() { return 8; }
+int gemm_i8_variants() { return 12; }
 
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s) {
   if (a.nrhs <= 0) return hipSuccess;
-  if (a.P % 256 != 0 || a.Rpad % BN != 0) return hipErrorInvalidValue;
+  if (a.P % 256 != 0 || a.Rpad % BN != 0) return hipErrorInvalidValue;  // tiles cover P and Rpad exactly
   switch (a.S * 4 + a.SR) {
     case 1 * 4 + 1: return launch_t<1, 1>(a, s);
     case 1 * 4 + 2: return launch_t<1, 2>(a, s);
