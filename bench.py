@@ -198,7 +198,7 @@ def main():
             "algorithmic_ops_per_launch": ops, "avg_launch_ms": gi8_avg, "launches": gi8_n,
         },
         "roofline_fp64": {
-            "kernel": "gemm_f64_kernel<1,1>",
+            "kernel": "gemm_f64_nt_kernel<true>",
             "bound": "mfma", "achieved": ach_f64, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": ach_f64 / PEAK_FP64_TFLOPS,
             "traffic": _traffic("gemm_f64_quant_128.traffic.json", "paper_1602_00001_amd/csrc/gemm_f64.hip"),
