@@ -596,61 +596,120 @@ int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
     }
   }
   if (ops.empty()) return PINV_OK;
-  // column tables of all groups: input column pointers then output column pointers
-  std::vector<int64_t> first(ops.size()), count(ops.size());
-  std::vector<const void*> table;
-  for (size_t g = 0; g < ops.size(); ++g) {
-    first[g] = (int64_t)table.size();
+  const int ng = (int)ops.size();
+
+  // Every group of one digit count S runs in one grouped quantisation launch
+  // and one grouped product launch.  The product's kernel variant is that of
+  // the operator with the most work in the class.
+  std::vector<int64_t> first(ng), count(ng), Rpad(ng), xq_off(ng), f_off(ng);
+  std::vector<const void*> cols;
+  size_t xq_bytes = 0, f_bytes = 0;
+  for (int g = 0; g < ng; ++g) {
+    first[g] = (int64_t)cols.size();
     for (int i : members[ops[g]])
-      for (int j = 0; j < reqs[i].nrhs; ++j) table.push_back(reqs[i].rho + (int64_t)j * reqs[i].ld);
-    count[g] = (int64_t)table.size() - first[g];
+      for (int j = 0; j < reqs[i].nrhs; ++j) cols.push_back(reqs[i].rho + (int64_t)j * reqs[i].ld);
+    count[g] = (int64_t)cols.size() - first[g];
     for (int i : members[ops[g]])
-      for (int j = 0; j < reqs[i].nrhs; ++j) table.push_back(reqs[i].u + (int64_t)j * reqs[i].ld);
+      for (int j = 0; j < reqs[i].nrhs; ++j) cols.push_back(reqs[i].u + (int64_t)j * reqs[i].ld);
+    Rpad[g] = (count[g] + 127) / 128 * 128;
+    xq_off[g] = (int64_t)xq_bytes;
+    xq_bytes += (size_t)SR * Rpad[g] * ops[g]->P;
+    f_off[g] = (int64_t)f_bytes;
+    f_bytes += (size_t)Rpad[g] * sizeof(int32_t);
   }
+  auto align16 = [](size_t b) { return (b + 15) / 16 * 16; };
+  const size_t cols_bytes = align16(cols.size() * sizeof(void*));
+  const size_t qg_bytes = align16(ng * sizeof(QuantColsGroup));
+  const size_t gg_bytes = align16(ng * sizeof(GemmI8Group));
+  const size_t table_bytes = cols_bytes + qg_bytes + gg_bytes;
+  const size_t scratch_bytes = align16(xq_bytes) + f_bytes;
+
   hipStream_t s = as_stream(stream);
   configure_pool_once();
-  void* dtable = nullptr;
-  PINV_HIP_TRY(hipMallocAsync(&dtable, table.size() * sizeof(void*), s));
-  hipError_t e = hipMemcpyAsync(dtable, table.data(), table.size() * sizeof(void*), hipMemcpyHostToDevice, s);
-  // the host table must outlive the copy
+  char* dtable = nullptr;
+  char* scratch = nullptr;
+  PINV_HIP_TRY(hipMallocAsync((void**)&dtable, table_bytes, s));
+  hipError_t e = hipMallocAsync((void**)&scratch, scratch_bytes, s);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(dtable, s);
+    return pinv_hip_status(e);
+  }
+  const void* const* dcols = (const void* const*)dtable;
+  int8_t* Xq = (int8_t*)scratch;
+  int32_t* F = (int32_t*)(scratch + align16(xq_bytes));
+
+  // host image of the tables, groups ordered by digit count
+  std::vector<char> host(table_bytes, 0);
+  std::memcpy(host.data(), cols.data(), cols.size() * sizeof(void*));
+  QuantColsGroup* hq = (QuantColsGroup*)(host.data() + cols_bytes);
+  GemmI8Group* hg = (GemmI8Group*)(host.data() + cols_bytes + qg_bytes);
+  struct Launch { int S, g0, ng, cols, tiles, variant; };
+  std::vector<Launch> launches;
+  int slot = 0;
+  for (int S = 1; S <= 3; ++S) {
+    Launch L{S, slot, 0, 0, 0, 0};
+    double most = -1.0;
+    for (int g = 0; g < ng; ++g)
+      if (ops[g]->S == S) {
+        const double work = (double)ops[g]->P * ops[g]->P * Rpad[g];
+        if (work > most) {
+          most = work;
+          L.variant = ops[g]->i8_variant[SR];
+        }
+      }
+    const int rows = gemm_i8_tile_rows(L.variant);
+    for (int g = 0; g < ng; ++g) {
+      if (ops[g]->S != S) continue;
+      pinv_op op = ops[g];
+      QuantColsGroup& q = hq[slot];
+      q.xcols = (const double* const*)(dcols + first[g]);
+      q.Xq = Xq + xq_off[g];
+      q.f = (int32_t*)((char*)F + f_off[g]);
+      q.P = op->P;
+      q.n = op->n;
+      q.nrhs = (int)count[g];
+      q.Rpad = (int)Rpad[g];
+      q.col0 = L.cols;
+      GemmI8Group& G = hg[slot];
+      G.a.Q = op->Q; G.a.S = op->S;
+      G.a.X = q.Xq; G.a.SR = SR;
+      G.a.P = op->P; G.a.Rpad = (int)Rpad[g];
+      G.a.n = op->n; G.a.nrhs = (int)count[g];
+      G.a.row_exp = op->e;
+      G.a.col_exp = q.f;
+      G.a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
+      G.a.w = op->w;
+      G.a.U = nullptr; G.a.ldu = 0;
+      G.a.ucols = (double* const*)(dcols + first[g] + count[g]);
+      G.tilesM = (int)(op->P / rows);
+      G.tilesN = (int)(Rpad[g] / 128);
+      G.tile0 = L.tiles;
+      L.cols += (int)Rpad[g];
+      L.tiles += G.tilesM * G.tilesN;
+      ++L.ng;
+      ++slot;
+    }
+    if (L.ng) launches.push_back(L);
+  }
+  e = hipMemcpyAsync(dtable, host.data(), table_bytes, hipMemcpyHostToDevice, s);
+  // the host image must outlive the copy
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  for (size_t g = 0; g < ops.size() && e == hipSuccess; ++g) {
-    pinv_op op = ops[g];
-    const int R = (int)count[g];
-    const int Rpad = (R + 127) / 128 * 128;
-    const size_t xq_bytes = (size_t)SR * Rpad * op->P;
-    void* scratch = nullptr;
-    e = hipMallocAsync(&scratch, xq_bytes + (size_t)Rpad * sizeof(int32_t), s);
+  const QuantColsGroup* dq = (const QuantColsGroup*)(dtable + cols_bytes);
+  const GemmI8Group* dg = (const GemmI8Group*)(dtable + cols_bytes + qg_bytes);
+  for (const Launch& L : launches) {
     if (e != hipSuccess) break;
-    int8_t* Xq = (int8_t*)scratch;
-    int32_t* f = (int32_t*)((char*)scratch + xq_bytes);
-    const void* const* dt = (const void* const*)dtable;
     {
       TraceScope ts("quantize_cols", s);
-      e = launch_quantize_cols(nullptr, 0, (const double* const*)(dt + first[g]), op->n, R, Rpad, SR, op->P, nullptr,
-                               Xq, f, s);
+      e = launch_quantize_cols_grouped(dq + L.g0, L.ng, L.cols, SR, s);
     }
-    if (e == hipSuccess) {
-      TraceScope ts("gemm_i8", s);
-      GemmI8Args a{};
-      a.Q = op->Q; a.S = op->S;
-      a.X = Xq; a.SR = SR;
-      a.P = op->P; a.Rpad = Rpad;
-      a.n = op->n; a.nrhs = R;
-      a.row_exp = op->e;
-      a.col_exp = f;
-      a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
-      a.w = op->w;
-      a.U = nullptr; a.ldu = 0;
-      a.ucols = (double* const*)(dt + first[g] + count[g]);
-      a.variant = op->i8_variant[SR];
-      e = launch_gemm_i8(a, s);
-    }
-    const hipError_t e2 = hipFreeAsync(scratch, s);
-    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) break;
+    TraceScope ts("gemm_i8", s);
+    e = launch_gemm_i8_grouped(dg + L.g0, L.ng, L.tiles, L.S, SR, L.variant, s);
   }
+  const hipError_t e2 = hipFreeAsync(scratch, s);
   const hipError_t e3 = hipFreeAsync(dtable, s);
   if (e != hipSuccess) return pinv_hip_status(e);
+  if (e2 != hipSuccess) return pinv_hip_status(e2);
   return pinv_hip_status(e3);
 }
 

@@ -145,6 +145,31 @@ struct GemmI8Args {
 };
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s);
 int gemm_i8_variants();
+
+// Grouped int8 product: several operators (same S and SR) in one launch.
+// Group g owns global tiles [tile0, tile0 + tilesM*tilesN) of the launch, tiles
+// of gemm_i8_tile_rows(variant) rows x 128 right-hand sides; a.variant is
+// ignored (the launch's variant applies to every group).
+struct GemmI8Group {
+  GemmI8Args a;
+  int tilesM, tilesN;
+  int tile0;
+  int _pad;
+};
+int gemm_i8_tile_rows(int variant);
+hipError_t launch_gemm_i8_grouped(const GemmI8Group* d_groups, int ngroups, int total_tiles, int S, int SR,
+                                  int variant, hipStream_t s);
+
+// Grouped rho quantisation: workgroups [col0, col0 + Rpad) serve group g.
+struct QuantColsGroup {
+  const double* const* xcols;   // nrhs column pointers
+  int8_t* Xq;                   // [SR][Rpad][P]
+  int32_t* f;                   // [Rpad]
+  int64_t P;
+  int n, nrhs, Rpad, col0;
+};
+hipError_t launch_quantize_cols_grouped(const QuantColsGroup* groups, int ngroups, int total_cols, int SR,
+                                        hipStream_t s);
 hipError_t launch_fill_random_i8(int8_t* p, size_t n, uint32_t seed, hipStream_t s);
 
 // ---- split precision ----------------------------------------------------------

@@ -41,14 +41,13 @@ namespace {
 constexpr int BN = 128;               // right-hand sides per tile
 constexpr int LDS_BYTES = 163840;     // per compute unit
 
+// Tile processed by workgroup bid out of T: MAP 0 hands XCD x (workgroups
+// x, x+8, ...) a contiguous range of tiles, so tiles sharing a row block of G
+// share that XCD's L2; MAP 1 is linear.
 template <int MAP>
-__device__ inline void tile_of(int bid, int tilesM, int tilesN, int& mt, int& nt, bool& valid) {
-  const int T = tilesM * tilesN;
+__device__ inline int tile_index(int bid, int T) {
   const int per = (T + 7) / 8;
-  const int tile = MAP == 0 ? (bid % 8) * per + bid / 8 : bid;
-  valid = tile < T;
-  mt = valid ? tile / tilesN : 0;
-  nt = valid ? tile % tilesN : 0;
+  return MAP == 0 ? (bid % 8) * per + bid / 8 : bid;
 }
 
 // s_waitcnt with only the vector-memory counter constrained (<= V)
@@ -108,18 +107,34 @@ __device__ inline int swz(int row, int c) {
 }
 
 template <int S, int SR, int BKV, int MAP, int PF, int NWV>
-__global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(GemmI8Args a, int tilesM,
-                                                                         int tilesN) {
+__global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(GemmI8Args a_in, int tilesM, int tilesN,
+                                                                         const GemmI8Group* __restrict__ groups,
+                                                                         int ngroups, int total) {
   using K = Cfg<S, SR, BKV, NWV>;
   constexpr int C = K::C, BK = K::BK, CH = K::CH, STAGE = K::STAGE, NST = K::NST;
   constexpr int BM = K::BM, NW = K::NW, PLANE_A = K::PLANE_A, PLANE_B = K::PLANE_B;
   constexpr int RPI = K::RPI, IPA = K::IPA, IPB = K::IPB, L = K::L;
   __shared__ __attribute__((aligned(1024))) int8_t sm[NST * STAGE];
 
-  int mt, nt;
-  bool valid;
-  tile_of<MAP>(blockIdx.x, tilesM, tilesN, mt, nt, valid);
-  if (!valid) return;
+  // tile of this workgroup; in a grouped launch, also its group (binary
+  // search over the groups' first tiles, uniform per workgroup) and the
+  // group's arguments
+  GemmI8Args a = a_in;
+  int tN = tilesN;
+  const int T = groups ? total : tilesM * tilesN;
+  int tile = tile_index<MAP>(blockIdx.x, T);
+  if (tile >= T) return;
+  if (groups) {
+    int lo = 0, hi = ngroups - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (groups[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    }
+    a = groups[lo].a;
+    tN = groups[lo].tilesN;
+    tile -= groups[lo].tile0;
+  }
+  const int mt = tile / tN, nt = tile % tN;
   const int m0 = mt * BM, n0 = nt * BN;
   const int64_t P = a.P;
   const int nsteps = (int)(P / BK);
@@ -349,34 +364,51 @@ constexpr int bk_of(int v) {
 }
 
 template <int S, int SR, int V>
-hipError_t launch_v(const GemmI8Args& a, hipStream_t s) {
+hipError_t launch_v(const GemmI8Args& a, const GemmI8Group* groups, int ngroups, int total, hipStream_t s) {
   constexpr int NWV = V >= 10 ? 4 : 8;
   constexpr int BKV = bk_of<S, SR>(V);
   constexpr int MAP = V >= 10 ? V - 10 : V >= 8 ? V - 8 : (V / 2) % 2;
   constexpr int PF = V >= 10 ? 1 : V >= 8 ? 2 : V / 4;
   using K = Cfg<S, SR, BKV, NWV>;
-  const int tilesM = (int)(a.P / K::BM), tilesN = a.Rpad / BN;
-  const int T = tilesM * tilesN;
+  const int tilesM = groups ? 0 : (int)(a.P / K::BM), tilesN = groups ? 0 : a.Rpad / BN;
+  const int T = groups ? total : tilesM * tilesN;
   const int grid = MAP == 0 ? ((T + 7) / 8) * 8 : T;
-  hipLaunchKernelGGL((gemm_i8_kernel<S, SR, BKV, MAP, PF, NWV>), dim3(grid), dim3(K::NT), 0, s, a, tilesM, tilesN);
+  hipLaunchKernelGGL((gemm_i8_kernel<S, SR, BKV, MAP, PF, NWV>), dim3(grid), dim3(K::NT), 0, s, a, tilesM, tilesN,
+                     groups, ngroups, total);
   return hipGetLastError();
 }
 
 template <int S, int SR>
-hipError_t launch_t(const GemmI8Args& a, hipStream_t s) {
-  switch (a.variant) {
-    case 1: return launch_v<S, SR, 1>(a, s);
-    case 2: return launch_v<S, SR, 2>(a, s);
-    case 3: return launch_v<S, SR, 3>(a, s);
-    case 4: return launch_v<S, SR, 4>(a, s);
-    case 5: return launch_v<S, SR, 5>(a, s);
-    case 6: return launch_v<S, SR, 6>(a, s);
-    case 7: return launch_v<S, SR, 7>(a, s);
-    case 8: return launch_v<S, SR, 8>(a, s);
-    case 9: return launch_v<S, SR, 9>(a, s);
-    case 10: return launch_v<S, SR, 10>(a, s);
-    case 11: return launch_v<S, SR, 11>(a, s);
-    default: return launch_v<S, SR, 0>(a, s);
+hipError_t launch_t(const GemmI8Args& a, int variant, const GemmI8Group* g, int ng, int tot, hipStream_t s) {
+  switch (variant) {
+    case 1: return launch_v<S, SR, 1>(a, g, ng, tot, s);
+    case 2: return launch_v<S, SR, 2>(a, g, ng, tot, s);
+    case 3: return launch_v<S, SR, 3>(a, g, ng, tot, s);
+    case 4: return launch_v<S, SR, 4>(a, g, ng, tot, s);
+    case 5: return launch_v<S, SR, 5>(a, g, ng, tot, s);
+    case 6: return launch_v<S, SR, 6>(a, g, ng, tot, s);
+    case 7: return launch_v<S, SR, 7>(a, g, ng, tot, s);
+    case 8: return launch_v<S, SR, 8>(a, g, ng, tot, s);
+    case 9: return launch_v<S, SR, 9>(a, g, ng, tot, s);
+    case 10: return launch_v<S, SR, 10>(a, g, ng, tot, s);
+    case 11: return launch_v<S, SR, 11>(a, g, ng, tot, s);
+    default: return launch_v<S, SR, 0>(a, g, ng, tot, s);
+  }
+}
+
+hipError_t dispatch(int S, int SR, const GemmI8Args& a, int variant, const GemmI8Group* g, int ng, int tot,
+                    hipStream_t s) {
+  switch (S * 4 + SR) {
+    case 1 * 4 + 1: return launch_t<1, 1>(a, variant, g, ng, tot, s);
+    case 1 * 4 + 2: return launch_t<1, 2>(a, variant, g, ng, tot, s);
+    case 1 * 4 + 3: return launch_t<1, 3>(a, variant, g, ng, tot, s);
+    case 2 * 4 + 1: return launch_t<2, 1>(a, variant, g, ng, tot, s);
+    case 2 * 4 + 2: return launch_t<2, 2>(a, variant, g, ng, tot, s);
+    case 2 * 4 + 3: return launch_t<2, 3>(a, variant, g, ng, tot, s);
+    case 3 * 4 + 1: return launch_t<3, 1>(a, variant, g, ng, tot, s);
+    case 3 * 4 + 2: return launch_t<3, 2>(a, variant, g, ng, tot, s);
+    case 3 * 4 + 3: return launch_t<3, 3>(a, variant, g, ng, tot, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -384,19 +416,18 @@ hipError_t launch_t(const GemmI8Args& a, hipStream_t s) {
 
 int gemm_i8_variants() { return 12; }
 
+int gemm_i8_tile_rows(int variant) { return variant >= 10 ? 64 : 128; }
+
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s) {
   if (a.nrhs <= 0) return hipSuccess;
   if (a.P % 256 != 0 || a.Rpad % BN != 0) return hipErrorInvalidValue;  // tiles cover P and Rpad exactly
-  switch (a.S * 4 + a.SR) {
-    case 1 * 4 + 1: return launch_t<1, 1>(a, s);
-    case 1 * 4 + 2: return launch_t<1, 2>(a, s);
-    case 1 * 4 + 3: return launch_t<1, 3>(a, s);
-    case 2 * 4 + 1: return launch_t<2, 1>(a, s);
-    case 2 * 4 + 2: return launch_t<2, 2>(a, s);
-    case 2 * 4 + 3: return launch_t<2, 3>(a, s);
-    case 3 * 4 + 1: return launch_t<3, 1>(a, s);
-    case 3 * 4 + 2: return launch_t<3, 2>(a, s);
-    case 3 * 4 + 3: return launch_t<3, 3>(a, s);
-    default: return hipErrorInvalidValue;
-  }
+  return dispatch(a.S, a.SR, a, a.variant, nullptr, 0, 0, s);
+}
+
+hipError_t launch_gemm_i8_grouped(const GemmI8Group* d_groups, int ngroups, int total_tiles, int S, int SR,
+                                  int variant, hipStream_t s) {
+  if (ngroups <= 0 || total_tiles <= 0) return hipSuccess;
+  if (!d_groups || variant < 0 || variant >= gemm_i8_variants()) return hipErrorInvalidValue;
+  GemmI8Args none{};
+  return dispatch(S, SR, none, variant, d_groups, ngroups, total_tiles, s);
 }

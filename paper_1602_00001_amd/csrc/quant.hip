@@ -114,20 +114,15 @@ __global__ __launch_bounds__(256) void transpose_planes_kernel(const int8_t* __r
   *(v4i*)(dst + (bk * 64 + r) * P + bi * 64 + c) = ov;
 }
 
-// One workgroup per column r of X (column-major n x nrhs, stride ldx); rows of
-// the output [SR][Rpad][P]; columns r >= nrhs are written as zeros.  Each
-// thread handles 4 consecutive k per pass (32-byte reads, 4-byte writes per
-// digit plane), so both the reads and the writes of a wave are contiguous.
+// One workgroup per column r of X (column-major n x nrhs, stride ldx): the
+// exponent of its largest magnitude, then its rows of the output
+// [SR][Rpad][P] (rows n..P-1 and columns r >= nrhs are written as zeros).
+// Each thread handles 4 consecutive k per pass (32-byte reads, 4-byte writes
+// per digit plane), so both the reads and the writes of a wave are contiguous.
 template <int SR>
-__global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __restrict__ X, int64_t ldx,
-                                                           const double* const* __restrict__ xcols, int n,
-                                                           int nrhs, int Rpad, int64_t P,
-                                                           const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
-                                                           int32_t* __restrict__ f) {
-  __shared__ double red[4];
-  const int r = blockIdx.x;
-  const bool live = r < nrhs;
-  const double* x = live ? (xcols ? xcols[r] : X + (int64_t)r * ldx) : X;
+__device__ inline void quantize_col(const double* __restrict__ x, bool live, int n, int r, int Rpad, int64_t P,
+                                    const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
+                                    int32_t* __restrict__ f, double* red) {
   double m = 0.0;
   if (live)
     for (int k = threadIdx.x; k < n; k += 256) {
@@ -162,6 +157,38 @@ __global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __rest
   }
 }
 
+template <int SR>
+__global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __restrict__ X, int64_t ldx,
+                                                           const double* const* __restrict__ xcols, int n,
+                                                           int nrhs, int Rpad, int64_t P,
+                                                           const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
+                                                           int32_t* __restrict__ f) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  const bool live = r < nrhs;
+  const double* x = live ? (xcols ? xcols[r] : X + (int64_t)r * ldx) : X;
+  quantize_col<SR>(x, live, n, r, Rpad, P, pre, Xq, f, red);
+}
+
+// Grouped form: workgroup b serves group g with g.col0 <= b < next group's
+// col0 (binary search over the table, uniform per workgroup).
+template <int SR>
+__global__ __launch_bounds__(256) void quantize_cols_grouped_kernel(const QuantColsGroup* __restrict__ groups,
+                                                                   int ngroups) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  int lo = 0, hi = ngroups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].col0 <= b) lo = mid; else hi = mid - 1;
+  }
+  const QuantColsGroup g = groups[lo];
+  const int r = b - g.col0;
+  const bool live = r < g.nrhs;
+  const double* x = live ? g.xcols[r] : nullptr;
+  quantize_col<SR>(x, live, g.n, r, g.Rpad, g.P, nullptr, g.Xq, g.f, red);
+}
+
 __global__ void fill_random_i8_kernel(int8_t* __restrict__ p, size_t n, uint32_t seed) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -180,6 +207,19 @@ hipError_t launch_fill_random_i8(int8_t* p, size_t n, uint32_t seed, hipStream_t
 }
 
 int64_t pinv_max_mag(int S) { return 127LL * ((1LL << (8 * S)) - 1) / 255; }
+
+hipError_t launch_quantize_cols_grouped(const QuantColsGroup* groups, int ngroups, int total_cols, int SR,
+                                        hipStream_t s) {
+  if (ngroups <= 0 || total_cols <= 0) return hipSuccess;
+  const dim3 grid((unsigned)total_cols);
+  switch (SR) {
+    case 1: hipLaunchKernelGGL(quantize_cols_grouped_kernel<1>, grid, dim3(256), 0, s, groups, ngroups); break;
+    case 2: hipLaunchKernelGGL(quantize_cols_grouped_kernel<2>, grid, dim3(256), 0, s, groups, ngroups); break;
+    case 3: hipLaunchKernelGGL(quantize_cols_grouped_kernel<3>, grid, dim3(256), 0, s, groups, ngroups); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_quantize_rows(const double* G, int64_t ldg, int n, int S, int64_t P, int8_t* Q, int32_t* e,
                                 hipStream_t s) {

@@ -1,7 +1,9 @@
 """Batched uneven requests: pinv_apply_batched equals one pinv_apply_inverse per
 request, bit for bit in INT8 mode (the grouping only changes which columns share
 a launch; every column's quantisation and integer product are independent),
-and the per-request results match the oracle."""
+and the per-request results match the oracle.  The operators carry different
+inverse precisions (8/16/24-bit: one grouped launch per digit count) and
+different int8 kernel variants."""
 
 import numpy as np
 import pytest
@@ -24,21 +26,26 @@ def pinv():
     return p
 
 
-GRIDS = [(12, 9), (20, 20), (33, 17), (40, 40)]
+GRIDS = [(12, 9), (20, 20), (33, 17), (40, 40), (25, 30)]
+BITS = [16, 24, 8, 16, 24]
+VARIANTS = [None, 10, None, 8, 3]
 
 
 @pytest.fixture(scope="module")
 def ops(torch, pinv):
     g = np.random.default_rng(40)
     out = []
-    for (nx, ny) in GRIDS:
+    for (nx, ny), bits, var in zip(GRIDS, BITS, VARIANTS):
         eps = workloads.random_eps(nx, ny, g)
         ub = g.standard_normal((ny, nx)) if nx == 20 else None
         h = 1.0 / (max(nx, ny) - 1)
         G, w, _ = oracle_inverse(nx, ny, eps, ub)
         op = pinv.PoissonInverse.from_inverse(nx, ny, h, G, eps, ub, w)
-        op.quantize(16)
-        out.append(dict(op=op, G=G, w=w, h=h))
+        op.quantize(bits)
+        if var is not None:
+            for rb in (8, 16, 24):
+                op.set_int8_variant(rb, var)
+        out.append(dict(op=op, G=G, w=w, h=h, S=bits // 8))
     yield out
     for o in out:
         o["op"].close()
@@ -61,8 +68,8 @@ def _requests(torch, ops, seed, nreq=40):
 
 @pytest.mark.parametrize("rho_bits", [8, 16, 24])
 def test_batched_int8_equals_per_request(torch, pinv, ops, rho_bits):
-    announce(f"apply_batched int8 rho_bits={rho_bits} 40 requests over {len(GRIDS)} ops")
-    reqs = _requests(torch, ops, 100 + rho_bits)
+    announce(f"apply_batched int8 rho_bits={rho_bits} 60 requests over {len(GRIDS)} ops")
+    reqs = _requests(torch, ops, 100 + rho_bits, 60)
     pinv.apply_batched([(ops[k]["op"], rho, u) for (k, rho, u, _) in reqs], "int8", rho_bits)
     for (k, rho, u, rho_h) in reqs:
         if rho.shape[0] == 0:
@@ -75,9 +82,9 @@ def test_batched_int8_equals_per_request(torch, pinv, ops, rho_bits):
         if not mine:
             continue
         _, _, u, rho_h = mine[0]
-        qG, e = quant.quantize_rows(o["G"], 2)
+        qG, e = quant.quantize_rows(o["G"], o["S"])
         qR, f = quant.quantize_cols(rho_h.T, rho_bits // 8)
-        ref, _ = apply.integer_apply(qG, e, 2, qR, f, rho_bits // 8, o["h"], o["w"])
+        ref, _ = apply.integer_apply(qG, e, o["S"], qR, f, rho_bits // 8, o["h"], o["w"])
         assert np.array_equal(host(u).T, ref)
 
 
