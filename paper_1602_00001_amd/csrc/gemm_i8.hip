@@ -90,10 +90,12 @@ struct Cfg {
 
 // rho digits whose half-step products are deferred past the barrier in the
 // split-step pipeline: registers per lane ~ 32 C (accumulators) + 4 (2S + 4SR)
-// (fragments being read) + 4 (2S + 4DT) (fragments held) + 24 <= 256
-constexpr int dt_of(int S, int SR) {
+// (fragments being read) + 4 (2S + 4DT) (fragments held) + misc <= 256
+// (misc = registers for addresses and loop state: 8 when the compiler
+// schedules freely, 24 with the order pinned)
+constexpr int dt_of(int S, int SR, int misc) {
   int dt = SR;
-  while (dt > 1 && 32 * (S + SR - 1) + 4 * (2 * S + 4 * SR) + 4 * (2 * S + 4 * dt) + 24 > 256) --dt;
+  while (dt > 1 && 32 * (S + SR - 1) + 4 * (2 * S + 4 * SR) + 4 * (2 * S + 4 * dt) + misc > 256) --dt;
   return dt;
 }
 
@@ -165,7 +167,10 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
 
   auto issue = [&](int step) {
     int8_t* dst = sm + (step % NST) * STAGE;
-    const int64_t k0 = (int64_t)step * BK;
+    // (through readfirstlane, so the compiler keeps one scalar base per plane
+    // and a 32-bit lane offset instead of strength-reducing every DMA address
+    // into a 64-bit vector register)
+    const int64_t k0 = (int64_t)__builtin_amdgcn_readfirstlane(step * BK);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int8_t* b = tileA + s * planeA + k0;
@@ -206,6 +211,13 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
 #pragma unroll
     for (int i = 0; i < 2; ++i) fa[i] = *(const v4i*)(base + s * PLANE_A + (wm * 32 + i * 16) * BK + foff[h]);
   };
+  auto read_b_t = [&](const int8_t* base, int h, int t0, int t1, v4i (&fb)[SR][4]) {
+#pragma unroll
+    for (int t = t0; t < t1; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        fb[t][j] = *(const v4i*)(base + S * PLANE_A + t * PLANE_B + (wn * 64 + j * 16) * BK + foff[h]);
+  };
   auto read_b = [&](const int8_t* base, int h, v4i (&fb)[SR][4]) {
 #pragma unroll
     for (int t = 0; t < SR; ++t)
@@ -232,7 +244,7 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
           acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
   };
 
-  if constexpr (PF == 2 && NST == 2 && BK == 128) {
+  if constexpr (PF >= 2 && NST == 2 && BK == 128) {
     // Split-step pipeline: the barrier sits inside the second k half of a
     // step.  Before it a wave multiplies half 0 while reading half 1, then the
     // first SR - DT rho digits of half 1; after it the wave multiplies the last
@@ -241,7 +253,7 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
     // stage's first fragments are in flight.  DT is as large as the registers
     // allow (the fragments held across the barrier are 2S + 4DT registers of
     // 128 bits).
-    constexpr int DT = dt_of(S, SR);
+    constexpr int DT = dt_of(S, SR, PF == 3 ? 24 : 8);
     v4i xa[S][2], xb[SR][4], ya[S][2], yb[SR][4];
     issue(0);
     wait_vm<0>();
@@ -252,11 +264,27 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
     for (int s = 0; s < S; ++s) read_a(sm, 0, s, xa[s]);
     for (int k = 0; k < nsteps; ++k) {
       const int8_t* base = sm + (k & 1) * STAGE;
-      read_b(base, 1, yb);
+      if constexpr (PF == 3) {
+        // order pinned: half 1's rho fragments first, then after the products
+        // of each G digit of half 0 the reads of that digit for half 1 (into
+        // registers it has just freed), so every read has a digit's products
+        // to hide behind and no more than one and a half fragment sets live
+        read_b(base, 1, yb);
 #pragma unroll
-      for (int s = 0; s < S; ++s) read_a(base, 1, s, ya[s]);
+        for (int s = 0; s < S; ++s) {
+          __builtin_amdgcn_sched_barrier(0);
+          products(s, xa[s], xb);
+          __builtin_amdgcn_sched_barrier(0);
+          read_a(base, 1, s, ya[s]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        read_b(base, 1, yb);
 #pragma unroll
-      for (int s = 0; s < S; ++s) products(s, xa[s], xb);
+        for (int s = 0; s < S; ++s) read_a(base, 1, s, ya[s]);
+#pragma unroll
+        for (int s = 0; s < S; ++s) products(s, xa[s], xb);
+      }
 #pragma unroll
       for (int s = 0; s < S; ++s) products_t(s, 0, SR - DT, ya[s], yb);
       // this wave's reads of stage k are complete before any wave may
@@ -266,17 +294,32 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
       lds_barrier();
       __builtin_amdgcn_sched_barrier(0);
       if (k + 2 < nsteps) issue(k + 2);
-      {
-        // (unconditional: after the last step this re-reads a stage that no
-        // DMA writes any more, and the values go unused; a branch here would
-        // stretch the fragments' live ranges over both paths)
-        const int8_t* next = sm + ((k + 1) & 1) * STAGE;
+      // (the reads of the next stage are unconditional: after the last step
+      // they re-read a stage that no DMA writes any more, and the values go
+      // unused; a branch here would stretch the fragments' live ranges over
+      // both paths)
+      const int8_t* next = sm + ((k + 1) & 1) * STAGE;
+      if constexpr (PF == 3) {
+        // order pinned: the rho fragments whose registers are already free,
+        // then after the deferred products of each G digit that digit's next
+        // fragments (into the registers just freed), the rest of rho last
+        read_b_t(next, 0, 0, SR - DT, xb);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          __builtin_amdgcn_sched_barrier(0);
+          products_t(s, SR - DT, SR, ya[s], yb);
+          __builtin_amdgcn_sched_barrier(0);
+          read_a(next, 0, s, xa[s]);
+        }
+        read_b_t(next, 0, SR - DT, SR, xb);
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
         read_b(next, 0, xb);
 #pragma unroll
         for (int s = 0; s < S; ++s) read_a(next, 0, s, xa[s]);
-      }
 #pragma unroll
-      for (int s = 0; s < S; ++s) products_t(s, SR - DT, SR, ya[s], yb);
+        for (int s = 0; s < S; ++s) products_t(s, SR - DT, SR, ya[s], yb);
+      }
     }
   } else {
     // Every step issues one DMA group; past the last k step the group re-loads
@@ -356,19 +399,21 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
 // workgroups with 64 x 128 tiles, two per compute unit (their barriers are
 // independent, so one workgroup's waits are covered by the other's products),
 // all fragments up front, BK = 128 where two stages fit in half the LDS, else
-// 64; MAP = v - 10.
+// 64; MAP = v - 10.  Variant 12: the split-step pipeline with its instruction
+// order pinned (PF = 3), XCD order.
 template <int S, int SR>
 constexpr int bk_of(int v) {
+  if (v == 12) return 2 * (S + SR) * 128 * 128 <= LDS_BYTES ? 128 : 64;
   if (v >= 10) return 2 * ((S * 64 + SR * 128) * 128) <= LDS_BYTES / 2 ? 128 : 64;
   return ((v >= 8 || v % 2 == 0) && 2 * (S + SR) * 128 * 128 <= LDS_BYTES) ? 128 : 64;
 }
 
 template <int S, int SR, int V>
 hipError_t launch_v(const GemmI8Args& a, const GemmI8Group* groups, int ngroups, int total, hipStream_t s) {
-  constexpr int NWV = V >= 10 ? 4 : 8;
+  constexpr int NWV = (V == 10 || V == 11) ? 4 : 8;
   constexpr int BKV = bk_of<S, SR>(V);
-  constexpr int MAP = V >= 10 ? V - 10 : V >= 8 ? V - 8 : (V / 2) % 2;
-  constexpr int PF = V >= 10 ? 1 : V >= 8 ? 2 : V / 4;
+  constexpr int MAP = V == 12 ? 0 : V >= 10 ? V - 10 : V >= 8 ? V - 8 : (V / 2) % 2;
+  constexpr int PF = V == 12 ? 3 : V >= 10 ? 1 : V >= 8 ? 2 : V / 4;
   using K = Cfg<S, SR, BKV, NWV>;
   const int tilesM = groups ? 0 : (int)(a.P / K::BM), tilesN = groups ? 0 : a.Rpad / BN;
   const int T = groups ? total : tilesM * tilesN;
@@ -392,6 +437,7 @@ hipError_t launch_t(const GemmI8Args& a, int variant, const GemmI8Group* g, int 
     case 9: return launch_v<S, SR, 9>(a, g, ng, tot, s);
     case 10: return launch_v<S, SR, 10>(a, g, ng, tot, s);
     case 11: return launch_v<S, SR, 11>(a, g, ng, tot, s);
+    case 12: return launch_v<S, SR, 12>(a, g, ng, tot, s);
     default: return launch_v<S, SR, 0>(a, g, ng, tot, s);
   }
 }
@@ -414,9 +460,9 @@ hipError_t dispatch(int S, int SR, const GemmI8Args& a, int variant, const GemmI
 
 }  // namespace
 
-int gemm_i8_variants() { return 12; }
+int gemm_i8_variants() { return 13; }
 
-int gemm_i8_tile_rows(int variant) { return variant >= 10 ? 64 : 128; }
+int gemm_i8_tile_rows(int variant) { return (variant == 10 || variant == 11) ? 64 : 128; }
 
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s) {
   if (a.nrhs <= 0) return hipSuccess;
