@@ -313,26 +313,42 @@ __global__ __launch_bounds__(256) void gemv_f64_kernel(const double* __restrict_
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   const double* g = G + (int64_t)row * ldg;
-  double s[NR];
+  // four independent partial sums per right-hand side, so the loads of four
+  // k blocks are in flight together (the row is short at small grids and the
+  // loop would otherwise wait for each load in turn)
+  constexpr int U = 4;
+  double s[U][NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) s[r] = 0.0;
-  for (int k = lane; k < n; k += 64) {
+  for (int q = 0; q < U; ++q)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s[q][r] = 0.0;
+  int k = lane;
+  for (; k + 64 * (U - 1) < n; k += 64 * U) {
+    double gv[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) gv[q] = g[k + 64 * q];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) s[q][r] = fma(gv[q], x[(int64_t)r * ldx + k + 64 * q], s[q][r]);
+  }
+  for (; k < n; k += 64) {
     const double gv = g[k];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) s[r] = fma(gv, x[(int64_t)r * ldx + k], s[r]);
+    for (int r = 0; r < NR; ++r) s[0][r] = fma(gv, x[(int64_t)r * ldx + k], s[0][r]);
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    double v = s[r];
+    double v = ((s[0][r] + s[1][r]) + s[2][r]) + s[3][r];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    s[r] = v;
+    s[0][r] = v;
   }
   if (lane < NR) {
     double v = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-      if (r == lane) v = s[r];
+      if (r == lane) v = s[0][r];
     v = alpha * v;
     if (bias) v += bias[row];
     u[(int64_t)lane * ldu + row] = v;
