@@ -178,11 +178,15 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
                    const double* X, int64_t ldx, int nrhs, const double* w, double* U, int64_t ldu,
                    hipStream_t s) {
   const int Rpad = (nrhs + 127) / 128 * 128;
+  const int variant = op->i8_variant[SR];
+  int ksplit = 1, kchunk = (int)op->P;
+  gemm_i8_split_plan(op->P, Rpad, variant, &ksplit, &kchunk);
   const size_t xq_bytes = (size_t)SR * Rpad * op->P;
-  const size_t f_bytes = (size_t)Rpad * sizeof(int32_t);
+  const size_t f_bytes = ((size_t)Rpad * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t part_bytes = ksplit > 1 ? (size_t)ksplit * (op->S + SR - 1) * Rpad * op->P * sizeof(int32_t) : 0;
   void* scratch = nullptr;
   configure_pool_once();
-  PINV_HIP_TRY(hipMallocAsync(&scratch, xq_bytes + f_bytes, s));
+  PINV_HIP_TRY(hipMallocAsync(&scratch, xq_bytes + f_bytes + part_bytes, s));
   int8_t* Xq = (int8_t*)scratch;
   int32_t* f = (int32_t*)((char*)scratch + xq_bytes);
   hipError_t e;
@@ -202,7 +206,10 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
     a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
     a.w = w;
     a.U = U; a.ldu = ldu;
-    a.variant = op->i8_variant[SR];
+    a.variant = variant;
+    a.ksplit = ksplit;
+    a.kchunk = kchunk;
+    a.part = ksplit > 1 ? (int32_t*)((char*)scratch + xq_bytes + f_bytes) : nullptr;
     e = launch_gemm_i8(a, s);
   }
   hipError_t e2 = hipFreeAsync(scratch, s);

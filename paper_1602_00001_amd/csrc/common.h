@@ -142,9 +142,17 @@ struct GemmI8Args {
   double* U; int64_t ldu;
   double* const* ucols;            // if not null, column r of the output is ucols[r]
   int variant;                     // kernel variant (0 .. gemm_i8_variants()-1)
+  // split-K: ksplit > 1 workgroups share each tile, each over k in
+  // [z*kchunk, (z+1)*kchunk) (kchunk a multiple of 128); their int32 class
+  // sums go to part[z][class][Rpad][P] and a second kernel adds them (exactly)
+  // and applies the epilogue
+  int ksplit, kchunk;
+  int32_t* part;
 };
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s);
 int gemm_i8_variants();
+// split plan for one launch of `variant` (ksplit = 1: none)
+void gemm_i8_split_plan(int64_t P, int Rpad, int variant, int* ksplit, int* kchunk);
 
 // Grouped int8 product: several operators (same S and SR) in one launch.
 // Group g owns global tiles [tile0, tile0 + tilesM*tilesN) of the launch, tiles

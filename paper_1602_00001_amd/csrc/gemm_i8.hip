@@ -139,7 +139,10 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
   const int mt = tile / tN, nt = tile % tN;
   const int m0 = mt * BM, n0 = nt * BN;
   const int64_t P = a.P;
-  const int nsteps = (int)(P / BK);
+  // k steps of this workgroup: all of k, or its split's share
+  const int z = blockIdx.y;
+  const int kfirst = a.ksplit > 1 ? z * (a.kchunk / BK) : 0;
+  const int nsteps = a.ksplit > 1 ? (int)(min(P, (int64_t)(z + 1) * a.kchunk) / BK) - kfirst : (int)(P / BK);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -170,7 +173,7 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
     // (through readfirstlane, so the compiler keeps one scalar base per plane
     // and a 32-bit lane offset instead of strength-reducing every DMA address
     // into a 64-bit vector register)
-    const int64_t k0 = (int64_t)__builtin_amdgcn_readfirstlane(step * BK);
+    const int64_t k0 = (int64_t)__builtin_amdgcn_readfirstlane((kfirst + step) * BK);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int8_t* b = tileA + s * planeA + k0;
@@ -365,6 +368,25 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
     }
   }
 
+  if (a.ksplit > 1) {
+    // raw class sums of this split, rows m fastest
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (n >= a.nrhs) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+          if (m >= a.n) continue;
+#pragma unroll
+          for (int c = 0; c < C; ++c) a.part[(((int64_t)z * C + c) * a.Rpad + n) * P + m] = acc[c][i][j][r];
+        }
+      }
+    return;
+  }
+
   // exact recombination and the single scaling
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -389,6 +411,26 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
       }
     }
   }
+}
+
+// Split-K epilogue: one thread per output (rows fastest); the splits' class
+// sums are added exactly in int64, then recombined and scaled as in the GEMM
+// epilogue (same operations, so the result is bit-identical).
+__global__ __launch_bounds__(256) void gemm_i8_splitk_epilogue(GemmI8Args a, int C) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)a.n * a.nrhs) return;
+  const int m = (int)(idx % a.n), n = (int)(idx / a.n);
+  int64_t cls[5] = {0, 0, 0, 0, 0};
+  for (int z = 0; z < a.ksplit; ++z)
+    for (int c = 0; c < C; ++c) cls[c] += a.part[(((int64_t)z * C + c) * a.Rpad + n) * a.P + m];
+  int64_t v = cls[0];
+  for (int c = 1; c < C; ++c) v = v * 256 + cls[c];
+  const int em = a.row_exp ? a.row_exp[m] : 0;
+  const double scale = ldexp(a.c, em + a.col_exp[n]);
+  double u = (double)v * scale;
+  if (a.w) u = u + a.w[m];
+  double* ucol = a.ucols ? a.ucols[n] : a.U + (int64_t)n * a.ldu;
+  ucol[m] = u;
 }
 
 // Variants 0-7 (8-wave workgroups, 128 x 128 tiles, one per compute unit):
@@ -418,7 +460,8 @@ hipError_t launch_v(const GemmI8Args& a, const GemmI8Group* groups, int ngroups,
   const int tilesM = groups ? 0 : (int)(a.P / K::BM), tilesN = groups ? 0 : a.Rpad / BN;
   const int T = groups ? total : tilesM * tilesN;
   const int grid = MAP == 0 ? ((T + 7) / 8) * 8 : T;
-  hipLaunchKernelGGL((gemm_i8_kernel<S, SR, BKV, MAP, PF, NWV>), dim3(grid), dim3(K::NT), 0, s, a, tilesM, tilesN,
+  const int zs = (!groups && a.ksplit > 1) ? a.ksplit : 1;
+  hipLaunchKernelGGL((gemm_i8_kernel<S, SR, BKV, MAP, PF, NWV>), dim3(grid, zs), dim3(K::NT), 0, s, a, tilesM, tilesN,
                      groups, ngroups, total);
   return hipGetLastError();
 }
@@ -464,10 +507,40 @@ int gemm_i8_variants() { return 13; }
 
 int gemm_i8_tile_rows(int variant) { return (variant == 10 || variant == 11) ? 64 : 128; }
 
+void gemm_i8_split_plan(int64_t P, int Rpad, int variant, int* ksplit, int* kchunk) {
+  // Split k only when the tiles alone leave resident workgroup slots empty
+  // (T < W): z = min(W / T, 4), with at least 2048 of k per split.  (With more
+  // tiles than slots, splitting the last round measured no gain: the product
+  // is then limited by the operand stream into LDS, not by idle units.)
+  const int rows = gemm_i8_tile_rows(variant);
+  const int T = (int)(P / rows) * (Rpad / BN);
+  const int W = rows == 128 ? 256 : 512;  // workgroups resident at once
+  int zz = T > 0 ? W / T : 1;
+  if (zz > 4) zz = 4;
+  while (zz > 1 && P / zz < 2048) --zz;
+  if (zz < 2) {
+    *ksplit = 1;
+    *kchunk = (int)P;
+    return;
+  }
+  int64_t chunk = (P + zz - 1) / zz;
+  chunk = (chunk + 127) / 128 * 128;
+  *ksplit = (int)((P + chunk - 1) / chunk);
+  *kchunk = (int)chunk;
+}
+
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s) {
   if (a.nrhs <= 0) return hipSuccess;
   if (a.P % 256 != 0 || a.Rpad % BN != 0) return hipErrorInvalidValue;  // tiles cover P and Rpad exactly
-  return dispatch(a.S, a.SR, a, a.variant, nullptr, 0, 0, s);
+  const bool split = a.ksplit > 1;
+  if (split && (!a.part || a.kchunk <= 0 || a.kchunk % 128 != 0 || (int64_t)a.kchunk * (a.ksplit - 1) >= a.P))
+    return hipErrorInvalidValue;
+  hipError_t e = dispatch(a.S, a.SR, a, a.variant, nullptr, 0, 0, s);
+  if (e != hipSuccess || !split) return e;
+  const int64_t outs = (int64_t)a.n * a.nrhs;
+  hipLaunchKernelGGL(gemm_i8_splitk_epilogue, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s, a,
+                     a.S + a.SR - 1);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm_i8_grouped(const GemmI8Group* d_groups, int ngroups, int total_tiles, int S, int SR,

@@ -24,8 +24,10 @@ def pinv():
     return p
 
 
-@pytest.mark.parametrize("nx,ny,bits,rho_bits", [(40, 31, 24, 16), (33, 20, 16, 24), (12, 9, 8, 8)])
+@pytest.mark.parametrize("nx,ny,bits,rho_bits", [(40, 31, 24, 16), (33, 20, 16, 24), (12, 9, 8, 8), (66, 66, 24, 16)])
 def test_every_variant_bit_exact(torch, pinv, nx, ny, bits, rho_bits):
+    """(66, 66) has P = 4096 and few tiles, so every variant also runs split
+    over k (integer class sums of the splits added exactly)."""
     g = np.random.default_rng(nx * ny + bits)
     ub = g.standard_normal((ny, nx))
     h = 1.0 / (max(nx, ny) - 1)

@@ -129,8 +129,9 @@ def test_int8_apply_bit_exact(torch, pinv, nx, ny, bits, rho_bits):
     assert np.array_equal(u.T, ref)
 
 
-@pytest.mark.parametrize("nx,ny", [(12, 9), (50, 37)])
+@pytest.mark.parametrize("nx,ny", [(12, 9), (50, 37), (66, 66)])
 def test_int8_adjoint_bit_exact(torch, pinv, nx, ny):
+    """(66, 66): P = 4096 with one tile column, so the product splits k."""
     announce(f"adjoint int8 nx={nx} ny={ny}")
     g = np.random.default_rng(11)
     h = 1.0 / (max(nx, ny) - 1)
