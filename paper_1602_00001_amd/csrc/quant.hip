@@ -123,11 +123,20 @@ template <int SR>
 __device__ inline void quantize_col(const double* __restrict__ x, bool live, int n, int r, int Rpad, int64_t P,
                                     const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
                                     int32_t* __restrict__ f, double* red) {
+  // Loads are unconditional from clamped indices (k < n selects the value
+  // afterwards): a load under a per-lane condition makes the next write of its
+  // register wait for it, which would serialise the loads of a pass.
   double m = 0.0;
   if (live)
-    for (int k = threadIdx.x; k < n; k += 256) {
-      const double v = pre ? ldexp(x[k], pre[k]) : x[k];
-      m = fmax(m, fabs(v));
+    for (int64_t k0 = (int64_t)threadIdx.x * 4; k0 < n; k0 += 256 * 4) {
+      double v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t k = min(k0 + t, (int64_t)n - 1);
+        v[t] = pre ? ldexp(x[k], pre[k]) : x[k];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) m = fmax(m, k0 + t < n ? fabs(v[t]) : 0.0);
     }
   m = block_max_256(m, red);
   const int fr = frexp_exp(m);
@@ -135,14 +144,19 @@ __device__ inline void quantize_col(const double* __restrict__ x, bool live, int
   const double M = (double)(127LL * ((1LL << (8 * SR)) - 1) / 255);
   for (int64_t k0 = (int64_t)threadIdx.x * 4; k0 < P; k0 += 256 * 4) {
     int8_t d[SR][4];
+    double v[4];
+    if (live) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t k = min(k0 + t, (int64_t)n - 1);
+        v[t] = pre ? ldexp(x[k], pre[k]) : x[k];
+      }
+    }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int64_t k = k0 + t;
       int q = 0;
-      if (live && k < n) {
-        const double v = pre ? ldexp(x[k], pre[k]) : x[k];
-        q = (int)rint(ldexp(v, -fr) * M);
-      }
+      if (live && k < n) q = (int)rint(ldexp(v[t], -fr) * M);
       int8_t dd[SR];
       digits<SR>(q, dd);
 #pragma unroll
@@ -150,9 +164,9 @@ __device__ inline void quantize_col(const double* __restrict__ x, bool live, int
     }
 #pragma unroll
     for (int s = 0; s < SR; ++s) {
-      int v;
-      __builtin_memcpy(&v, d[s], 4);
-      *(int*)(Xq + ((int64_t)s * Rpad + r) * P + k0) = v;
+      int word;
+      __builtin_memcpy(&word, d[s], 4);
+      *(int*)(Xq + ((int64_t)s * Rpad + r) * P + k0) = word;
     }
   }
 }
