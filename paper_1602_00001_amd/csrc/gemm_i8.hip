@@ -13,20 +13,26 @@
 // Tiling: 128 (rows of G) x 128 (right-hand sides) per 512-thread workgroup,
 // 8 waves in 4x2 (two per SIMD, so one wave's waits are covered by the other's
 // matrix-core work), each 32x64 = 2x4 blocks of v_mfma_i32_16x16x64_i8 per
-// class (128 accumulator registers per wave).
+// class (128 accumulator registers per wave at four classes); or 64 x 128 per
+// 256-thread workgroup, two workgroups per compute unit.
 // Operand tiles move global -> LDS with global_load_lds_dwordx4 (no staging
 // registers): one instruction fills 1 KB of LDS (one block of rows) per wave.
-// LDS rows are unpadded; the four 16-byte chunks of row r are stored at chunk
-// position c ^ ((r >> 2) & 3), so the 16 lanes of a 128-bit fragment read
-// (16 consecutive rows, same logical chunk) hit 16 distinct 4-bank groups.  A
+// LDS rows (BK = 128 or 64 bytes of k) are unpadded; the 16-byte chunks of a
+// row are XOR-swizzled so the 16 lanes of a 128-bit fragment read (16
+// consecutive rows, same logical chunk) hit 16 distinct 4-bank groups, and a
 // lane of the DMA loads the global chunk that belongs at its own LDS slot.
-// NST LDS stages (4 when they fit in the 160 KB of a CU, else 3) keep NST-1 k
-// steps of loads in flight.  Each wave waits for its own DMA group (vmcnt),
-// then a plain s_barrier (no fence: a fence would drain all in-flight stages)
-// makes the stage visible to all waves and frees the stage read one step
-// earlier.
+// NST LDS stages (as many as fit, at most 4) keep NST-1 k steps of loads in
+// flight.  Each wave waits for its own DMA group (vmcnt), then a plain
+// s_barrier (no fence: a fence would drain all in-flight stages) makes the
+// stage visible to all waves and frees the stage read one step earlier.
 // The digit planes and quantised right-hand sides are zero-padded to the tile
 // grid, so the main loop has no bounds checks.
+//
+// The variants (tile shape, k depth, tile order, fragment-read schedule) are
+// listed above launch_v; all compute the same class sums.  Optional split-K
+// (partial class sums added by a second kernel) and grouped launches (several
+// operators, each workgroup finding its group in a device table) reuse the
+// same kernel.
 //
 // v_mfma_i32_16x16x64_i8 layout (lane l, result register r):
 //   A(i = l%16, k = 16*(l/16) + b), B(k = 16*(l/16) + b, j = l%16),

@@ -105,7 +105,7 @@ struct SplitArgs {
 constexpr int BM = 128, BN = 128, ROWB = 80;
 
 template <int NP>
-__global__ __launch_bounds__(256, 1) void gemm_bf16_kernel(SplitArgs a, int tilesM, int tilesN) {
+__global__ __launch_bounds__(256, NP == 2 ? 2 : 1) void gemm_bf16_kernel(SplitArgs a, int tilesM, int tilesN) {
   constexpr int PLANE = BM * ROWB;
   constexpr int STAGE = 2 * NP * PLANE;
   __shared__ __attribute__((aligned(16))) int8_t sm[2 * STAGE];
@@ -163,27 +163,31 @@ __global__ __launch_bounds__(256, 1) void gemm_bf16_kernel(SplitArgs a, int tile
     const bool has_next = kb + 64 < KB;
     if (has_next) load(kb + 64);
     const int8_t* base = sm + st * STAGE;
-    v8bf fa[NP][4], fb[NP][4];
+    // the right-hand side fragments of the whole step, the G fragments one
+    // 16-row block at a time (fewer live registers: two waves per SIMD for
+    // BF16x3)
+    v8bf fb[NP][4];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) fa[p][i] = *(const v8bf*)(base + p * PLANE + (wm * 64 + i * 16) * ROWB + frag_off);
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         fb[p][j] = *(const v8bf*)(base + (NP + p) * PLANE + (wn * 64 + j * 16) * ROWB + frag_off);
-    }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+      v8bf fa[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) fa[p] = *(const v8bf*)(base + p * PLANE + (wm * 64 + i * 16) * ROWB + frag_off);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        big[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[0][j], big[i][j], 0, 0, 0);
+        big[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0], fb[0][j], big[i][j], 0, 0, 0);
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
           for (int q = 0; q < NP; ++q)
             if (p + q > 0 && p + q <= NP - 1)
-              small[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[p][i], fb[q][j], small[i][j], 0, 0, 0);
+              small[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[p], fb[q][j], small[i][j], 0, 0, 0);
       }
+    }
     if (has_next) store(st ^ 1);
     __syncthreads();
     st ^= 1;

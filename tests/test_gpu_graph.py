@@ -1,0 +1,53 @@
+"""The FP64 GEMV apply (at most 4 right-hand sides) allocates nothing and
+records no memset, so a time loop of applies can be captured in a HIP graph:
+every replay, with eager work and synchronisations in between, gives the eager
+result bit for bit."""
+
+import numpy as np
+import pytest
+
+from oracle import apply
+from tests.gpu_util import announce, dev, host, oracle_inverse, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_graph_replay_of_fp64_gemv_apply(torch, nrhs):
+    from paper_1602_00001_amd import pinv
+    announce(f"HIP graph of 8 fp64 GEMV applies, nrhs={nrhs}")
+    nx, ny = 32, 32
+    h = 1.0 / (nx - 1)
+    G, _, _ = oracle_inverse(nx, ny)
+    g = np.random.default_rng(60 + nrhs)
+    rho_h = g.standard_normal((nrhs, G.shape[0]))
+    with pinv.PoissonInverse.from_inverse(nx, ny, h, G) as op:
+        rho = dev(rho_h)
+        eager = op.apply(rho, "fp64")
+        u = torch.full_like(rho, float("nan"))
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            op.apply(rho, "fp64", out=u)
+        torch.cuda.current_stream().wait_stream(s)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for _ in range(8):
+                op.apply(rho, "fp64", out=u)
+        ref = apply.plain_apply(G, rho_h.T, h, None)
+        for rep in range(4):
+            u.fill_(float("nan"))
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(u, eager), rep
+            # eager work between replays
+            other = op.apply(dev(g.standard_normal((nrhs, G.shape[0]))), "fp64")
+            torch.cuda.synchronize()
+            del other
+        assert np.max(np.abs(host(u).T - ref)) <= 1e-12 * np.max(np.abs(ref))
+        del graph
