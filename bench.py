@@ -274,9 +274,12 @@ def bench_plain_32(args):
     op = pinv.PoissonInverse.build(n, n, h)
     rho = torch.from_numpy(wl["rho"]).cuda()
     u = torch.empty_like(rho)
+    for _ in range(args.warmup):
+        op.apply(rho, "fp64", out=u)
+    torch.cuda.synchronize()
     pinv.trace_read("gemv_f64")
     pinv.trace_enable(True)
-    dt = _timed(lambda: op.apply(rho, "fp64", out=u), args.steps, args.warmup)
+    dt = _timed(lambda: op.apply(rho, "fp64", out=u), args.steps, 0)
     pinv.trace_enable(False)
     ms, cnt = pinv.trace_read("gemv_f64")
     kms = ms / max(cnt, 1)
@@ -331,9 +334,12 @@ def bench_vareps_64(args):
         if mode != "fp64":
             op.prepare_split(mode)
         u = torch.empty_like(rho)
+        for _ in range(args.warmup):
+            op.apply(rho, mode, out=u)
+        torch.cuda.synchronize()
         pinv.trace_read(kern)
         pinv.trace_enable(True)
-        dt = _timed(lambda: op.apply(rho, mode, out=u), args.steps, args.warmup)
+        dt = _timed(lambda: op.apply(rho, mode, out=u), args.steps, 0)
         pinv.trace_enable(False)
         ms, cnt = pinv.trace_read(kern)
         kms = ms / max(cnt, 1)
@@ -383,10 +389,13 @@ def bench_grad_192(args):
         op.apply_adjoint(gu, "int8", 16, out=lam)
         op.grad_eps(u, lam, out=ge)
 
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
     for k in ("gemm_i8", "grad_eps", "quantize_cols"):
         pinv.trace_read(k)
     pinv.trace_enable(True)
-    dt = _timed(step, args.steps, args.warmup)
+    dt = _timed(step, args.steps, 0)
     pinv.trace_enable(False)
     gms, gcnt = pinv.trace_read("gemm_i8")
     ems, ecnt = pinv.trace_read("grad_eps")
@@ -441,14 +450,17 @@ def bench_batched(args):
     t0 = time.perf_counter()
     variants = [_autotune(op, args, 16, torch.cat(rl))[0] for (op, rl) in group.values()]
     t_tune = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        pinv.apply_batched(batch, "int8", 16)
+    torch.cuda.synchronize()
     for k in ("gemm_i8", "quantize_cols"):
         pinv.trace_read(k)
     pinv.trace_enable(True)
-    dt = _timed(lambda: pinv.apply_batched(batch, "int8", 16), args.steps, args.warmup)
+    dt = _timed(lambda: pinv.apply_batched(batch, "int8", 16), args.steps, 0)
     pinv.trace_enable(False)
     gms, gcnt = pinv.trace_read("gemm_i8")
     qms, qcnt = pinv.trace_read("quantize_cols")
-    steps_traced = args.steps + args.warmup
+    steps_traced = args.steps
     gemm_ms_per_step = gms / steps_traced
     ach = ops_count / (gemm_ms_per_step * 1e-3) / 1e12
     for op in ops:

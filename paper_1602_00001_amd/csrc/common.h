@@ -148,8 +148,17 @@ struct GemmI8Args {
   // and applies the epilogue
   int ksplit, kchunk;
   int32_t* part;
+  // bytes of k per operand row (the row stride); 0 means P (int8 digits)
+  int64_t kbytes;
 };
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s);
+// The same tiled product over bfloat16 split parts (G parts in Q as
+// [S][P][P] bf16, right-hand-side parts in X as [S][Rpad][P] bf16, kbytes =
+// 2P): products of parts p + q <= S-1 summed in two FP32 accumulators
+// (leading part, corrections), u = c * (big + small) + w.  With ksplit > 1
+// the splits' FP64 sums go to partf[z][r][m] and launch_splitk_reduce adds
+// them.  col_exp and row_exp are unused.
+hipError_t launch_gemm_bf16_parts(const GemmI8Args& a, double* partf, hipStream_t s);
 int gemm_i8_variants();
 // split plan for one launch of `variant` (ksplit = 1: none)
 void gemm_i8_split_plan(int64_t P, int Rpad, int variant, int* ksplit, int* kchunk);

@@ -99,11 +99,14 @@ struct Cfg {
 // (fragments being read) + 4 (2S + 4DT) (fragments held) + misc <= 256
 // (misc = registers for addresses and loop state: 8 when the compiler
 // schedules freely, 24 with the order pinned)
-constexpr int dt_of(int S, int SR, int misc) {
+constexpr int dt_of(int S, int SR, int misc, int acc_sets) {
   int dt = SR;
-  while (dt > 1 && 32 * (S + SR - 1) + 4 * (2 * S + 4 * SR) + 4 * (2 * S + 4 * dt) + misc > 256) --dt;
+  while (dt > 1 && 32 * acc_sets + 4 * (2 * S + 4 * SR) + 4 * (2 * S + 4 * dt) + misc > 256) --dt;
   return dt;
 }
+
+template <int KIND> struct AccOf { using T = v4i; };   // int8 digit classes
+template <> struct AccOf<1> { using T = v4f; };        // bfloat16 parts
 
 // Swizzle: the 16-byte chunk c of tile row r sits at chunk position
 // c ^ ((r >> 1) & 7) (128-byte rows) or c ^ ((r >> 2) & 3) (64-byte rows), so
@@ -114,12 +117,17 @@ __device__ inline int swz(int row, int c) {
   return CH == 8 ? (c ^ ((row >> 1) & 7)) : (c ^ ((row >> 2) & 3));
 }
 
-template <int S, int SR, int BKV, int MAP, int PF, int NWV>
+// KIND 0: int8 digit planes, int32 class accumulators (the quantised apply).
+// KIND 1: bfloat16 split parts (S = SR = number of parts), two FP32
+// accumulators; the operand movement is byte for byte the same.
+template <int S, int SR, int BKV, int MAP, int PF, int NWV, int KIND = 0>
 __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(GemmI8Args a_in, int tilesM, int tilesN,
                                                                          const GemmI8Group* __restrict__ groups,
-                                                                         int ngroups, int total) {
+                                                                         int ngroups, int total, double* partf) {
   using K = Cfg<S, SR, BKV, NWV>;
   constexpr int C = K::C, BK = K::BK, CH = K::CH, STAGE = K::STAGE, NST = K::NST;
+  constexpr int CA = KIND == 0 ? C : 2;  // accumulator sets
+  using AT = typename AccOf<KIND>::T;
   constexpr int BM = K::BM, NW = K::NW, PLANE_A = K::PLANE_A, PLANE_B = K::PLANE_B;
   constexpr int RPI = K::RPI, IPA = K::IPA, IPB = K::IPB, L = K::L;
   __shared__ __attribute__((aligned(1024))) int8_t sm[NST * STAGE];
@@ -145,10 +153,11 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
   const int mt = tile / tN, nt = tile % tN;
   const int m0 = mt * BM, n0 = nt * BN;
   const int64_t P = a.P;
+  const int64_t KBY = a.kbytes ? a.kbytes : P;  // bytes of k per row
   // k steps of this workgroup: all of k, or its split's share
   const int z = blockIdx.y;
   const int kfirst = a.ksplit > 1 ? z * (a.kchunk / BK) : 0;
-  const int nsteps = a.ksplit > 1 ? (int)(min(P, (int64_t)(z + 1) * a.kchunk) / BK) - kfirst : (int)(P / BK);
+  const int nsteps = a.ksplit > 1 ? (int)(min(KBY, (int64_t)(z + 1) * a.kchunk) / BK) - kfirst : (int)(KBY / BK);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -163,16 +172,16 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
 #pragma unroll
   for (int j = 0; j < IPA; ++j) {
     const int row = wave * (BM / NW) + j * RPI + lane / CH;
-    offa[j] = (uint32_t)row * (uint32_t)P + (uint32_t)(swz<CH>(row, lane % CH) * 16);  // swizzle is an involution
+    offa[j] = (uint32_t)row * (uint32_t)KBY + (uint32_t)(swz<CH>(row, lane % CH) * 16);  // swizzle is an involution
   }
 #pragma unroll
   for (int j = 0; j < IPB; ++j) {
     const int row = wave * (BN / NW) + j * RPI + lane / CH;
-    offb[j] = (uint32_t)row * (uint32_t)P + (uint32_t)(swz<CH>(row, lane % CH) * 16);
+    offb[j] = (uint32_t)row * (uint32_t)KBY + (uint32_t)(swz<CH>(row, lane % CH) * 16);
   }
-  const int8_t* tileA = a.Q + (int64_t)m0 * P;
-  const int8_t* tileB = a.X + (int64_t)n0 * P;
-  const int64_t planeA = P * P, planeB = (int64_t)a.Rpad * P;
+  const int8_t* tileA = a.Q + (int64_t)m0 * KBY;
+  const int8_t* tileB = a.X + (int64_t)n0 * KBY;
+  const int64_t planeA = P * KBY, planeB = (int64_t)a.Rpad * KBY;
 
   auto issue = [&](int step) {
     int8_t* dst = sm + (step % NST) * STAGE;
@@ -205,13 +214,26 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
 #pragma unroll
   for (int h = 0; h < BK / 64; ++h) foff[h] = frow * BK + swz<CH>(frow, 4 * h + (lane >> 4)) * 16;
 
-  v4i acc[C][2][4];
+  AT acc[CA][2][4];
 #pragma unroll
-  for (int c = 0; c < C; ++c)
+  for (int c = 0; c < CA; ++c)
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[c][i][j] = v4i{0, 0, 0, 0};
+      for (int j = 0; j < 4; ++j) acc[c][i][j] = AT{0, 0, 0, 0};
+
+  // one product of digit s of G with digit t of rho (KIND 1: of part s of G
+  // with part t of rho, kept only when s + t <= S - 1)
+  auto mma = [&](int s, int t, int i, int j, const v4i& fa, const v4i& fb) {
+    if constexpr (KIND == 0) {
+      acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa, fb, acc[s + t][i][j], 0, 0, 0);
+    } else {
+      if (s + t > S - 1) return;
+      const int q = s + t == 0 ? 0 : 1;
+      acc[q][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, fa), __builtin_bit_cast(v8bf, fb),
+                                                             acc[q][i][j], 0, 0, 0);
+    }
+  };
 
   // fragment reads of k half h of the stage at `base` and the products of one
   // k half (16-row blocks start at multiples of 16, where the swizzle of the
@@ -240,8 +262,7 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) mma(s, t, i, j, fa[i], fb[t][j]);
   };
   auto products = [&](int s, const v4i (&fa)[2], const v4i (&fb)[SR][4]) {
 #pragma unroll
@@ -249,8 +270,7 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) mma(s, t, i, j, fa[i], fb[t][j]);
   };
 
   if constexpr (PF >= 2 && NST == 2 && BK == 128) {
@@ -262,7 +282,7 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
     // stage's first fragments are in flight.  DT is as large as the registers
     // allow (the fragments held across the barrier are 2S + 4DT registers of
     // 128 bits).
-    constexpr int DT = dt_of(S, SR, PF == 3 ? 24 : 8);
+    constexpr int DT = dt_of(S, SR, PF == 3 ? 24 : 8, CA);
     v4i xa[S][2], xb[SR][4], ya[S][2], yb[SR][4];
     issue(0);
     wait_vm<0>();
@@ -374,6 +394,31 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
     }
   }
 
+  if constexpr (KIND == 1) {
+    // bfloat16 parts: leading and correction sums combined in FP64
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (n >= a.nrhs) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+          if (m >= a.n) continue;
+          const double sum = (double)acc[0][i][j][r] + (double)acc[1][i][j][r];
+          if (a.ksplit > 1) {
+            partf[((int64_t)z * a.nrhs + n) * a.n + m] = sum;
+          } else {
+            double v = a.c * sum;
+            if (a.w) v += a.w[m];
+            a.U[(int64_t)n * a.ldu + m] = v;
+          }
+        }
+      }
+    return;
+  }
+
   if (a.ksplit > 1) {
     // raw class sums of this split, rows m fastest
 #pragma unroll
@@ -468,7 +513,7 @@ hipError_t launch_v(const GemmI8Args& a, const GemmI8Group* groups, int ngroups,
   const int grid = MAP == 0 ? ((T + 7) / 8) * 8 : T;
   const int zs = (!groups && a.ksplit > 1) ? a.ksplit : 1;
   hipLaunchKernelGGL((gemm_i8_kernel<S, SR, BKV, MAP, PF, NWV>), dim3(grid, zs), dim3(K::NT), 0, s, a, tilesM, tilesN,
-                     groups, ngroups, total);
+                     groups, ngroups, total, (double*)nullptr);
   return hipGetLastError();
 }
 
@@ -555,4 +600,30 @@ hipError_t launch_gemm_i8_grouped(const GemmI8Group* d_groups, int ngroups, int 
   if (!d_groups || variant < 0 || variant >= gemm_i8_variants()) return hipErrorInvalidValue;
   GemmI8Args none{};
   return dispatch(S, SR, none, variant, d_groups, ngroups, total_tiles, s);
+}
+
+hipError_t launch_gemm_bf16_parts(const GemmI8Args& a, double* partf, hipStream_t s) {
+  if (a.nrhs <= 0) return hipSuccess;
+  if (a.P % 256 != 0 || a.Rpad % BN != 0 || a.kbytes != 2 * a.P || a.S != a.SR) return hipErrorInvalidValue;
+  const bool split = a.ksplit > 1;
+  if (split && (!partf || a.kchunk <= 0 || a.kchunk % 128 != 0 || (int64_t)a.kchunk * (a.ksplit - 1) >= a.kbytes))
+    return hipErrorInvalidValue;
+  // 8-wave 128 x 128 tiles, all fragments of a k half read up front, XCD order;
+  // 128-byte k steps where two stages fit, else 64
+  const int tilesM = (int)(a.P / 128), tilesN = a.Rpad / BN;
+  const int T = tilesM * tilesN;
+  const dim3 grid(((T + 7) / 8) * 8, split ? a.ksplit : 1);
+  switch (a.S) {
+    case 2:
+      hipLaunchKernelGGL((gemm_i8_kernel<2, 2, 128, 0, 1, 8, 1>), grid, dim3(512), 0, s, a, tilesM, tilesN,
+                         (const GemmI8Group*)nullptr, 0, 0, partf);
+      break;
+    case 3:
+      hipLaunchKernelGGL((gemm_i8_kernel<3, 3, 64, 0, 1, 8, 1>), grid, dim3(512), 0, s, a, tilesM, tilesN,
+                         (const GemmI8Group*)nullptr, 0, 0, partf);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }

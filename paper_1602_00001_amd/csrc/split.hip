@@ -9,12 +9,13 @@
 // FP64 at the end (the published bfloat16 split scheme of Henry, Tang and
 // Heinecke, ARITH 2019).
 //
-// The bf16 GEMM uses the same tile geometry as the int8 digit GEMM: a 64-byte
-// k chunk (32 bf16) per LDS row with 16 pad bytes, 128x128 tiles, 4 waves of
-// 64x64, v_mfma_f32_16x16x32_bf16 (lane l: A(i = l%16, k = 8*(l/16) + t),
-// B(k = 8*(l/16) + t, j = l%16), D(i = 4*(l/16) + r, j = l%16)).
-// G's parts and the right-hand sides' parts are stored zero-padded to P x P and
-// Rpad x P, so the main loops carry no bounds checks.
+// The bf16 products run on the tiled DMA kernel of the int8 digit GEMM
+// (launch_gemm_bf16_parts): v_mfma_f32_16x16x32_bf16 takes its operands in the
+// same 16-byte-per-lane layout as v_mfma_i32_16x16x64_i8 (lane l: A(i = l%16,
+// k = 8*(l/16) + t), B(k = 8*(l/16) + t, j = l%16), D(i = 4*(l/16) + r,
+// j = l%16)), 64 bytes of k per instruction, so the operand movement is the
+// same byte for byte.  G's parts and the right-hand sides' parts are stored
+// zero-padded to P x P and Rpad x P, so the main loops carry no bounds checks.
 
 #include "common.h"
 
@@ -102,117 +103,7 @@ struct SplitArgs {
   double* part;
 };
 
-constexpr int BM = 128, BN = 128, ROWB = 80;
-
-template <int NP>
-__global__ __launch_bounds__(256, NP == 2 ? 2 : 1) void gemm_bf16_kernel(SplitArgs a, int tilesM, int tilesN) {
-  constexpr int PLANE = BM * ROWB;
-  constexpr int STAGE = 2 * NP * PLANE;
-  __shared__ __attribute__((aligned(16))) int8_t sm[2 * STAGE];
-  int mt, nt;
-  bool valid;
-  tile_of(blockIdx.x, tilesM, tilesN, mt, nt, valid);
-  if (!valid) return;
-  const int m0 = mt * BM, n0 = nt * BN;
-  const int64_t P = a.P;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lrow0 = tid >> 2, lch = tid & 3;
-  const int8_t* ga[NP];
-  const int8_t* gb[NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    ga[p] = (const int8_t*)a.A + ((int64_t)p * P * P + (int64_t)(m0 + lrow0) * P) * 2 + lch * 16;
-    gb[p] = (const int8_t*)a.B + ((int64_t)p * a.Rpad * P + (int64_t)(n0 + lrow0) * P) * 2 + lch * 16;
-  }
-  const int64_t step64 = 64 * P * 2;
-  v4i pa[NP][2], pb[NP][2];
-  auto load = [&](int64_t kb) {  // kb: byte offset along k
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      pa[p][0] = *(const v4i*)(ga[p] + kb);
-      pa[p][1] = *(const v4i*)(ga[p] + step64 + kb);
-      pb[p][0] = *(const v4i*)(gb[p] + kb);
-      pb[p][1] = *(const v4i*)(gb[p] + step64 + kb);
-    }
-  };
-  auto store = [&](int st) {
-    int8_t* base = sm + st * STAGE;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      *(v4i*)(base + p * PLANE + lrow0 * ROWB + lch * 16) = pa[p][0];
-      *(v4i*)(base + p * PLANE + (lrow0 + 64) * ROWB + lch * 16) = pa[p][1];
-      *(v4i*)(base + (NP + p) * PLANE + lrow0 * ROWB + lch * 16) = pb[p][0];
-      *(v4i*)(base + (NP + p) * PLANE + (lrow0 + 64) * ROWB + lch * 16) = pb[p][1];
-    }
-  };
-  v4f big[4][4], small[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) big[i][j] = small[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int frag_off = (lane & 15) * ROWB + (lane >> 4) * 16;
-  const int kz = blockIdx.y;
-  const int64_t KB0 = a.ksplit > 1 ? kz * a.kchunk * 2 : 0;                  // bytes along k
-  const int64_t KB = a.ksplit > 1 ? min(P, (kz + 1) * a.kchunk) * 2 : P * 2;
-  int st = 0;
-  load(KB0);
-  store(0);
-  __syncthreads();
-  for (int64_t kb = KB0; kb < KB; kb += 64) {
-    const bool has_next = kb + 64 < KB;
-    if (has_next) load(kb + 64);
-    const int8_t* base = sm + st * STAGE;
-    // the right-hand side fragments of the whole step, the G fragments one
-    // 16-row block at a time (fewer live registers: two waves per SIMD for
-    // BF16x3)
-    v8bf fb[NP][4];
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        fb[p][j] = *(const v8bf*)(base + (NP + p) * PLANE + (wn * 64 + j * 16) * ROWB + frag_off);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      v8bf fa[NP];
-#pragma unroll
-      for (int p = 0; p < NP; ++p) fa[p] = *(const v8bf*)(base + p * PLANE + (wm * 64 + i * 16) * ROWB + frag_off);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        big[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0], fb[0][j], big[i][j], 0, 0, 0);
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-#pragma unroll
-          for (int q = 0; q < NP; ++q)
-            if (p + q > 0 && p + q <= NP - 1)
-              small[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[p], fb[q][j], small[i][j], 0, 0, 0);
-      }
-    }
-    if (has_next) store(st ^ 1);
-    __syncthreads();
-    st ^= 1;
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + wn * 64 + j * 16 + (lane & 15);
-      if (n >= a.nrhs) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-        if (m >= a.n) continue;
-        const double sum = (double)big[i][j][r] + (double)small[i][j][r];
-        if (a.ksplit > 1) {
-          a.part[((int64_t)kz * a.nrhs + n) * a.n + m] = sum;
-          continue;
-        }
-        double v = a.alpha * sum;
-        if (a.w) v += a.w[m];
-        a.U[(int64_t)n * a.ldu + m] = v;
-      }
-    }
-}
+constexpr int BM = 128, BN = 128;
 
 // FP32: 128x128 tiles, k step 16 floats, v_mfma_f32_16x16x4f32
 // (lane l: A(i = l%16, k = l/16), B(k = l/16, j = l%16), D(i = 4*(l/16) + r, j = l%16)).
@@ -389,12 +280,24 @@ hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int
     const int parts = mode == PINV_BF16X3 ? 2 : 3;
     hipLaunchKernelGGL(pack_bf16_kernel, dim3(pgrid), dim3(256), 0, s, X, ldx, op->n, nrhs, Rpad, P, parts,
                        (__bf16*)scratch);
-    a.A = op->Gb;
-    // G's parts are stored with op->nbf planes; the kernel reads the first `parts`
-    if (parts == 2)
-      hipLaunchKernelGGL(gemm_bf16_kernel<2>, g3, dim3(256), 0, s, a, tilesM, tilesN);
-    else
-      hipLaunchKernelGGL(gemm_bf16_kernel<3>, g3, dim3(256), 0, s, a, tilesM, tilesN);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the parts' products on the tiled DMA kernel of the int8 slice GEMM (the
+    // same byte layout: 128 x 128 tiles, 16-byte fragments, 64 bytes of k per
+    // matrix-core instruction); G's parts are stored with op->nbf planes, the
+    // first `parts` are read
+    GemmI8Args g{};
+    g.Q = (const int8_t*)op->Gb; g.S = parts;
+    g.X = (const int8_t*)scratch; g.SR = parts;
+    g.P = P; g.Rpad = Rpad; g.kbytes = 2 * P;
+    g.n = op->n; g.nrhs = nrhs;
+    g.c = alpha; g.w = op->w;
+    g.U = U; g.ldu = ldu;
+    g.ksplit = a.ksplit;
+    g.kchunk = (int)(2 * a.kchunk);
+    e = launch_gemm_bf16_parts(g, a.part, s);
+    if (e != hipSuccess || a.ksplit <= 1) return e;
+    return launch_splitk_reduce(a.part, a.ksplit, op->n, nrhs, alpha, 0.0, op->w, U, 1, ldu, s);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.ksplit <= 1) return e;
