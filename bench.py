@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--workload", default="quant_128",
-                    choices=["quant_128", "plain_32", "vareps_64", "grad_192", "batched"],
+                    choices=["quant_128", "plain_32", "vareps_64", "grad_192", "batched", "coupled_32"],
                     help="quant_128 is the headline metric; the others measure the remaining paths")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -314,6 +314,61 @@ def bench_plain_32(args):
     return line
 
 
+def bench_coupled_32(args):
+    """Time-coupled stepping on 30^2 unknowns: rho_{t+1} = rho_t + tau u_t, one
+    right-hand side per step, eager and as a HIP graph of the whole loop."""
+    import torch
+    from paper_1602_00001_amd import pinv, workloads
+    wl = workloads.coupled_32()
+    n, h, tau, steps = wl["n"], wl["h"], wl["tau"], wl["steps"]
+    op = pinv.PoissonInverse.build(n, n, h)
+    rho0 = torch.from_numpy(wl["rho0"]).cuda()
+    r = rho0.clone()
+    u = torch.empty_like(r)
+
+    def loop():
+        for _ in range(steps):
+            op.apply(r, "fp64", out=u)
+            r.add_(u, alpha=tau)
+
+    for _ in range(max(args.warmup, 1)):
+        r.copy_(rho0)
+        loop()
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r.copy_(rho0)
+        loop()
+    torch.cuda.synchronize()
+    dt_eager = (time.perf_counter() - t0) / (reps * steps)
+    eager = r.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        r.copy_(rho0)
+        op.apply(r, "fp64", out=u)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        loop()
+
+    def replay():
+        r.copy_(rho0)
+        graph.replay()
+
+    dt_graph = _timed(replay, reps, 1) / steps
+    exact = bool(torch.equal(r, eager))
+    del graph
+    op.close()
+    line = _base("coupled time steps/sec, 30x30 unknowns, one right-hand side per step (FP64 apply + coupling), HIP graph",
+                 1.0 / dt_graph, "steps/s", args, dt_graph * 1e3, "f64",
+                 {"workload": f"coupled_32: 32x32 grid, 900 unknowns, rho_(t+1) = rho_t + {tau} u_t, {steps} steps per loop"})
+    line["us_per_step"] = {"hip_graph": dt_graph * 1e6, "eager": dt_eager * 1e6}
+    line["graph_bit_identical_to_eager"] = exact
+    return line
+
+
 def bench_vareps_64(args):
     """64x64 grid, variable eps, 256 drifting-blob time steps: FP64 against the
     FP32 and BF16 split forms."""
@@ -478,7 +533,7 @@ def bench_batched(args):
 
 
 OTHER = {"plain_32": bench_plain_32, "vareps_64": bench_vareps_64, "grad_192": bench_grad_192,
-         "batched": bench_batched}
+         "batched": bench_batched, "coupled_32": bench_coupled_32}
 
 
 if __name__ == "__main__":

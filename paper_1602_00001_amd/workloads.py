@@ -109,6 +109,14 @@ def plain_32():
     return dict(n=n, h=1.0 / (n - 1), eps=None, ub=None, rho=blob_rhs(n, 1, rng(1, 0)))
 
 
+def coupled_32(steps=64, tau=4.0):
+    """Time-coupled stepping on the 32x32 grid: rho_{t+1} = rho_t + tau * u_t
+    with u_t the solution for rho_t (one right-hand side per step, each step
+    depending on the previous one); rho_0 is the plain_32 blob field."""
+    n = 32
+    return dict(n=n, h=1.0 / (n - 1), rho0=blob_rhs(n, 1, rng(1, 0)), tau=tau, steps=steps)
+
+
 def vareps_64(nrhs=256):
     """64x64 grid, eps = 1 + 0.5 sin(2 pi x) cos(2 pi y), 256 drifting-blob time steps."""
     n = 64
