@@ -167,3 +167,41 @@ def interior_to_nodes(nx, ny, u_int, ub_nodes=None):
 def nodes_to_interior(nx, ny, nodal):
     """Gather the interior values of a [n_y][n_x] array in p order."""
     return np.ascontiguousarray(np.asarray(nodal)[1:ny - 1, 1:nx - 1]).reshape(-1)
+
+
+# --- three dimensions (the paper's N = n_x n_y n_z, "Statement of the problem") ---
+
+def conservative_operator_3d(nx, ny, nz, eps_nodes=None, ub_nodes=None):
+    """7-point conservative operator on an n_z x n_y x n_x grid (nodal arrays
+    [n_z][n_y][n_x], slowest axis z; interior index
+    p = ((k-1)(n_y-2) + (i-1))(n_x-2) + (j-1)), built exactly as the 2-D form:
+    for every interior node p and each of its 6 faces f to node q,
+        K[p,p] += eps_f,  K[p,q] -= eps_f (q interior),
+        b_B[p] += eps_f * u_B(q) (q on the boundary),
+    with eps_f the mean of the two nodal values.  With eps = 1, K is 6 I minus
+    the interior adjacency (the 7-point Laplacian times -h^2)."""
+    if eps_nodes is None:
+        eps_nodes = np.ones((nz, ny, nx), dtype=np.float64)
+    if ub_nodes is None:
+        ub_nodes = np.zeros((nz, ny, nx), dtype=np.float64)
+    mz, my, mx = nz - 2, ny - 2, nx - 2
+    N = mz * my * mx
+    K = np.zeros((N, N), dtype=np.float64)
+    bB = np.zeros(N, dtype=np.float64)
+
+    def bnd(k, i, j):
+        return k in (0, nz - 1) or i in (0, ny - 1) or j in (0, nx - 1)
+
+    for k in range(1, nz - 1):
+        for i in range(1, ny - 1):
+            for j in range(1, nx - 1):
+                p = ((k - 1) * my + (i - 1)) * mx + (j - 1)
+                for (a, b, c) in ((k - 1, i, j), (k + 1, i, j), (k, i - 1, j), (k, i + 1, j), (k, i, j - 1),
+                                  (k, i, j + 1)):
+                    ef = 0.5 * (eps_nodes[k, i, j] + eps_nodes[a, b, c])
+                    K[p, p] += ef
+                    if bnd(a, b, c):
+                        bB[p] += ef * ub_nodes[a, b, c]
+                    else:
+                        K[p, ((a - 1) * my + (b - 1)) * mx + (c - 1)] -= ef
+    return K, bB

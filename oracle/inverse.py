@@ -64,3 +64,16 @@ def dst_inverse_rows(nx, ny, rows):
         C = (Sy[:, i][:, None] * Sx[:, j][None, :]) * inv        # [a, b]
         out[t] = (Sy.T @ C @ Sx).reshape(-1)                     # [k, l]
     return out
+
+
+def dst_inverse_3d(nx, ny, nz):
+    """Closed-form K^{-1} for the 7-point operator with eps = 1:
+    K = T_z (x) I (x) I + I (x) T_y (x) I + I (x) I (x) T_x with T = tridiag(-1, 2, -1),
+    so K = V diag(lz_a + ly_b + lx_c) V^T with V = S_z (x) S_y (x) S_x (the
+    orthonormal DST-I bases), and K^{-1} = V diag(1 / (lz_a + ly_b + lx_c)) V^T."""
+    Sz, lz = dst_basis(nz - 2)
+    Sy, ly = dst_basis(ny - 2)
+    Sx, lx = dst_basis(nx - 2)
+    V = np.kron(Sz, np.kron(Sy, Sx))
+    lam = (lz[:, None, None] + ly[None, :, None] + lx[None, None, :]).reshape(-1)
+    return (V / lam[None, :]) @ V.T
