@@ -90,7 +90,8 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--workload", default="quant_128",
-                    choices=["quant_128", "plain_32", "vareps_64", "grad_192", "batched", "coupled_32"],
+                    choices=["quant_128", "plain_32", "vareps_64", "grad_192", "batched", "coupled_32",
+                             "poisson3d_26"],
                     help="quant_128 is the headline metric; the others measure the remaining paths")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -369,6 +370,56 @@ def bench_coupled_32(args):
     return line
 
 
+def bench_poisson3d_26(args):
+    """3-D 7-point operator on a 26^3 grid (24^3 = 13824 unknowns), eps = 1,
+    1024 uniform right-hand sides: int8 slices (24-bit x 16-bit) against FP64."""
+    import torch
+    from paper_1602_00001_amd import pinv, workloads
+    n, R = 26, 1024
+    N = (n - 2) ** 3
+    h = 1.0 / (n - 1)
+    t0 = time.perf_counter()
+    op = pinv.PoissonInverse.build3d(n, n, n, h)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    op.quantize(24)
+    rho = torch.from_numpy(workloads.uniform_rhs_n(N, R, workloads.rng(6, 0))).cuda()
+    variant, _ = _autotune(op, args, 16, rho)
+    u8 = torch.empty_like(rho)
+    u64 = torch.empty_like(rho)
+    for _ in range(args.warmup):
+        op.apply(rho, "int8", 16, out=u8)
+        op.apply(rho, "fp64", out=u64)
+    torch.cuda.synchronize()
+    for k in ("gemm_i8", "gemm_f64"):
+        pinv.trace_read(k)
+    pinv.trace_enable(True)
+    dt8 = _timed(lambda: op.apply(rho, "int8", 16, out=u8), args.steps, 0)
+    dt64 = _timed(lambda: op.apply(rho, "fp64", out=u64), args.steps, 0)
+    pinv.trace_enable(False)
+    gms, gcnt = pinv.trace_read("gemm_i8")
+    fms, fcnt = pinv.trace_read("gemm_f64")
+    err = torch.linalg.vector_norm(u8 - u64, dim=1) / torch.linalg.vector_norm(u64, dim=1)
+    op.close()
+    kms8, kms64 = gms / max(gcnt, 1), fms / max(fcnt, 1)
+    ach8 = 2.0 * 6 * N * N * R / (kms8 * 1e-3) / 1e12
+    ach64 = 2.0 * N * N * R / (kms64 * 1e-3) / 1e12
+    line = _base("solves/sec at 24^3 unknowns (3-D 7-point): int8-slice MFMA vs FP64 GEMM", R / dt8, "solves/s", args,
+                 dt8 * 1e3, "i8", {"workload": f"poisson3d_26: 26^3 grid, {N} unknowns, eps=1, {R} uniform[-1,1] RHS, "
+                                               "24-bit inverse x 16-bit rho"})
+    line["fp64_gemm"] = {"value": R / dt64, "unit": "solves/s", "ms_per_step": dt64 * 1e3}
+    line["int8_over_fp64"] = dt64 / dt8
+    line["rel_l2_vs_fp64"] = {"max": float(err.max()), "median": float(err.median())}
+    line["roofline"] = {"kernel": f"gemm_i8_kernel<3,2> variant {variant}", "bound": "mfma", "achieved": ach8,
+                        "peak": PEAK_INT8_TOPS, "unit": "TOP/s", "frac": ach8 / PEAK_INT8_TOPS, "traffic": None,
+                        "avg_launch_ms": kms8}
+    line["roofline_fp64"] = {"kernel": "gemm_f64_nt_kernel<true>", "bound": "mfma", "achieved": ach64,
+                             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach64 / PEAK_FP64_TFLOPS,
+                             "avg_launch_ms": kms64}
+    line["setup_s"] = {"build_inverse": t_build}
+    return line
+
+
 def bench_vareps_64(args):
     """64x64 grid, variable eps, 256 drifting-blob time steps: FP64 against the
     FP32 and BF16 split forms."""
@@ -533,7 +584,7 @@ def bench_batched(args):
 
 
 OTHER = {"plain_32": bench_plain_32, "vareps_64": bench_vareps_64, "grad_192": bench_grad_192,
-         "batched": bench_batched, "coupled_32": bench_coupled_32}
+         "batched": bench_batched, "coupled_32": bench_coupled_32, "poisson3d_26": bench_poisson3d_26}
 
 
 if __name__ == "__main__":

@@ -68,7 +68,7 @@ extern "C" {
 #define PINV_E_NOT_SPD       -2  /* Cholesky met a non-positive pivot          */
 #define PINV_E_OOM           -3  /* device allocation failed or would not fit  */
 #define PINV_E_HIP           -4  /* a HIP runtime call failed                  */
-#define PINV_E_UNSUPPORTED   -5  /* size beyond the integer headroom limits    */
+#define PINV_E_UNSUPPORTED   -5  /* size beyond the integer headroom limits, or an operation the op does not support */
 #define PINV_E_STATE         -6  /* representation needed by the call missing  */
 
 /* ---- enums -------------------------------------------------------------- */
@@ -96,6 +96,8 @@ typedef struct {
   int32_t has_fp32, has_bf16;
   int32_t has_lift;         /* nonzero Dirichlet data (w != 0)                  */
   int64_t device_bytes;     /* device memory held by the op                     */
+  int32_t nz;               /* n_z for a 3-D op, 0 for a 2-D op                 */
+  int32_t _pad;
 } pinv_info;
 
 /* Steps 1-2 of "The solution steps": assemble the interior operator K from the
@@ -111,6 +113,23 @@ typedef struct {
  * N^2 doubles afterwards. */
 int32_t pinv_build_inverse(const pinv_grid* g, const double* eps_nodes,
                            const double* u_boundary, void* stream, pinv_op* out);
+
+/* The same for the 3-D operator (N = n_x n_y n_z in the problem statement;
+ * 7-point conservative stencil, face eps = mean of the two nodal values):
+ *   g           grid with n_z >= 3 (host).
+ *   eps_nodes   host [n_z][n_y][n_x], or NULL for eps = 1.
+ *   u_boundary  host [n_z][n_y][n_x]; only boundary entries are read.  NULL = 0.
+ * Interior unknowns are ordered p = ((k-1)(n_y-2) + (i-1))(n_x-2) + (j-1)
+ * (z slowest, x fastest).  The resulting op supports quantize, apply and the
+ * adjoint like a 2-D op; pinv_grad_eps returns PINV_E_UNSUPPORTED for it. */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t _pad;
+  double h;
+} pinv_grid3;
+
+int32_t pinv_build_inverse_3d(const pinv_grid3* g, const double* eps_nodes,
+                              const double* u_boundary, void* stream, pinv_op* out);
 
 /* Create an op from an inverse computed elsewhere (step 2 by "any standard
  * matrix inversion method"; also restores a saved op).
@@ -174,6 +193,7 @@ int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits,
  * over the faces f = (p, q) of the operator (lambda = 0 and u = u_B on the
  * boundary), and grad_nodes[i][j] = half the sum over the faces touching the
  * node.  grad_nodes: device [n_y][n_x], overwritten (no accumulation).
+ * 2-D ops only (PINV_E_UNSUPPORTED for an op from pinv_build_inverse_3d).
  * Deterministic (fixed summation order).  For nrhs > 16 a stream-ordered
  * scratch of ceil(nrhs/16) * n_x * n_y doubles is taken from the device's
  * memory pool for the duration of the call.  Asynchronous. */

@@ -49,6 +49,40 @@ __global__ void assemble_kernel(int nx, int ny, const double* __restrict__ eps, 
   if (bB) bB[p] = b;
 }
 
+// The 7-point form on an n_z x n_y x n_x grid (nodal arrays [n_z][n_y][n_x];
+// interior index p = ((k-1)(n_y-2) + (i-1))(n_x-2) + (j-1)): the same face
+// rule over the 6 faces of each interior node.
+__global__ void assemble_3d_kernel(int nx, int ny, int nz, const double* __restrict__ eps,
+                                   const double* __restrict__ ub, double* __restrict__ K, int64_t ldk,
+                                   double* __restrict__ bB) {
+  const int mx = nx - 2, my = ny - 2, mz = nz - 2;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= mx * my * mz) return;
+  const int k = p / (mx * my) + 1, i = (p / mx) % my + 1, j = p % mx + 1;
+  const int nk[6] = {k - 1, k + 1, k, k, k, k};
+  const int ni[6] = {i, i, i - 1, i + 1, i, i};
+  const int nj[6] = {j, j, j, j, j - 1, j + 1};
+  const int64_t node = ((int64_t)k * ny + i) * nx + j;
+  const double ep = eps ? eps[node] : 1.0;
+  double diag = 0.0, b = 0.0;
+  for (int t = 0; t < 6; ++t) {
+    const int a = nk[t], c = ni[t], d = nj[t];
+    const int64_t q_node = ((int64_t)a * ny + c) * nx + d;
+    const double eq = eps ? eps[q_node] : 1.0;
+    const double ef = 0.5 * (ep + eq);
+    diag += ef;
+    const bool bnd = (a == 0 || a == nz - 1 || c == 0 || c == ny - 1 || d == 0 || d == nx - 1);
+    if (bnd) {
+      if (ub) b += ef * ub[q_node];
+    } else {
+      const int q = ((a - 1) * my + (c - 1)) * mx + (d - 1);
+      if (K) K[(int64_t)p * ldk + q] = -ef;
+    }
+  }
+  if (K) K[(int64_t)p * ldk + p] = diag;
+  if (bB) bB[p] = b;
+}
+
 // Factor the kn x kn diagonal block at (k0, k0) in place (lower triangle, zero
 // upper) and write its triangular inverse to Wd (64 x 64, zero padded).
 __global__ __launch_bounds__(256) void diag_block_kernel(double* __restrict__ A, int64_t lda, int k0, int kn,
@@ -117,8 +151,13 @@ __global__ void set_identity_kernel(double* __restrict__ A, int64_t lda, int n) 
 
 }  // namespace
 
-hipError_t launch_assemble(int nx, int ny, const double* eps, const double* ub, double* K, int64_t ldk,
+hipError_t launch_assemble(int nx, int ny, int nz, const double* eps, const double* ub, double* K, int64_t ldk,
                            double* bB, hipStream_t s) {
+  if (nz > 0) {
+    const int n = (nx - 2) * (ny - 2) * (nz - 2);
+    hipLaunchKernelGGL(assemble_3d_kernel, dim3((n + 255) / 256), dim3(256), 0, s, nx, ny, nz, eps, ub, K, ldk, bB);
+    return hipGetLastError();
+  }
   const int n = (nx - 2) * (ny - 2);
   hipLaunchKernelGGL(assemble_kernel, dim3((n + 255) / 256), dim3(256), 0, s, nx, ny, eps, ub, K, ldk, bB);
   return hipGetLastError();
@@ -152,7 +191,7 @@ int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub
   PINV_BAIL(hipMemsetAsync(flag, 0, sizeof(int), s));
   PINV_BAIL(hipMemsetAsync(Kb, 0, mat_bytes, s));
   PINV_BAIL(hipMemsetAsync(Wb, 0, mat_bytes, s));
-  PINV_BAIL(launch_assemble(op->nx, op->ny, eps_dev, ub_dev, Kb, ld, bB, s));
+  PINV_BAIL(launch_assemble(op->nx, op->ny, op->nz, eps_dev, ub_dev, Kb, ld, bB, s));
 
   // Cholesky, L overwrites the lower triangle of Kb
   for (int kb = 0; kb < nblk; ++kb) {

@@ -288,6 +288,11 @@ const char* pinv_status_string(int32_t st) {
   }
 }
 
+// Steps 1-2 for a new op (2-D or 3-D): device copies of the nodal data, the
+// device build, the Dirichlet data kept for the eps-gradient.
+int32_t build_op(pinv_op op, int nodes, bool has_ub, const double* eps_nodes, const double* u_boundary,
+                 hipStream_t s, pinv_op* out);
+
 int32_t pinv_build_inverse(const pinv_grid* g, const double* eps_nodes, const double* u_boundary, void* stream,
                            pinv_op* out) {
   if (!out) return PINV_E_INVALID_ARG;
@@ -296,7 +301,41 @@ int32_t pinv_build_inverse(const pinv_grid* g, const double* eps_nodes, const do
   hipStream_t s = as_stream(stream);
   pinv_op op = new_op(g);
   if (!op) return PINV_E_OOM;
-  const int nodes = g->nx * g->ny;
+  return build_op(op, g->nx * g->ny, boundary_nonzero(g, u_boundary), eps_nodes, u_boundary, s, out);
+}
+
+int32_t pinv_build_inverse_3d(const pinv_grid3* g, const double* eps_nodes, const double* u_boundary, void* stream,
+                              pinv_op* out) {
+  if (!out) return PINV_E_INVALID_ARG;
+  *out = nullptr;
+  if (!g || g->nx < 3 || g->ny < 3 || g->nz < 3 || !(g->h > 0.0) || !std::isfinite(g->h)) return PINV_E_INVALID_ARG;
+  const int64_t n = (int64_t)(g->nx - 2) * (g->ny - 2) * (g->nz - 2);
+  if (n > (int64_t)1 << 20) return PINV_E_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  pinv_grid g2{g->nx, g->ny, g->h};
+  pinv_op op = new_op(&g2);
+  if (!op) return PINV_E_OOM;
+  op->nz = g->nz;
+  op->mz = g->nz - 2;
+  op->n = (int)n;
+  op->ldg = (op->n + 31) / 32 * 32;
+  const int nodes = g->nx * g->ny * g->nz;
+  bool has_ub = false;
+  if (u_boundary)
+    for (int k = 0; k < g->nz && !has_ub; ++k)
+      for (int i = 0; i < g->ny && !has_ub; ++i)
+        for (int j = 0; j < g->nx; ++j) {
+          const bool b = k == 0 || k == g->nz - 1 || i == 0 || i == g->ny - 1 || j == 0 || j == g->nx - 1;
+          if (b && u_boundary[((int64_t)k * g->ny + i) * g->nx + j] != 0.0) {
+            has_ub = true;
+            break;
+          }
+        }
+  return build_op(op, nodes, has_ub, eps_nodes, u_boundary, s, out);
+}
+
+int32_t build_op(pinv_op op, int nodes, bool has_ub, const double* eps_nodes, const double* u_boundary,
+                 hipStream_t s, pinv_op* out) {
   const size_t need = 2 * (size_t)op->n * op->ldg * sizeof(double);
   size_t freeb = 0, totalb = 0;
   if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need > freeb) {
@@ -305,7 +344,7 @@ int32_t pinv_build_inverse(const pinv_grid* g, const double* eps_nodes, const do
   }
   double *eps_d = nullptr, *ub_d = nullptr;
   int32_t st = copy_nodal(eps_nodes, nodes, &eps_d, s);
-  if (st == PINV_OK && boundary_nonzero(g, u_boundary)) st = copy_nodal(u_boundary, nodes, &ub_d, s);
+  if (st == PINV_OK && has_ub) st = copy_nodal(u_boundary, nodes, &ub_d, s);
   if (st == PINV_OK) st = build_inverse_device(op, eps_d, ub_d, s);
   if (eps_d) {
     (void)hipStreamSynchronize(s);
@@ -362,7 +401,7 @@ int32_t pinv_import_inverse(const pinv_grid* g, const double* G_host, int64_t ld
         st = copy_nodal(eps_nodes, nodes, &eps_d, s);
         if (st == PINV_OK) {
           e = hipMalloc(&bB, (size_t)n * sizeof(double));
-          if (e == hipSuccess) e = launch_assemble(g->nx, g->ny, eps_d, op->ub, nullptr, 0, bB, s);
+          if (e == hipSuccess) e = launch_assemble(g->nx, g->ny, 0, eps_d, op->ub, nullptr, 0, bB, s);
           if (e == hipSuccess) e = launch_gemv_f64(op->G, op->ldg, n, bB, n, 1, 1.0, nullptr, op->w, n, s);
           (void)hipStreamSynchronize(s);
           if (bB) (void)hipFree(bB);
@@ -549,6 +588,7 @@ int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u, const double* l
                       int32_t nrhs, double* grad_nodes, void* stream) {
   if (!op || !grad_nodes || nrhs < 0) return PINV_E_INVALID_ARG;
   if (nrhs > 0 && (!u || !lambda || ld_u < op->n || ld_lambda < op->n)) return PINV_E_INVALID_ARG;
+  if (op->nz) return PINV_E_UNSUPPORTED;
   hipStream_t s = as_stream(stream);
   const int chunks = grad_eps_chunks(nrhs);
   void* part = nullptr;
@@ -732,6 +772,7 @@ int32_t pinv_get_info(pinv_op op, pinv_info* info) {
   info->has_bf16 = op->nbf;
   info->has_lift = op->w != nullptr;
   info->device_bytes = op->bytes;
+  info->nz = op->nz;
   return PINV_OK;
 }
 

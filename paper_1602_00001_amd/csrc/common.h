@@ -22,6 +22,7 @@ static inline int64_t pinv_pad_dim(int64_t n) { return (n + 255) / 256 * 256; }
 
 struct pinv_op_s {
   int nx = 0, ny = 0, mx = 0, my = 0, n = 0;
+  int nz = 0, mz = 1;        // 3-D grids: n_z nodes along z (0 for a 2-D grid)
   double h = 0.0;
   int device = 0;
 
@@ -112,7 +113,9 @@ hipError_t launch_gemv_f64(const double* G, int64_t ldg, int n, const double* x,
                            hipStream_t s);
 
 // ---- setup kernels ------------------------------------------------------------
-hipError_t launch_assemble(int nx, int ny, const double* eps, const double* ub, double* K,
+// nz = 0: the 5-point operator of an n_y x n_x grid; nz >= 3: the 7-point
+// operator of an n_z x n_y x n_x grid
+hipError_t launch_assemble(int nx, int ny, int nz, const double* eps, const double* ub, double* K,
                            int64_t ldk, double* bB, hipStream_t s);
 int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub_dev,
                              hipStream_t s);

@@ -33,10 +33,16 @@ class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("h", ctypes.c_double)]
 
 
+class Grid3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("_pad", ctypes.c_int32),
+                ("h", ctypes.c_double)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n", ctypes.c_int32), ("h", ctypes.c_double),
                 ("has_fp64", ctypes.c_int32), ("int8_slices", ctypes.c_int32), ("has_fp32", ctypes.c_int32),
-                ("has_bf16", ctypes.c_int32), ("has_lift", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("has_bf16", ctypes.c_int32), ("has_lift", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("nz", ctypes.c_int32), ("_pad", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -52,6 +58,7 @@ def _load():
     P = ctypes.POINTER
     sig = {
         "pinv_build_inverse": ([P(Grid), dp, dp, vp, P(vp)], i32),
+        "pinv_build_inverse_3d": ([P(Grid3), dp, dp, vp, P(vp)], i32),
         "pinv_import_inverse": ([P(Grid), dp, i64, dp, dp, dp, vp, P(vp)], i32),
         "pinv_export_inverse": ([vp, dp, i64, dp, vp], i32),
         "pinv_quantize_inverse": ([vp, i32, i32, i32, vp], i32),
@@ -80,7 +87,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("pinv_build_inverse", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
+EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
             "pinv_prepare_split", "pinv_export_quantized", "pinv_apply_inverse", "pinv_apply_inverse_adjoint",
             "pinv_grad_eps", "pinv_apply_batched", "pinv_get_info", "pinv_destroy", "pinv_status_string",
             "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_int8_variants",
@@ -161,10 +168,10 @@ def _vectors(t, n, name):
 class PoissonInverse:
     """A precomputed dense inverse of the 5-point operator on one grid."""
 
-    def __init__(self, handle, nx, ny, h):
+    def __init__(self, handle, nx, ny, h, nz=0):
         self._h = handle
-        self.nx, self.ny, self.h = nx, ny, h
-        self.n = (nx - 2) * (ny - 2)
+        self.nx, self.ny, self.nz, self.h = nx, ny, nz, h
+        self.n = (nx - 2) * (ny - 2) * (nz - 2 if nz else 1)
 
     # -- construction ---------------------------------------------------------
     @classmethod
@@ -179,6 +186,27 @@ class PoissonInverse:
         _check(lib.pinv_build_inverse(ctypes.byref(g), _ptr(e), _ptr(ub), _stream(stream), ctypes.byref(out)),
                "pinv_build_inverse")
         return cls(out, nx, ny, h)
+
+    @classmethod
+    def build3d(cls, nx, ny, nz, h=None, eps=None, u_boundary=None, stream=None):
+        """Steps 1-2 for the 3-D 7-point operator; nodal arrays are [nz, ny, nx]."""
+        if h is None:
+            h = 1.0 / (max(nx, ny, nz) - 1)
+        g = Grid3(nx, ny, nz, 0, h)
+
+        def nodal(a):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+            if a.shape != (nz, ny, nx):
+                raise ValueError(f"nodal array must have shape ({nz}, {ny}, {nx}), got {a.shape}")
+            return a
+
+        e, ub = nodal(eps), nodal(u_boundary)
+        out = ctypes.c_void_p()
+        _check(lib.pinv_build_inverse_3d(ctypes.byref(g), _ptr(e), _ptr(ub), _stream(stream), ctypes.byref(out)),
+               "pinv_build_inverse_3d")
+        return cls(out, nx, ny, h, nz)
 
     @classmethod
     def from_inverse(cls, nx, ny, h, G, eps=None, u_boundary=None, w=None, stream=None):

@@ -101,6 +101,11 @@ def uniform_rhs(n, nrhs, g):
     return g.uniform(-1.0, 1.0, (nrhs, (n - 2) * (n - 2)))
 
 
+def uniform_rhs_n(N, nrhs, g):
+    """[nrhs][N] iid uniform[-1, 1] values for N unknowns (any dimension)."""
+    return g.uniform(-1.0, 1.0, (nrhs, N))
+
+
 # --- the five workloads -----------------------------------------------------
 
 def plain_32():

@@ -66,6 +66,11 @@ def test_host_side_argument_errors(pinv):
     assert lib.pinv_get_info(None, None) == pinv.E_INVALID_ARG
     assert lib.pinv_apply_batched(None, 3, 4, 16, None) == pinv.E_INVALID_ARG
     assert lib.pinv_apply_batched(None, 0, 4, 16, None) == pinv.OK
+    g3 = pinv.Grid3(10, 10, 2, 0, 0.1)
+    assert lib.pinv_build_inverse_3d(ctypes.byref(g3), None, None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
+    g3 = pinv.Grid3(200, 200, 200, 0, 0.1)      # 198^3 interior unknowns > 2^20
+    assert lib.pinv_build_inverse_3d(ctypes.byref(g3), None, None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
+    assert lib.pinv_build_inverse_3d(None, None, None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
     assert lib.pinv_int8_variants() >= 1
     assert lib.pinv_set_int8_variant(None, 16, 0) == pinv.E_INVALID_ARG
     assert lib.pinv_autotune_int8(None, 16, None, 0, 128, 1, None, 0, None, None) == pinv.E_INVALID_ARG

@@ -1,0 +1,88 @@
+"""The 3-D operator (N = n_x n_y n_z): the GPU build against the oracle's LU
+inverse (random eps, random Dirichlet data, with the lift) and against the
+closed-form inverse for eps = 1; the FP64 apply and the bit-exact int8 apply on
+a 3-D op; the eps-gradient is refused for 3-D ops."""
+
+import numpy as np
+import pytest
+
+from oracle import apply, grid, inverse, metrics
+from tests.gpu_util import announce, dev, host, oracle_int8, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def pinv():
+    from paper_1602_00001_amd import pinv as p
+    return p
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(3, 3, 3), (9, 8, 7), (6, 11, 5)])
+def test_build_3d_matches_oracle(torch, pinv, nx, ny, nz):
+    announce(f"build 3-D nx={nx} ny={ny} nz={nz}")
+    g = np.random.default_rng(nx * ny * nz)
+    eps = g.uniform(0.5, 2.0, (nz, ny, nx))
+    ub = g.standard_normal((nz, ny, nx))
+    h = 1.0 / (max(nx, ny, nz) - 1)
+    K, bB = grid.conservative_operator_3d(nx, ny, nz, eps, ub)
+    G = inverse.lu_inverse(K)
+    w = apply.lift(G, bB)
+    with pinv.PoissonInverse.build3d(nx, ny, nz, h, eps, ub) as op:
+        assert op.n == G.shape[0] and op.info()["nz"] == nz
+        Gg, wg = op.export_inverse()
+        assert np.max(np.abs(Gg - G)) <= 1e-12 * np.max(np.abs(G))
+        assert np.max(np.abs(wg - w)) <= 1e-12 * max(np.max(np.abs(w)), 1e-300)
+        rho = g.uniform(-1, 1, (7, op.n))
+        u = host(op.apply(dev(rho), "fp64"))
+        ref = apply.plain_apply(G, rho.T, h, w)
+        assert np.max(metrics.rel_l2_per_rhs(u.T, ref)) <= 1e-12
+
+
+def test_build_3d_eps_one_matches_closed_form(torch, pinv):
+    n = 14
+    announce(f"build 3-D {n}^3, eps = 1, against the DST inverse")
+    D = inverse.dst_inverse_3d(n, n, n)
+    with pinv.PoissonInverse.build3d(n, n, n) as op:
+        Gg, _ = op.export_inverse()
+    assert np.linalg.norm(Gg - D) <= 1e-12 * np.linalg.norm(D)
+
+
+@pytest.mark.parametrize("bits,rho_bits", [(24, 16), (16, 16), (8, 24)])
+def test_int8_apply_3d(torch, pinv, bits, rho_bits):
+    """The int8 path on a 3-D inverse: bit for bit against the oracle's integer
+    apply on the oracle's inverse (imported into an op; the apply depends only on
+    N and h), and on the GPU-built 3-D op within the rounding envelope of the
+    FP64 solve."""
+    nx, ny, nz = 12, 10, 9
+    announce(f"int8 apply 3-D {nx}x{ny}x{nz} bits={bits} rho_bits={rho_bits}")
+    g = np.random.default_rng(bits + rho_bits)
+    eps = g.uniform(0.5, 2.0, (nz, ny, nx))
+    h = 1.0 / (nx - 1)
+    K, _ = grid.conservative_operator_3d(nx, ny, nz, eps)
+    G = inverse.lu_inverse(K)
+    N = G.shape[0]
+    rho = g.uniform(-1, 1, (150, N))
+    ref, _, _ = oracle_int8(G, bits // 8, rho.T, rho_bits // 8, h)
+    with pinv.PoissonInverse.from_inverse(N + 2, 3, h, G) as op:      # N x 1 interior: a container for G
+        op.quantize(bits)
+        u = host(op.apply(dev(rho), "int8", rho_bits))
+    assert np.array_equal(u.T, ref)
+
+    u64 = apply.plain_apply(G, rho.T, h, None)
+    # envelopes for per-row b-bit entries and uniform rho (cancellation in G rho
+    # amplifies the per-entry 2^-b; the oracle's own integer apply measures
+    # 7.1e-2, 3.0e-4 and 2.4e-5 here)
+    bound = {8: 0.2, 16: 2e-3, 24: 2e-4}[min(bits, rho_bits)]
+    with pinv.PoissonInverse.build3d(nx, ny, nz, h, eps) as op:
+        op.quantize(bits)
+        u = host(op.apply(dev(rho), "int8", rho_bits))
+        assert np.max(metrics.rel_l2_per_rhs(u.T, u64)) <= bound
+        with pytest.raises(pinv.PinvError) as ei:
+            op.grad_eps(dev(rho[:2]), dev(rho[:2]), out=torch.empty((ny, nx), dtype=torch.float64, device="cuda"))
+        assert ei.value.status == pinv.E_UNSUPPORTED
