@@ -205,3 +205,53 @@ def conservative_operator_3d(nx, ny, nz, eps_nodes=None, ub_nodes=None):
                     else:
                         K[p, ((a - 1) * my + (b - 1)) * mx + (c - 1)] -= ef
     return K, bB
+
+
+# --- non-uniform tensor grids and per-direction permittivity (Eq. 1's eps_i) ---
+
+def conservative_operator_general(x, y, eps_x=None, eps_y=None, ub_nodes=None):
+    """Finite-volume form of Eq. 1 with eps_i per direction on a tensor grid with
+    node coordinates x[0..n_x-1], y[0..n_y-1] (strictly increasing).
+
+    Interior node p = (i, j) owns the control volume
+        A_p = (x_{j+1} - x_{j-1}) / 2 * (y_{i+1} - y_{i-1}) / 2.
+    The face towards its x-neighbour q = (i, j +- 1) carries
+        c = eps_x,f * ((y_{i+1} - y_{i-1}) / 2) / |x_q - x_j|,
+    towards a y-neighbour c = eps_y,f * ((x_{j+1} - x_{j-1}) / 2) / |y_q - y_i|,
+    with eps_f the mean of the two nodal values of that direction's field.
+    Summing the face fluxes of Eq. 1 over the control volume:
+        K[p,p] = sum c,  K[p,q] = -c (q interior),  b_B[p] = sum c * u_B(q) (q on the boundary),
+        K u = -A rho + b_B.
+    On a uniform grid (spacing h) with eps_x = eps_y = eps this is
+    :func:`conservative_operator` with A = h^2.  Returns (K, b_B, A)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    nx, ny = x.size, y.size
+    if eps_x is None:
+        eps_x = np.ones((ny, nx), dtype=np.float64)
+    if eps_y is None:
+        eps_y = eps_x
+    if ub_nodes is None:
+        ub_nodes = np.zeros((ny, nx), dtype=np.float64)
+    my, mx = interior_shape(nx, ny)
+    N = my * mx
+    K = np.zeros((N, N), dtype=np.float64)
+    bB = np.zeros(N, dtype=np.float64)
+    A = np.zeros(N, dtype=np.float64)
+    for i in range(1, ny - 1):
+        for j in range(1, nx - 1):
+            p = (i - 1) * mx + (j - 1)
+            wx = 0.5 * (x[j + 1] - x[j - 1])
+            wy = 0.5 * (y[i + 1] - y[i - 1])
+            A[p] = wx * wy
+            for (k, l) in neighbours(i, j):
+                if k == i:
+                    c = 0.5 * (eps_x[i, j] + eps_x[k, l]) * wy / abs(x[l] - x[j])
+                else:
+                    c = 0.5 * (eps_y[i, j] + eps_y[k, l]) * wx / abs(y[k] - y[i])
+                K[p, p] += c
+                if is_boundary(nx, ny, k, l):
+                    bB[p] += c * ub_nodes[k, l]
+                else:
+                    K[p, (k - 1) * mx + (l - 1)] -= c
+    return K, bB, A
