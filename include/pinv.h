@@ -97,7 +97,7 @@ typedef struct {
   int32_t has_lift;         /* nonzero Dirichlet data (w != 0)                  */
   int64_t device_bytes;     /* device memory held by the op                     */
   int32_t nz;               /* n_z for a 3-D op, 0 for a 2-D op                 */
-  int32_t _pad;
+  int32_t general;          /* built by pinv_build_inverse_general (h = 1)      */
 } pinv_info;
 
 /* Steps 1-2 of "The solution steps": assemble the interior operator K from the
@@ -130,6 +130,29 @@ typedef struct {
 
 int32_t pinv_build_inverse_3d(const pinv_grid3* g, const double* eps_nodes,
                               const double* u_boundary, void* stream, pinv_op* out);
+
+/* Steps 1-2 for Eq. 1 with a permittivity per direction (eps_x, eps_y) on a
+ * non-uniform tensor grid (node coordinates x[n_x], y[n_y], strictly
+ * increasing), in finite-volume form: node (i, j) owns the control volume
+ * A = (x[j+1]-x[j-1])/2 * (y[i+1]-y[i-1])/2; an x-face carries
+ * eps_x,f * (y[i+1]-y[i-1])/2 / |x_q - x_j|, a y-face
+ * eps_y,f * (x[j+1]-x[j-1])/2 / |y_q - y_i| (eps_f the mean of the two nodal
+ * values), so K u = -A rho + b_B.  The op stores G = K^{-1} diag(A) with h = 1,
+ * so pinv_apply_inverse gives u = -G rho + w as for the uniform forms (the
+ * adjoint applies the transpose of this G).
+ *   eps_x, eps_y  host [n_y][n_x]; NULL eps_x = 1, NULL eps_y = eps_x.
+ *   u_boundary    host [n_y][n_x]; only boundary entries are read.  NULL = 0.
+ * pinv_grad_eps returns PINV_E_UNSUPPORTED for the op.  On a uniform grid with
+ * eps_x = eps_y this builds h^2 times the G of pinv_build_inverse. */
+typedef struct {
+  int32_t nx, ny;
+  const double* x;    /* host [n_x] */
+  const double* y;    /* host [n_y] */
+} pinv_grid_general;
+
+int32_t pinv_build_inverse_general(const pinv_grid_general* g, const double* eps_x,
+                                   const double* eps_y, const double* u_boundary,
+                                   void* stream, pinv_op* out);
 
 /* Create an op from an inverse computed elsewhere (step 2 by "any standard
  * matrix inversion method"; also restores a saved op).
@@ -193,7 +216,8 @@ int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits,
  * over the faces f = (p, q) of the operator (lambda = 0 and u = u_B on the
  * boundary), and grad_nodes[i][j] = half the sum over the faces touching the
  * node.  grad_nodes: device [n_y][n_x], overwritten (no accumulation).
- * 2-D ops only (PINV_E_UNSUPPORTED for an op from pinv_build_inverse_3d).
+ * Uniform 2-D ops only (PINV_E_UNSUPPORTED for ops from
+ * pinv_build_inverse_3d and pinv_build_inverse_general).
  * Deterministic (fixed summation order).  For nrhs > 16 a stream-ordered
  * scratch of ceil(nrhs/16) * n_x * n_y doubles is taken from the device's
  * memory pool for the duration of the call.  Asynchronous. */

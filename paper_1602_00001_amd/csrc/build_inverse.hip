@@ -83,6 +83,56 @@ __global__ void assemble_3d_kernel(int nx, int ny, int nz, const double* __restr
   if (bB) bB[p] = b;
 }
 
+// Non-uniform tensor grid, permittivity per direction (finite-volume form):
+// node (i, j) owns the control volume A = (x[j+1]-x[j-1])/2 * (y[i+1]-y[i-1])/2;
+// an x-face carries eps_x,f * (y[i+1]-y[i-1])/2 / |x_q - x_j|, a y-face
+// eps_y,f * (x[j+1]-x[j-1])/2 / |y_q - y_i|, eps_f the mean of the two nodal
+// values of that direction's field.  Writes the areas to A.
+__global__ void assemble_general_kernel(int nx, int ny, const double* __restrict__ x, const double* __restrict__ y,
+                                        const double* __restrict__ epsx, const double* __restrict__ epsy,
+                                        const double* __restrict__ ub, double* __restrict__ K, int64_t ldk,
+                                        double* __restrict__ bB, double* __restrict__ A) {
+  const int mx = nx - 2, my = ny - 2;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= mx * my) return;
+  if (!epsy) epsy = epsx;  // one field for both directions (null: eps = 1)
+  const int i = p / mx + 1, j = p % mx + 1;
+  const double wx = 0.5 * (x[j + 1] - x[j - 1]);
+  const double wy = 0.5 * (y[i + 1] - y[i - 1]);
+  const int ni[4] = {i - 1, i + 1, i, i};
+  const int nj[4] = {j, j, j - 1, j + 1};
+  double diag = 0.0, b = 0.0;
+  for (int t = 0; t < 4; ++t) {
+    const int k = ni[t], l = nj[t];
+    double c;
+    if (k == i) {
+      const double ep = epsx ? epsx[(int64_t)i * nx + j] : 1.0, eq = epsx ? epsx[(int64_t)k * nx + l] : 1.0;
+      c = 0.5 * (ep + eq) * wy / fabs(x[l] - x[j]);
+    } else {
+      const double ep = epsy ? epsy[(int64_t)i * nx + j] : 1.0, eq = epsy ? epsy[(int64_t)k * nx + l] : 1.0;
+      c = 0.5 * (ep + eq) * wx / fabs(y[k] - y[i]);
+    }
+    diag += c;
+    const bool bnd = (k == 0 || k == ny - 1 || l == 0 || l == nx - 1);
+    if (bnd) {
+      if (ub) b += c * ub[(int64_t)k * nx + l];
+    } else {
+      K[(int64_t)p * ldk + (k - 1) * mx + (l - 1)] = -c;
+    }
+  }
+  K[(int64_t)p * ldk + p] = diag;
+  bB[p] = b;
+  A[p] = wx * wy;
+}
+
+// G[i][q] *= A[q]: the inverse then maps rho straight to u (u = -G rho + w)
+__global__ void scale_columns_kernel(double* __restrict__ G, int64_t ld, int n, const double* __restrict__ A) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), q = (int)(idx % n);
+  G[(int64_t)i * ld + q] *= A[q];
+}
+
 // Factor the kn x kn diagonal block at (k0, k0) in place (lower triangle, zero
 // upper) and write its triangular inverse to Wd (64 x 64, zero padded).
 __global__ __launch_bounds__(256) void diag_block_kernel(double* __restrict__ A, int64_t lda, int k0, int kn,
@@ -164,7 +214,10 @@ hipError_t launch_assemble(int nx, int ny, int nz, const double* eps, const doub
 }
 
 // Fills op->G (allocated here), op->w.  eps_dev / ub_dev: device nodal arrays or null.
-int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub_dev, hipStream_t s) {
+// gen: non-uniform grid data (device), or null for the uniform 2-D / 3-D forms;
+// then eps_dev is eps_x.
+int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub_dev, const GeneralGrid* gen,
+                             hipStream_t s) {
   const int n = op->n;
   const int64_t ld = op->ldg;
   const int nblk = (n + NB - 1) / NB;
@@ -191,7 +244,13 @@ int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub
   PINV_BAIL(hipMemsetAsync(flag, 0, sizeof(int), s));
   PINV_BAIL(hipMemsetAsync(Kb, 0, mat_bytes, s));
   PINV_BAIL(hipMemsetAsync(Wb, 0, mat_bytes, s));
-  PINV_BAIL(launch_assemble(op->nx, op->ny, op->nz, eps_dev, ub_dev, Kb, ld, bB, s));
+  if (gen) {
+    hipLaunchKernelGGL(assemble_general_kernel, dim3((n + 255) / 256), dim3(256), 0, s, op->nx, op->ny, gen->x, gen->y,
+                       eps_dev, gen->eps_y, ub_dev, Kb, ld, bB, gen->area);
+    PINV_BAIL(hipGetLastError());
+  } else {
+    PINV_BAIL(launch_assemble(op->nx, op->ny, op->nz, eps_dev, ub_dev, Kb, ld, bB, s));
+  }
 
   // Cholesky, L overwrites the lower triangle of Kb
   for (int kb = 0; kb < nblk; ++kb) {
@@ -251,6 +310,12 @@ int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub
     PINV_BAIL(hipMalloc(&op->w, (size_t)n * sizeof(double)));
     op->bytes += (int64_t)n * sizeof(double);
     PINV_BAIL(launch_gemv_f64(Kb, ld, n, bB, n, 1, 1.0, nullptr, op->w, n, s));
+  }
+  if (gen) {
+    // after the lift (w = K^{-1} b_B): fold the control volumes into G's columns
+    hipLaunchKernelGGL(scale_columns_kernel, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, s, Kb, ld,
+                       n, (const double*)gen->area);
+    PINV_BAIL(hipGetLastError());
   }
   {
     int hflag = 0;

@@ -291,7 +291,7 @@ const char* pinv_status_string(int32_t st) {
 // Steps 1-2 for a new op (2-D or 3-D): device copies of the nodal data, the
 // device build, the Dirichlet data kept for the eps-gradient.
 int32_t build_op(pinv_op op, int nodes, bool has_ub, const double* eps_nodes, const double* u_boundary,
-                 hipStream_t s, pinv_op* out);
+                 hipStream_t s, pinv_op* out, const GeneralGrid* gen = nullptr);
 
 int32_t pinv_build_inverse(const pinv_grid* g, const double* eps_nodes, const double* u_boundary, void* stream,
                            pinv_op* out) {
@@ -334,8 +334,54 @@ int32_t pinv_build_inverse_3d(const pinv_grid3* g, const double* eps_nodes, cons
   return build_op(op, nodes, has_ub, eps_nodes, u_boundary, s, out);
 }
 
+int32_t pinv_build_inverse_general(const pinv_grid_general* g, const double* eps_x, const double* eps_y,
+                                   const double* u_boundary, void* stream, pinv_op* out) {
+  if (!out) return PINV_E_INVALID_ARG;
+  *out = nullptr;
+  if (!g || g->nx < 3 || g->ny < 3 || !g->x || !g->y) return PINV_E_INVALID_ARG;
+  for (int j = 0; j < g->nx; ++j)
+    if (!std::isfinite(g->x[j]) || (j > 0 && !(g->x[j] > g->x[j - 1]))) return PINV_E_INVALID_ARG;
+  for (int i = 0; i < g->ny; ++i)
+    if (!std::isfinite(g->y[i]) || (i > 0 && !(g->y[i] > g->y[i - 1]))) return PINV_E_INVALID_ARG;
+  const int64_t n64 = (int64_t)(g->nx - 2) * (g->ny - 2);
+  if (n64 > (int64_t)1 << 20) return PINV_E_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  pinv_grid g2{g->nx, g->ny, 1.0};
+  pinv_op op = new_op(&g2);
+  if (!op) return PINV_E_OOM;
+  op->general = 1;
+  const int nodes = g->nx * g->ny;
+  GeneralGrid gen{};
+  double *x_d = nullptr, *y_d = nullptr, *ey_d = nullptr, *area_d = nullptr;
+  int32_t st = copy_nodal(g->x, g->nx, &x_d, s);
+  if (st == PINV_OK) st = copy_nodal(g->y, g->ny, &y_d, s);
+  if (st == PINV_OK) st = copy_nodal(eps_y, nodes, &ey_d, s);
+  if (st == PINV_OK) {
+    const hipError_t e = hipMalloc(&area_d, (size_t)op->n * sizeof(double));
+    if (e != hipSuccess) st = pinv_hip_status(e);
+  }
+  if (st != PINV_OK) {
+    if (x_d) (void)hipFree(x_d);
+    if (y_d) (void)hipFree(y_d);
+    if (ey_d) (void)hipFree(ey_d);
+    delete op;
+    return st;
+  }
+  gen.x = x_d;
+  gen.y = y_d;
+  gen.eps_y = ey_d;
+  gen.area = area_d;
+  st = build_op(op, nodes, boundary_nonzero(&g2, u_boundary), eps_x, u_boundary, s, out, &gen);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(x_d);
+  (void)hipFree(y_d);
+  if (ey_d) (void)hipFree(ey_d);
+  (void)hipFree(area_d);
+  return st;
+}
+
 int32_t build_op(pinv_op op, int nodes, bool has_ub, const double* eps_nodes, const double* u_boundary,
-                 hipStream_t s, pinv_op* out) {
+                 hipStream_t s, pinv_op* out, const GeneralGrid* gen) {
   const size_t need = 2 * (size_t)op->n * op->ldg * sizeof(double);
   size_t freeb = 0, totalb = 0;
   if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need > freeb) {
@@ -345,7 +391,7 @@ int32_t build_op(pinv_op op, int nodes, bool has_ub, const double* eps_nodes, co
   double *eps_d = nullptr, *ub_d = nullptr;
   int32_t st = copy_nodal(eps_nodes, nodes, &eps_d, s);
   if (st == PINV_OK && has_ub) st = copy_nodal(u_boundary, nodes, &ub_d, s);
-  if (st == PINV_OK) st = build_inverse_device(op, eps_d, ub_d, s);
+  if (st == PINV_OK) st = build_inverse_device(op, eps_d, ub_d, gen, s);
   if (eps_d) {
     (void)hipStreamSynchronize(s);
     (void)hipFree(eps_d);
@@ -588,7 +634,7 @@ int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u, const double* l
                       int32_t nrhs, double* grad_nodes, void* stream) {
   if (!op || !grad_nodes || nrhs < 0) return PINV_E_INVALID_ARG;
   if (nrhs > 0 && (!u || !lambda || ld_u < op->n || ld_lambda < op->n)) return PINV_E_INVALID_ARG;
-  if (op->nz) return PINV_E_UNSUPPORTED;
+  if (op->nz || op->general) return PINV_E_UNSUPPORTED;
   hipStream_t s = as_stream(stream);
   const int chunks = grad_eps_chunks(nrhs);
   void* part = nullptr;
@@ -773,6 +819,7 @@ int32_t pinv_get_info(pinv_op op, pinv_info* info) {
   info->has_lift = op->w != nullptr;
   info->device_bytes = op->bytes;
   info->nz = op->nz;
+  info->general = op->general;
   return PINV_OK;
 }
 

@@ -23,6 +23,7 @@ static inline int64_t pinv_pad_dim(int64_t n) { return (n + 255) / 256 * 256; }
 struct pinv_op_s {
   int nx = 0, ny = 0, mx = 0, my = 0, n = 0;
   int nz = 0, mz = 1;        // 3-D grids: n_z nodes along z (0 for a 2-D grid)
+  int general = 0;           // non-uniform grid / per-direction eps: G holds K^{-1} diag(A), h = 1
   double h = 0.0;
   int device = 0;
 
@@ -117,7 +118,13 @@ hipError_t launch_gemv_f64(const double* G, int64_t ldg, int n, const double* x,
 // operator of an n_z x n_y x n_x grid
 hipError_t launch_assemble(int nx, int ny, int nz, const double* eps, const double* ub, double* K,
                            int64_t ldk, double* bB, hipStream_t s);
-int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub_dev,
+struct GeneralGrid {
+  const double* x;       // node coordinates [nx] (device)
+  const double* y;       // [ny]
+  const double* eps_y;   // y-direction permittivity [ny][nx], or null (= eps_x)
+  double* area;          // control volumes [n], written by the assembly (device scratch)
+};
+int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub_dev, const GeneralGrid* gen,
                              hipStream_t s);
 
 // ---- quantisation -------------------------------------------------------------

@@ -38,11 +38,15 @@ class Grid3(ctypes.Structure):
                 ("h", ctypes.c_double)]
 
 
+class GridGeneral(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n", ctypes.c_int32), ("h", ctypes.c_double),
                 ("has_fp64", ctypes.c_int32), ("int8_slices", ctypes.c_int32), ("has_fp32", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("has_lift", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
-                ("nz", ctypes.c_int32), ("_pad", ctypes.c_int32)]
+                ("nz", ctypes.c_int32), ("general", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -59,6 +63,7 @@ def _load():
     sig = {
         "pinv_build_inverse": ([P(Grid), dp, dp, vp, P(vp)], i32),
         "pinv_build_inverse_3d": ([P(Grid3), dp, dp, vp, P(vp)], i32),
+        "pinv_build_inverse_general": ([P(GridGeneral), dp, dp, dp, vp, P(vp)], i32),
         "pinv_import_inverse": ([P(Grid), dp, i64, dp, dp, dp, vp, P(vp)], i32),
         "pinv_export_inverse": ([vp, dp, i64, dp, vp], i32),
         "pinv_quantize_inverse": ([vp, i32, i32, i32, vp], i32),
@@ -87,7 +92,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
+EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_build_inverse_general", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
             "pinv_prepare_split", "pinv_export_quantized", "pinv_apply_inverse", "pinv_apply_inverse_adjoint",
             "pinv_grad_eps", "pinv_apply_batched", "pinv_get_info", "pinv_destroy", "pinv_status_string",
             "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_int8_variants",
@@ -207,6 +212,20 @@ class PoissonInverse:
         _check(lib.pinv_build_inverse_3d(ctypes.byref(g), _ptr(e), _ptr(ub), _stream(stream), ctypes.byref(out)),
                "pinv_build_inverse_3d")
         return cls(out, nx, ny, h, nz)
+
+    @classmethod
+    def build_general(cls, x, y, eps_x=None, eps_y=None, u_boundary=None, stream=None):
+        """Steps 1-2 on a non-uniform tensor grid (node coordinates x, y) with
+        permittivity per direction; the op's h is 1 (G holds K^{-1} diag(A))."""
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.float64))
+        nx, ny = x.size, y.size
+        g = GridGeneral(nx, ny, x.ctypes.data_as(ctypes.c_void_p), y.ctypes.data_as(ctypes.c_void_p))
+        ex, ey, ub = (_host_nodal(a, nx, ny) for a in (eps_x, eps_y, u_boundary))
+        out = ctypes.c_void_p()
+        _check(lib.pinv_build_inverse_general(ctypes.byref(g), _ptr(ex), _ptr(ey), _ptr(ub), _stream(stream),
+                                              ctypes.byref(out)), "pinv_build_inverse_general")
+        return cls(out, nx, ny, 1.0)
 
     @classmethod
     def from_inverse(cls, nx, ny, h, G, eps=None, u_boundary=None, w=None, stream=None):

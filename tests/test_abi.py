@@ -71,6 +71,14 @@ def test_host_side_argument_errors(pinv):
     g3 = pinv.Grid3(200, 200, 200, 0, 0.1)      # 198^3 interior unknowns > 2^20
     assert lib.pinv_build_inverse_3d(ctypes.byref(g3), None, None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
     assert lib.pinv_build_inverse_3d(None, None, None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
+    xs = (ctypes.c_double * 4)(0.0, 0.5, 0.4, 1.0)           # not increasing
+    ys = (ctypes.c_double * 3)(0.0, 0.5, 1.0)
+    gg = pinv.GridGeneral(4, 3, ctypes.cast(xs, ctypes.c_void_p), ctypes.cast(ys, ctypes.c_void_p))
+    assert lib.pinv_build_inverse_general(ctypes.byref(gg), None, None, None, None,
+                                          ctypes.byref(out)) == pinv.E_INVALID_ARG
+    gg = pinv.GridGeneral(2, 3, ctypes.cast(xs, ctypes.c_void_p), ctypes.cast(ys, ctypes.c_void_p))
+    assert lib.pinv_build_inverse_general(ctypes.byref(gg), None, None, None, None,
+                                          ctypes.byref(out)) == pinv.E_INVALID_ARG
     assert lib.pinv_int8_variants() >= 1
     assert lib.pinv_set_int8_variant(None, 16, 0) == pinv.E_INVALID_ARG
     assert lib.pinv_autotune_int8(None, 16, None, 0, 128, 1, None, 0, None, None) == pinv.E_INVALID_ARG
