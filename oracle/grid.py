@@ -255,3 +255,39 @@ def conservative_operator_general(x, y, eps_x=None, eps_y=None, ub_nodes=None):
                 else:
                     K[p, (k - 1) * mx + (l - 1)] -= c
     return K, bB, A
+
+
+# --- Eq. 3: the unit-diagonal system with arbitrary neighbour coefficients ---
+
+BETA_DIRECTIONS = ((-1, 0), (1, 0), (0, -1), (0, 1))   # (i-1, j), (i+1, j), (i, j-1), (i, j+1)
+
+
+def beta_operator(nx, ny, beta, ub_nodes=None):
+    """Eq. 3 restricted to the interior unknowns: row p = (i, j) reads
+        u_p - 0.25 * sum_d beta[d][i, j] * u_{q_d} = rho_p,
+    with q_d the neighbour in direction d (BETA_DIRECTIONS).  Boundary
+    neighbours carry their Dirichlet value, moved to the right-hand side:
+        A[p,p] = 1,  A[p,q_d] = -0.25 beta[d][i, j] (q_d interior),
+        b_B[p] = 0.25 * sum over boundary q_d of beta[d][i, j] * u_B(q_d),
+        u = A^{-1} (rho + b_B).
+    beta: [4][n_y][n_x] (one coefficient per row and direction, arbitrary
+    numbers).  With beta = 1 this is the interior part of Fig. 3's system.
+    Returns (A, b_B)."""
+    beta = np.asarray(beta, dtype=np.float64)
+    if ub_nodes is None:
+        ub_nodes = np.zeros((ny, nx), dtype=np.float64)
+    my, mx = interior_shape(nx, ny)
+    N = my * mx
+    A = np.eye(N, dtype=np.float64)
+    bB = np.zeros(N, dtype=np.float64)
+    for i in range(1, ny - 1):
+        for j in range(1, nx - 1):
+            p = (i - 1) * mx + (j - 1)
+            for d, (di, dj) in enumerate(BETA_DIRECTIONS):
+                k, l = i + di, j + dj
+                c = 0.25 * beta[d, i, j]
+                if is_boundary(nx, ny, k, l):
+                    bB[p] += c * ub_nodes[k, l]
+                else:
+                    A[p, (k - 1) * mx + (l - 1)] -= c
+    return A, bB
