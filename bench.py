@@ -34,9 +34,10 @@ def _src_hash(rel):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(summary, kernel_src):
+def _traffic(summary, kernel_src, variant=None):
     """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel source (and, for the int8 kernel, on the
+    variant this run uses); else None."""
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
@@ -44,6 +45,8 @@ def _traffic(summary, kernel_src):
         with open(path) as f:
             d = json.load(f)
         if d.get("kernel_source_sha256_16") != _src_hash(kernel_src):
+            return None
+        if variant is not None and d.get("variant") != variant:
             return None
         return float(d["hbm_bytes_per_launch"])
     except Exception:
@@ -195,7 +198,7 @@ def main():
             "kernel": f"gemm_i8_kernel<{S},{Sr}> variant {variant}",
             "bound": "mfma", "achieved": ach_i8, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
             "frac": ach_i8 / PEAK_INT8_TOPS,
-            "traffic": _traffic("gemm_i8_quant_128.traffic.json", "paper_1602_00001_amd/csrc/gemm_i8.hip"),
+            "traffic": _traffic("gemm_i8_quant_128.traffic.json", "paper_1602_00001_amd/csrc/gemm_i8.hip", variant),
             "algorithmic_ops_per_launch": ops, "avg_launch_ms": gi8_avg, "launches": gi8_n,
         },
         "roofline_fp64": {
