@@ -46,8 +46,9 @@ def _traffic(summary, kernel_src, variant=None):
             d = json.load(f)
         if d.get("kernel_source_sha256_16") != _src_hash(kernel_src):
             return None
-        if variant is not None and d.get("variant") != variant:
-            return None
+        if variant is not None:
+            by = d.get("hbm_bytes_per_launch_by_variant", {})
+            return float(by[str(variant)]) if str(variant) in by else None
         return float(d["hbm_bytes_per_launch"])
     except Exception:
         return None
