@@ -149,3 +149,39 @@ def sampling_loss_central_difference(nx, ny, h, eps_nodes, rho, sample, d, v_eps
     rp = banded_solve_refined(nx, ny, h, e_p, r_p_src, ub_nodes)[idx] - d
     rm = banded_solve_refined(nx, ny, h, e_m, r_m_src, ub_nodes)[idx] - d
     return float(np.sum((rp - rm) * (rp + rm))) / (2.0 * delta)
+
+
+def grad_eps_nodes_3d(nx, ny, nz, h, u_int, lam_int, ub_nodes=None):
+    """Nodal dLoss/deps for the 3-D operator (same face rule as
+    :func:`grad_eps_nodes` over the 6 face directions): for every face f = (p, q)
+    that is not between two boundary nodes,
+        g_f = (1/h^2) sum_r (lambda_p - lambda_q)(u_p - u_q)
+    (lambda = 0 and u = u_B on boundary nodes), half of it to each end node.
+    u_int, lam_int: [N, R] in the interior order of
+    :func:`grid.conservative_operator_3d`.  Returns [n_z][n_y][n_x]."""
+    mz, my, mx = nz - 2, ny - 2, nx - 2
+    u_int = np.asarray(u_int, dtype=np.float64).reshape(mz * my * mx, -1)
+    lam_int = np.asarray(lam_int, dtype=np.float64).reshape(mz * my * mx, -1)
+    R = u_int.shape[1]
+    U = np.zeros((nz, ny, nx, R))
+    if ub_nodes is not None:
+        U[:] = np.asarray(ub_nodes, dtype=np.float64)[..., None]
+    U[1:-1, 1:-1, 1:-1] = u_int.reshape(mz, my, mx, R)
+    L = np.zeros((nz, ny, nx, R))
+    L[1:-1, 1:-1, 1:-1] = lam_int.reshape(mz, my, mx, R)
+    out = np.zeros((nz, ny, nx))
+
+    def bnd(k, i, j):
+        return k in (0, nz - 1) or i in (0, ny - 1) or j in (0, nx - 1)
+
+    for (dk, di, dj) in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+        for k in range(nz - dk):
+            for i in range(ny - di):
+                for j in range(nx - dj):
+                    a, b, c = k + dk, i + di, j + dj
+                    if bnd(k, i, j) and bnd(a, b, c):
+                        continue
+                    gf = float(np.sum((L[k, i, j] - L[a, b, c]) * (U[k, i, j] - U[a, b, c]))) / (h * h)
+                    out[k, i, j] += 0.5 * gf
+                    out[a, b, c] += 0.5 * gf
+    return out

@@ -132,3 +132,35 @@ def test_refined_banded_solve_is_more_accurate():
     res_ref = np.abs(rhs - grad.apply_operator_extended(nx, ny, eps, u_ref)).max()
     assert res_ref <= res_plain
     assert np.max(np.abs(u_ref - u_plain)) <= 1e-12 * np.max(np.abs(u_plain))
+
+
+def test_grad_eps_3d_matches_central_differences():
+    """3-D face rule against central differences of the dense re-solved loss."""
+    g = np.random.default_rng(61)
+    nx, ny, nz = 7, 6, 5
+    h = 1.0 / (nx - 1)
+    eps = 1.0 + 0.5 * g.uniform(0, 1, (nz, ny, nx))
+    ub = g.standard_normal((nz, ny, nx))
+    N = (nx - 2) * (ny - 2) * (nz - 2)
+    rho = g.standard_normal((N, 2))
+    sample = np.sort(g.choice(N, 10, replace=False))
+    d = 0.01 * g.standard_normal((10, 2))
+
+    def solve(e):
+        K, bB = grid.conservative_operator_3d(nx, ny, nz, e, ub)
+        return np.linalg.solve(K, -(h * h) * rho + bB[:, None]), K
+
+    def loss(e):
+        u, _ = solve(e)
+        r = u[sample] - d
+        return float(np.sum(r * r))
+
+    u, K = solve(eps)
+    gu = grad.sampling_loss_grad_u(u, sample, d)
+    lam = grad.adjoint(np.linalg.inv(K), gu, h)
+    ge = grad.grad_eps_nodes_3d(nx, ny, nz, h, u, lam, ub)
+    for t in range(3):
+        v = g.standard_normal((nz, ny, nx))
+        fd = grad.central_difference(loss, eps, v, 1e-6)
+        an = float(np.sum(ge * v))
+        assert abs(fd - an) <= 1e-6 * abs(fd), (fd, an)
