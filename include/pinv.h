@@ -120,8 +120,8 @@ int32_t pinv_build_inverse(const pinv_grid* g, const double* eps_nodes,
  *   eps_nodes   host [n_z][n_y][n_x], or NULL for eps = 1.
  *   u_boundary  host [n_z][n_y][n_x]; only boundary entries are read.  NULL = 0.
  * Interior unknowns are ordered p = ((k-1)(n_y-2) + (i-1))(n_x-2) + (j-1)
- * (z slowest, x fastest).  The resulting op supports quantize, apply and the
- * adjoint like a 2-D op; pinv_grad_eps returns PINV_E_UNSUPPORTED for it. */
+ * (z slowest, x fastest).  The resulting op supports quantize, apply, the
+ * adjoint and the eps-gradient (over the 6 faces of each node) like a 2-D op. */
 typedef struct {
   int32_t nx, ny, nz;
   int32_t _pad;
@@ -215,11 +215,11 @@ int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits,
  *   dLoss/deps_f = (1/h^2) sum_r (lambda_p - lambda_q)(u_p - u_q)
  * over the faces f = (p, q) of the operator (lambda = 0 and u = u_B on the
  * boundary), and grad_nodes[i][j] = half the sum over the faces touching the
- * node.  grad_nodes: device [n_y][n_x], overwritten (no accumulation).
- * Uniform 2-D ops only (PINV_E_UNSUPPORTED for ops from
- * pinv_build_inverse_3d and pinv_build_inverse_general).
+ * node.  grad_nodes: device [n_y][n_x] ([n_z][n_y][n_x] for a 3-D op),
+ * overwritten (no accumulation).  Uniform-grid ops only (PINV_E_UNSUPPORTED
+ * for ops from pinv_build_inverse_general).
  * Deterministic (fixed summation order).  For nrhs > 16 a stream-ordered
- * scratch of ceil(nrhs/16) * n_x * n_y doubles is taken from the device's
+ * scratch of ceil(nrhs/16) doubles per node is taken from the device's
  * memory pool for the duration of the call.  Asynchronous. */
 int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u,
                       const double* lambda, int64_t ld_lambda, int32_t nrhs,

@@ -634,18 +634,19 @@ int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u, const double* l
                       int32_t nrhs, double* grad_nodes, void* stream) {
   if (!op || !grad_nodes || nrhs < 0) return PINV_E_INVALID_ARG;
   if (nrhs > 0 && (!u || !lambda || ld_u < op->n || ld_lambda < op->n)) return PINV_E_INVALID_ARG;
-  if (op->nz || op->general) return PINV_E_UNSUPPORTED;
+  if (op->general) return PINV_E_UNSUPPORTED;
   hipStream_t s = as_stream(stream);
   const int chunks = grad_eps_chunks(nrhs);
+  const size_t nodes = (size_t)op->nx * op->ny * (op->nz ? op->nz : 1);
   void* part = nullptr;
   if (chunks > 1) {
     configure_pool_once();
-    PINV_HIP_TRY(hipMallocAsync(&part, (size_t)chunks * op->nx * op->ny * sizeof(double), s));
+    PINV_HIP_TRY(hipMallocAsync(&part, (size_t)chunks * nodes * sizeof(double), s));
   }
   hipError_t e;
   {
     TraceScope ts("grad_eps", s);
-    e = launch_grad_eps(op->nx, op->ny, op->h, u, ld_u, lambda, ld_lambda, nrhs, op->ub, (double*)part, grad_nodes,
+    e = launch_grad_eps(op->nx, op->ny, op->nz, op->h, u, ld_u, lambda, ld_lambda, nrhs, op->ub, (double*)part, grad_nodes,
                         s);
   }
   const hipError_t e2 = part ? hipFreeAsync(part, s) : hipSuccess;

@@ -209,8 +209,9 @@ hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int
 size_t split_scratch_bytes(int mode, const pinv_op_s* op, int nrhs);
 
 // ---- gradient ------------------------------------------------------------------
-// part: scratch of grad_eps_chunks(nrhs) * nx * ny doubles (unused when that is <= 1)
+// nz = 0 for the 2-D operator.  part: scratch of grad_eps_chunks(nrhs) * (nodes)
+// doubles (unused when that is <= 1)
 int grad_eps_chunks(int nrhs);
-hipError_t launch_grad_eps(int nx, int ny, double h, const double* u, int64_t ldu,
+hipError_t launch_grad_eps(int nx, int ny, int nz, double h, const double* u, int64_t ldu,
                            const double* lam, int64_t ldl, int nrhs, const double* ub,
                            double* part, double* grad, hipStream_t s);

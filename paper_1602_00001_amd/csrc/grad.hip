@@ -9,9 +9,9 @@
 //
 // The right-hand sides are split into chunks of RC; workgroup (b, c) takes 256
 // nodes and chunk c, one thread per node: for each of its right-hand sides the
-// thread reads its own (u, lambda) and those of its four neighbours (the
-// threads of a wave read consecutive nodes, so the loads are coalesced and the
-// neighbours' come from cache) and adds the four face products.  Each chunk's
+// thread reads its own (u, lambda) and those of its 4 (2-D) or 6 (3-D)
+// neighbours (the threads of a wave read consecutive nodes, so the loads are
+// coalesced and the neighbours' come from cache) and adds the face products.  Each chunk's
 // partial sums go to scratch; a second kernel adds the chunks in order and
 // scales.  Every sum has a fixed order, so the result is deterministic.
 
@@ -21,49 +21,67 @@ namespace {
 
 constexpr int RC = 16;
 
-__global__ __launch_bounds__(256) void grad_eps_partial_kernel(int nx, int ny, double h, const double* __restrict__ u,
-                                                              int64_t ldu, const double* __restrict__ lam,
-                                                              int64_t ldl, int nrhs, const double* __restrict__ ub,
+// D = 2: nodes [n_y][n_x], 4 faces per node; D = 3: nodes [n_z][n_y][n_x]
+// (slowest axis z), 6 faces per node.  Interior vectors follow the operator's
+// row-major interior order.
+template <int D>
+__global__ __launch_bounds__(256) void grad_eps_partial_kernel(int nx, int ny, int nz, double h,
+                                                              const double* __restrict__ u, int64_t ldu,
+                                                              const double* __restrict__ lam, int64_t ldl, int nrhs,
+                                                              const double* __restrict__ ub,
                                                               double* __restrict__ out, int final_scale) {
+  constexpr int F = 2 * D;
   const int node = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nodes = nx * ny;
+  const int nodes = nx * ny * (D == 3 ? nz : 1);
   if (node >= nodes) return;
   const int r0 = blockIdx.y * RC;
   const int r1 = min(nrhs, r0 + RC);
-  const int i = node / nx, j = node % nx;
-  const int mx = nx - 2;
-  const bool bp = (i == 0 || i == ny - 1 || j == 0 || j == nx - 1);
-  const int ni[4] = {i - 1, i + 1, i, i};
-  const int nj[4] = {j, j, j - 1, j + 1};
-  const int64_t pp = bp ? 0 : (int64_t)(i - 1) * mx + (j - 1);
+  const int j = node % nx;
+  const int i = (node / nx) % ny;
+  const int k = D == 3 ? node / (nx * ny) : 0;
+  const int mx = nx - 2, my = ny - 2;
+  const int zlo = D == 3 ? 0 : -1, zhi = D == 3 ? nz - 1 : -1;  // no z boundary in 2-D
+  auto boundary = [&](int c, int a, int b) { return c == zlo || c == zhi || a == 0 || a == ny - 1 || b == 0 || b == nx - 1; };
+  auto interior = [&](int c, int a, int b) {
+    return ((int64_t)(D == 3 ? c - 1 : 0) * my + (a - 1)) * mx + (b - 1);
+  };
+  const bool bp = boundary(k, i, j);
+  const int nk[6] = {k, k, k, k, k - 1, k + 1};
+  const int ni[6] = {i - 1, i + 1, i, i, i, i};
+  const int nj[6] = {j, j, j - 1, j + 1, j, j};
+  const int64_t pp = bp ? 0 : interior(k, i, j);
   const double ubp = (bp && ub) ? ub[node] : 0.0;
-  bool use[4], bq[4];
-  int64_t qq[4];
-  double ubq[4];
+  bool use[F], bq[F];
+  int64_t qq[F];
+  double ubq[F];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int k = ni[t], l = nj[t];
-    const bool inside = k >= 0 && k < ny && l >= 0 && l < nx;
-    bq[t] = !inside || k == 0 || k == ny - 1 || l == 0 || l == nx - 1;
+  for (int t = 0; t < F; ++t) {
+    const int c = nk[t], a = ni[t], b = nj[t];
+    const bool inside = a >= 0 && a < ny && b >= 0 && b < nx && (D == 2 || (c >= 0 && c < nz));
+    bq[t] = !inside || boundary(c, a, b);
     use[t] = inside && !(bp && bq[t]);
-    qq[t] = bq[t] ? 0 : (int64_t)(k - 1) * mx + (l - 1);
-    ubq[t] = (use[t] && bq[t] && ub) ? ub[(int64_t)k * nx + l] : 0.0;
+    qq[t] = bq[t] ? 0 : interior(c, a, b);
+    ubq[t] = (use[t] && bq[t] && ub) ? ub[((int64_t)c * ny + a) * nx + b] : 0.0;
   }
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[F];
+#pragma unroll
+  for (int t = 0; t < F; ++t) acc[t] = 0.0;
   for (int r = r0; r < r1; ++r) {
     const double* ur = u + (int64_t)r * ldu;
     const double* lr = lam + (int64_t)r * ldl;
     const double up = bp ? ubp : ur[pp];
     const double lp = bp ? 0.0 : lr[pp];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < F; ++t) {
       if (!use[t]) continue;
       const double uq = bq[t] ? ubq[t] : ur[qq[t]];
       const double lq = bq[t] ? 0.0 : lr[qq[t]];
       acc[t] += (lp - lq) * (up - uq);
     }
   }
-  const double total = ((acc[0] + acc[1]) + acc[2]) + acc[3];
+  double total = acc[0];
+#pragma unroll
+  for (int t = 1; t < F; ++t) total += acc[t];
   if (final_scale)
     out[node] = 0.5 * total / (h * h);
   else
@@ -84,20 +102,23 @@ __global__ __launch_bounds__(256) void grad_eps_reduce_kernel(int nodes, int chu
 
 int grad_eps_chunks(int nrhs) { return (nrhs + RC - 1) / RC; }
 
-hipError_t launch_grad_eps(int nx, int ny, double h, const double* u, int64_t ldu, const double* lam, int64_t ldl,
-                           int nrhs, const double* ub, double* part, double* grad, hipStream_t s) {
-  const int nodes = nx * ny;
+hipError_t launch_grad_eps(int nx, int ny, int nz, double h, const double* u, int64_t ldu, const double* lam,
+                           int64_t ldl, int nrhs, const double* ub, double* part, double* grad, hipStream_t s) {
+  const int nodes = nx * ny * (nz ? nz : 1);
   const int chunks = grad_eps_chunks(nrhs);
   const dim3 blocks((nodes + 255) / 256);
-  if (chunks <= 1) {
-    // zero or one chunk: the partial kernel writes the scaled result directly
-    hipLaunchKernelGGL(grad_eps_partial_kernel, dim3(blocks.x, 1), dim3(256), 0, s, nx, ny, h, u, ldu, lam, ldl,
-                       nrhs, ub, grad, 1);
+  auto partial = [&](dim3 grid, double* dst, int final_scale) {
+    if (nz)
+      hipLaunchKernelGGL(grad_eps_partial_kernel<3>, grid, dim3(256), 0, s, nx, ny, nz, h, u, ldu, lam, ldl, nrhs,
+                         ub, dst, final_scale);
+    else
+      hipLaunchKernelGGL(grad_eps_partial_kernel<2>, grid, dim3(256), 0, s, nx, ny, 0, h, u, ldu, lam, ldl, nrhs, ub,
+                         dst, final_scale);
     return hipGetLastError();
-  }
-  hipLaunchKernelGGL(grad_eps_partial_kernel, dim3(blocks.x, chunks), dim3(256), 0, s, nx, ny, h, u, ldu, lam, ldl,
-                     nrhs, ub, part, 0);
-  hipError_t e = hipGetLastError();
+  };
+  // zero or one chunk: the partial kernel writes the scaled result directly
+  if (chunks <= 1) return partial(dim3(blocks.x, 1), grad, 1);
+  hipError_t e = partial(dim3(blocks.x, chunks), part, 0);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(grad_eps_reduce_kernel, blocks, dim3(256), 0, s, nodes, chunks, h, part, grad);
   return hipGetLastError();

@@ -296,16 +296,18 @@ class PoissonInverse:
         return out
 
     def grad_eps(self, u, lam, out=None, stream=None):
-        """Nodal dLoss/deps [n_y, n_x] from forward solutions and adjoint outputs."""
+        """Nodal dLoss/deps [n_y, n_x] ([n_z, n_y, n_x] for a 3-D op) from forward
+        solutions and adjoint outputs."""
         import torch
         p_u, ld_u, nu = _vectors(u, self.n, "u")
         p_l, ld_l, nl = _vectors(lam, self.n, "lambda")
         if nu != nl:
             raise ValueError("u and lambda must have the same number of rows")
+        shape = (self.nz, self.ny, self.nx) if self.nz else (self.ny, self.nx)
         if out is None:
-            out = torch.empty((self.ny, self.nx), dtype=torch.float64, device=u.device)
-        if out.dtype != torch.float64 or not out.is_contiguous() or tuple(out.shape) != (self.ny, self.nx):
-            raise ValueError("out must be a contiguous float64 [ny, nx] tensor")
+            out = torch.empty(shape, dtype=torch.float64, device=u.device)
+        if out.dtype != torch.float64 or not out.is_contiguous() or tuple(out.shape) != shape:
+            raise ValueError(f"out must be a contiguous float64 {list(shape)} tensor")
         _check(lib.pinv_grad_eps(self._h, p_u, ld_u, p_l, ld_l, nu, ctypes.c_void_p(out.data_ptr()),
                                  _stream(stream)), "pinv_grad_eps")
         return out
