@@ -65,7 +65,7 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------- */
 #define PINV_OK               0
 #define PINV_E_INVALID_ARG   -1  /* bad size, NULL pointer, ld < N, bad enum   */
-#define PINV_E_NOT_SPD       -2  /* Cholesky met a non-positive pivot          */
+#define PINV_E_NOT_SPD       -2  /* Cholesky met a non-positive pivot (LU: zero pivot) */
 #define PINV_E_OOM           -3  /* device allocation failed or would not fit  */
 #define PINV_E_HIP           -4  /* a HIP runtime call failed                  */
 #define PINV_E_UNSUPPORTED   -5  /* size beyond the integer headroom limits, or an operation the op does not support */
@@ -98,6 +98,8 @@ typedef struct {
   int64_t device_bytes;     /* device memory held by the op                     */
   int32_t nz;               /* n_z for a 3-D op, 0 for a 2-D op                 */
   int32_t general;          /* built by pinv_build_inverse_general (h = 1)      */
+  int32_t beta;             /* built by pinv_build_inverse_beta (h = 1)         */
+  int32_t _pad;
 } pinv_info;
 
 /* Steps 1-2 of "The solution steps": assemble the interior operator K from the
@@ -153,6 +155,28 @@ typedef struct {
 int32_t pinv_build_inverse_general(const pinv_grid_general* g, const double* eps_x,
                                    const double* eps_y, const double* u_boundary,
                                    void* stream, pinv_op* out);
+
+/* Steps 1-2 for Eq. 3 with arbitrary neighbour coefficients (the relaxation
+ * form of the discretisation, row-normalised and in general not symmetric),
+ * restricted to the interior unknowns: row p = (i, j) reads
+ *   u_p - sum_d beta[d][i][j] / 4 * u_{q_d} = rho_p,
+ * d over the neighbours (i-1, j), (i+1, j), (i, j-1), (i, j+1) in that order;
+ * a boundary neighbour's Dirichlet value moves to the right-hand side
+ * (b_B[p] += beta[d][i][j] / 4 * u_B(q_d)), so u = A^{-1} (rho + b_B).  The
+ * inverse is formed on the GPU by a blocked LU factorization without row
+ * exchanges (it exists and is stable when A is an M-matrix, e.g. beta >= 0 with
+ * sum_d beta_d <= 4 in every row, as for beta_d = 4 eps_f / sum of the node's
+ * face eps_f), then A^{-1} = U^{-1} L^{-1}.  The op stores G = -A^{-1} with h = 1,
+ * so pinv_apply_inverse gives u = -G rho + w = A^{-1} rho + w with the lift
+ * w = A^{-1} b_B; the adjoint applies the transpose.
+ *   g           grid (host); g->h is not used (the op's h is 1).
+ *   beta        host [4][n_y][n_x], finite; only interior nodes are read.
+ *   u_boundary  host [n_y][n_x]; only boundary entries are read.  NULL = 0.
+ * PINV_E_NOT_SPD if the factorization meets a zero or non-finite pivot;
+ * pinv_grad_eps returns PINV_E_UNSUPPORTED for the op.  Synchronous; device
+ * memory about 2 N^2 doubles at peak, N^2 afterwards. */
+int32_t pinv_build_inverse_beta(const pinv_grid* g, const double* beta,
+                                const double* u_boundary, void* stream, pinv_op* out);
 
 /* Create an op from an inverse computed elsewhere (step 2 by "any standard
  * matrix inversion method"; also restores a saved op).
@@ -217,7 +241,7 @@ int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits,
  * boundary), and grad_nodes[i][j] = half the sum over the faces touching the
  * node.  grad_nodes: device [n_y][n_x] ([n_z][n_y][n_x] for a 3-D op),
  * overwritten (no accumulation).  Uniform-grid ops only (PINV_E_UNSUPPORTED
- * for ops from pinv_build_inverse_general).
+ * for ops from pinv_build_inverse_general and pinv_build_inverse_beta).
  * Deterministic (fixed summation order).  For nrhs > 16 a stream-ordered
  * scratch of ceil(nrhs/16) doubles per node is taken from the device's
  * memory pool for the duration of the call.  Asynchronous. */

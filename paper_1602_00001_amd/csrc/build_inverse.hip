@@ -15,6 +15,13 @@
 // substitution and G = K^{-1} = W^T W by one more GEMM that skips the zero
 // upper triangle of W.  A non-positive (or NaN) pivot raises a device flag
 // that the host reads once at the end.
+//
+// Eq. 3 with arbitrary neighbour coefficients gives a unit-diagonal matrix
+// that is not symmetric: it is factored A = L U (L unit lower) by the same
+// right-looking blocking without row exchanges (the diagonal block's L, U and
+// both triangular inverses in LDS, panels and trailing update as GEMMs), then
+// X = L^{-1} by the forward substitution above and A^{-1} = U^{-1} X by block
+// back substitution, bottom block row first.
 
 #include "common.h"
 
@@ -192,6 +199,117 @@ __global__ __launch_bounds__(256) void diag_block_kernel(double* __restrict__ A,
   }
 }
 
+// Eq. 3 on the interior unknowns: A[p][p] = 1, A[p][q] = -beta_d(p)/4 for the
+// interior neighbour q in direction d (i-1, i+1, j-1, j+1 in that order), and
+// b_B[p] = sum of beta_d(p)/4 * u_B(q) over the boundary neighbours.
+// beta: [4][n_y][n_x].
+__global__ void assemble_beta_kernel(int nx, int ny, const double* __restrict__ beta, const double* __restrict__ ub,
+                                     double* __restrict__ K, int64_t ldk, double* __restrict__ bB) {
+  const int mx = nx - 2, my = ny - 2;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= mx * my) return;
+  const int i = p / mx + 1, j = p % mx + 1;
+  const int ni[4] = {i - 1, i + 1, i, i};
+  const int nj[4] = {j, j, j - 1, j + 1};
+  const int64_t plane = (int64_t)nx * ny;
+  double b = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    const int k = ni[d], l = nj[d];
+    const double c = 0.25 * beta[d * plane + (int64_t)i * nx + j];
+    if (k == 0 || k == ny - 1 || l == 0 || l == nx - 1) {
+      if (ub) b += c * ub[(int64_t)k * nx + l];
+    } else {
+      K[(int64_t)p * ldk + (k - 1) * mx + (l - 1)] = -c;
+    }
+  }
+  K[(int64_t)p * ldk + p] = 1.0;
+  bB[p] = b;
+}
+
+// Factor the kn x kn diagonal block at (k0, k0) as L U without row exchanges
+// (L unit lower, stored below the diagonal; U on and above it), and write
+// L^{-1} (unit lower) to Wl and U^{-1} (upper) to Wu, 64 x 64, zero padded.
+// A zero or non-finite pivot sets *flag (and is replaced by 1 so the
+// remaining arithmetic stays finite).
+__global__ __launch_bounds__(256) void lu_diag_block_kernel(double* __restrict__ A, int64_t lda, int k0, int kn,
+                                                            double* __restrict__ Wl, double* __restrict__ Wu,
+                                                            int* __restrict__ flag) {
+  __shared__ double F[NB][NB + 1];
+  __shared__ double tmp[NB];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, j = idx % NB;
+    F[i][j] = (i < kn && j < kn) ? A[(int64_t)(k0 + i) * lda + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < kn; ++j) {
+    if (tid == 0) {
+      const double d = F[j][j];
+      if (!(fabs(d) > 0.0 && fabs(d) < INFINITY)) {
+        *flag = 1;
+        F[j][j] = 1.0;
+      }
+    }
+    __syncthreads();
+    const double piv = F[j][j];
+    for (int i = j + 1 + tid; i < kn; i += 256) F[i][j] = F[i][j] / piv;
+    __syncthreads();
+    const int rem = kn - j - 1;
+    for (int idx = tid; idx < rem * rem; idx += 256) {
+      const int i = j + 1 + idx / rem, c = j + 1 + idx % rem;
+      F[i][c] -= F[i][j] * F[j][c];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < kn * kn; idx += 256) {
+    const int i = idx / kn, j = idx % kn;
+    A[(int64_t)(k0 + i) * lda + k0 + j] = F[i][j];
+  }
+  __syncthreads();
+  // L^{-1} in place below the diagonal, last column first:
+  //   Linv[i][j] = -(L[i][j] + sum_{j<k<i} Linv[i][k] L[k][j])  (i > j)
+  for (int j = kn - 1; j >= 0; --j) {
+    const int i = j + 1 + tid;
+    if (tid < NB && i < kn) {
+      double x = F[i][j];
+      for (int k = j + 1; k < i; ++k) x += F[i][k] * F[k][j];
+      tmp[i] = x;
+    }
+    __syncthreads();
+    if (tid < NB && i < kn) F[i][j] = -tmp[i];
+    __syncthreads();
+  }
+  // U^{-1} in place on and above the diagonal, last row first:
+  //   Uinv[i][i] = 1/U[i][i],  Uinv[i][j] = -(sum_{i<k<=j} U[i][k] Uinv[k][j]) / U[i][i]  (j > i)
+  for (int i = kn - 1; i >= 0; --i) {
+    const double uii = F[i][i];
+    const int j = i + 1 + tid;
+    if (tid < NB && j < kn) {
+      double x = 0.0;
+      for (int k = i + 1; k <= j; ++k) x += F[i][k] * F[k][j];
+      tmp[j] = x;
+    }
+    __syncthreads();
+    if (tid < NB && j < kn) F[i][j] = -tmp[j] / uii;
+    if (tid == 0) F[i][i] = 1.0 / uii;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, j = idx % NB;
+    const bool in = i < kn && j < kn;
+    Wl[idx] = in ? (i == j ? 1.0 : (j < i ? F[i][j] : 0.0)) : 0.0;
+    Wu[idx] = (in && j >= i) ? F[i][j] : 0.0;
+  }
+}
+
+// G = -G (n x n, row stride ld)
+__global__ void negate_kernel(double* __restrict__ G, int64_t ld, int n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), q = (int)(idx % n);
+  G[(int64_t)i * ld + q] = -G[(int64_t)i * ld + q];
+}
+
 __global__ void set_identity_kernel(double* __restrict__ A, int64_t lda, int n) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * n) return;
@@ -336,6 +454,147 @@ done:
   if (Kb) (void)hipFree(Kb);
   if (Wb) (void)hipFree(Wb);
   if (Wd) (void)hipFree(Wd);
+  if (bB) (void)hipFree(bB);
+  if (flag) (void)hipFree(flag);
+  return st;
+}
+
+// Eq. 3: fills op->G with -A^{-1} (so that u = -G rho + w = A^{-1}(rho + b_B)
+// with h = 1) and op->w = A^{-1} b_B when ub_dev is given.  beta_dev: device
+// [4][n_y][n_x].  PINV_E_NOT_SPD if the factorization without row exchanges
+// meets a zero or non-finite pivot.
+int32_t build_inverse_lu_device(pinv_op op, const double* beta_dev, const double* ub_dev, hipStream_t s) {
+  const int n = op->n;
+  const int64_t ld = op->ldg;
+  const int nblk = (n + NB - 1) / NB;
+  double *Kb = nullptr, *Wb = nullptr, *Wl = nullptr, *Wu = nullptr, *bB = nullptr;
+  int* flag = nullptr;
+  int32_t st = PINV_OK;
+  hipError_t e;
+  const size_t mat_bytes = (size_t)n * (size_t)ld * sizeof(double);
+
+#define PINV_BAIL(expr)                 \
+  do {                                  \
+    e = (expr);                         \
+    if (e != hipSuccess) {              \
+      st = pinv_hip_status(e);          \
+      goto done;                        \
+    }                                   \
+  } while (0)
+
+  PINV_BAIL(hipMalloc(&Kb, mat_bytes));
+  PINV_BAIL(hipMalloc(&Wb, mat_bytes));
+  PINV_BAIL(hipMalloc(&Wl, (size_t)nblk * NB * NB * sizeof(double)));
+  PINV_BAIL(hipMalloc(&Wu, (size_t)nblk * NB * NB * sizeof(double)));
+  PINV_BAIL(hipMalloc(&bB, (size_t)n * sizeof(double)));
+  PINV_BAIL(hipMalloc(&flag, sizeof(int)));
+  PINV_BAIL(hipMemsetAsync(flag, 0, sizeof(int), s));
+  PINV_BAIL(hipMemsetAsync(Kb, 0, mat_bytes, s));
+  PINV_BAIL(hipMemsetAsync(Wb, 0, mat_bytes, s));
+  hipLaunchKernelGGL(assemble_beta_kernel, dim3((n + 255) / 256), dim3(256), 0, s, op->nx, op->ny, beta_dev, ub_dev, Kb,
+                     ld, bB);
+  PINV_BAIL(hipGetLastError());
+
+  // A = L U in place: L below the diagonal (unit diagonal implied), U on and above
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * NB, kn = (n - k0 < NB) ? n - k0 : NB;
+    double* wl = Wl + (size_t)kb * NB * NB;
+    double* wu = Wu + (size_t)kb * NB * NB;
+    hipLaunchKernelGGL(lu_diag_block_kernel, dim3(1), dim3(256), 0, s, Kb, ld, k0, kn, wl, wu, flag);
+    PINV_BAIL(hipGetLastError());
+    const int r0 = k0 + kn, rn = n - r0;
+    if (rn <= 0) continue;
+    // L panel: A[r0:, k] <- A[r0:, k] U_kk^{-1} (in place: one 128-wide column tile holds all kn <= 64 columns)
+    GemmF64Args p{};
+    p.A = Kb + (int64_t)r0 * ld + k0; p.lda = ld; p.a_kcontig = 1;
+    p.B = wu; p.ldb = NB; p.b_kcontig = 0;
+    p.C = Kb + (int64_t)r0 * ld + k0; p.csm = ld; p.csn = 1;
+    p.M = rn; p.N = kn; p.K = kn; p.alpha = 1.0; p.beta = 0.0;
+    PINV_BAIL(launch_gemm_f64(p, s));
+    // U panel: A[k, r0:] <- L_kk^{-1} A[k, r0:] (in place: one 128-row tile holds all kn <= 64 rows)
+    GemmF64Args q{};
+    q.A = wl; q.lda = NB; q.a_kcontig = 1;
+    q.B = Kb + (int64_t)k0 * ld + r0; q.ldb = ld; q.b_kcontig = 0;
+    q.C = Kb + (int64_t)k0 * ld + r0; q.csm = ld; q.csn = 1;
+    q.M = kn; q.N = rn; q.K = kn; q.alpha = 1.0; q.beta = 0.0;
+    PINV_BAIL(launch_gemm_f64(q, s));
+    // trailing update A[r0:, r0:] -= L panel * U panel
+    GemmF64Args t{};
+    t.A = Kb + (int64_t)r0 * ld + k0; t.lda = ld; t.a_kcontig = 1;
+    t.B = Kb + (int64_t)k0 * ld + r0; t.ldb = ld; t.b_kcontig = 0;
+    t.C = Kb + (int64_t)r0 * ld + r0; t.csm = ld; t.csn = 1;
+    t.M = rn; t.N = rn; t.K = kn; t.alpha = -1.0; t.beta = 1.0;
+    PINV_BAIL(launch_gemm_f64(t, s));
+  }
+
+  // X = L^{-1} in Wb: block row i is Wl_i (E_i - sum_{k<i} L_ik X_k), accumulated right-looking
+  for (int ib = 0; ib < nblk; ++ib) {
+    const int i0 = ib * NB, in_ = (n - i0 < NB) ? n - i0 : NB;
+    hipLaunchKernelGGL(set_identity_kernel, dim3((in_ * in_ + 255) / 256), dim3(256), 0, s, Wb + (int64_t)i0 * ld + i0,
+                       ld, in_);
+    PINV_BAIL(hipGetLastError());
+    GemmF64Args a{};
+    a.A = Wl + (size_t)ib * NB * NB; a.lda = NB; a.a_kcontig = 1;
+    a.B = Wb + (int64_t)i0 * ld; a.ldb = ld; a.b_kcontig = 0;
+    a.C = Wb + (int64_t)i0 * ld; a.csm = ld; a.csn = 1;
+    a.M = in_; a.N = i0 + in_; a.K = in_; a.alpha = 1.0; a.beta = 0.0;
+    PINV_BAIL(launch_gemm_f64(a, s));
+    const int r0 = i0 + in_, rn = n - r0;
+    if (rn <= 0) continue;
+    GemmF64Args b{};
+    b.A = Kb + (int64_t)r0 * ld + i0; b.lda = ld; b.a_kcontig = 1;
+    b.B = Wb + (int64_t)i0 * ld; b.ldb = ld; b.b_kcontig = 0;
+    b.C = Wb + (int64_t)r0 * ld; b.csm = ld; b.csn = 1;
+    b.M = rn; b.N = r0; b.K = in_; b.alpha = -1.0; b.beta = 1.0;
+    PINV_BAIL(launch_gemm_f64(b, s));
+  }
+
+  // A^{-1} = U^{-1} X in Wb, bottom block row first: row block i becomes
+  // Wu_i Z_i, then Z[0:i0] -= U[0:i0, i] (row block i)
+  for (int ib = nblk - 1; ib >= 0; --ib) {
+    const int i0 = ib * NB, in_ = (n - i0 < NB) ? n - i0 : NB;
+    GemmF64Args a{};
+    a.A = Wu + (size_t)ib * NB * NB; a.lda = NB; a.a_kcontig = 1;
+    a.B = Wb + (int64_t)i0 * ld; a.ldb = ld; a.b_kcontig = 0;
+    a.C = Wb + (int64_t)i0 * ld; a.csm = ld; a.csn = 1;
+    a.M = in_; a.N = n; a.K = in_; a.alpha = 1.0; a.beta = 0.0;
+    PINV_BAIL(launch_gemm_f64(a, s));
+    if (i0 == 0) continue;
+    GemmF64Args b{};
+    b.A = Kb + i0; b.lda = ld; b.a_kcontig = 1;
+    b.B = Wb + (int64_t)i0 * ld; b.ldb = ld; b.b_kcontig = 0;
+    b.C = Wb; b.csm = ld; b.csn = 1;
+    b.M = i0; b.N = n; b.K = in_; b.alpha = -1.0; b.beta = 1.0;
+    PINV_BAIL(launch_gemm_f64(b, s));
+  }
+
+  if (ub_dev) {
+    PINV_BAIL(hipMalloc(&op->w, (size_t)n * sizeof(double)));
+    op->bytes += (int64_t)n * sizeof(double);
+    PINV_BAIL(launch_gemv_f64(Wb, ld, n, bB, n, 1, 1.0, nullptr, op->w, n, s));
+  }
+  hipLaunchKernelGGL(negate_kernel, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, s, Wb, ld, n);
+  PINV_BAIL(hipGetLastError());
+  {
+    int hflag = 0;
+    PINV_BAIL(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    PINV_BAIL(hipStreamSynchronize(s));
+    if (hflag) {
+      st = PINV_E_NOT_SPD;
+      goto done;
+    }
+  }
+  op->G = Wb;
+  op->bytes += (int64_t)mat_bytes;
+  Wb = nullptr;
+
+done:
+#undef PINV_BAIL
+  if (st != PINV_OK) (void)hipStreamSynchronize(s);
+  if (Kb) (void)hipFree(Kb);
+  if (Wb) (void)hipFree(Wb);
+  if (Wl) (void)hipFree(Wl);
+  if (Wu) (void)hipFree(Wu);
   if (bB) (void)hipFree(bB);
   if (flag) (void)hipFree(flag);
   return st;

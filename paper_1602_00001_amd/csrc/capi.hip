@@ -380,6 +380,52 @@ int32_t pinv_build_inverse_general(const pinv_grid_general* g, const double* eps
   return st;
 }
 
+int32_t pinv_build_inverse_beta(const pinv_grid* g, const double* beta, const double* u_boundary, void* stream,
+                                pinv_op* out) {
+  if (!out) return PINV_E_INVALID_ARG;
+  *out = nullptr;
+  if (!g || !beta) return PINV_E_INVALID_ARG;
+  pinv_grid g2{g->nx, g->ny, 1.0};
+  if (!grid_ok(&g2)) return PINV_E_INVALID_ARG;
+  const int nodes = g->nx * g->ny;
+  for (int64_t k = 0; k < 4 * (int64_t)nodes; ++k)
+    if (!std::isfinite(beta[k])) return PINV_E_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  pinv_op op = new_op(&g2);
+  if (!op) return PINV_E_OOM;
+  op->beta = 1;
+  const size_t need = 2 * (size_t)op->n * op->ldg * sizeof(double);
+  size_t freeb = 0, totalb = 0;
+  if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need > freeb) {
+    delete op;
+    return PINV_E_OOM;
+  }
+  double *beta_d = nullptr, *ub_d = nullptr;
+  int32_t st = PINV_OK;
+  {
+    const hipError_t e = hipMalloc(&beta_d, 4 * (size_t)nodes * sizeof(double));
+    if (e != hipSuccess) st = pinv_hip_status(e);
+    else {
+      const hipError_t e2 =
+          hipMemcpyAsync(beta_d, beta, 4 * (size_t)nodes * sizeof(double), hipMemcpyHostToDevice, s);
+      if (e2 != hipSuccess) st = pinv_hip_status(e2);
+    }
+  }
+  if (st == PINV_OK && boundary_nonzero(&g2, u_boundary)) st = copy_nodal(u_boundary, nodes, &ub_d, s);
+  if (st == PINV_OK) st = build_inverse_lu_device(op, beta_d, ub_d, s);
+  (void)hipStreamSynchronize(s);
+  if (beta_d) (void)hipFree(beta_d);
+  if (st != PINV_OK) {
+    if (ub_d) (void)hipFree(ub_d);
+    free_op(op);
+    return st;
+  }
+  op->ub = ub_d;
+  if (ub_d) op->bytes += (int64_t)nodes * sizeof(double);
+  *out = op;
+  return PINV_OK;
+}
+
 int32_t build_op(pinv_op op, int nodes, bool has_ub, const double* eps_nodes, const double* u_boundary,
                  hipStream_t s, pinv_op* out, const GeneralGrid* gen) {
   const size_t need = 2 * (size_t)op->n * op->ldg * sizeof(double);
@@ -634,7 +680,7 @@ int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u, const double* l
                       int32_t nrhs, double* grad_nodes, void* stream) {
   if (!op || !grad_nodes || nrhs < 0) return PINV_E_INVALID_ARG;
   if (nrhs > 0 && (!u || !lambda || ld_u < op->n || ld_lambda < op->n)) return PINV_E_INVALID_ARG;
-  if (op->general) return PINV_E_UNSUPPORTED;
+  if (op->general || op->beta) return PINV_E_UNSUPPORTED;
   hipStream_t s = as_stream(stream);
   const int chunks = grad_eps_chunks(nrhs);
   const size_t nodes = (size_t)op->nx * op->ny * (op->nz ? op->nz : 1);
@@ -820,6 +866,7 @@ int32_t pinv_get_info(pinv_op op, pinv_info* info) {
   info->has_lift = op->w != nullptr;
   info->device_bytes = op->bytes;
   info->nz = op->nz;
+  info->beta = op->beta;
   info->general = op->general;
   return PINV_OK;
 }

@@ -24,6 +24,7 @@ struct pinv_op_s {
   int nx = 0, ny = 0, mx = 0, my = 0, n = 0;
   int nz = 0, mz = 1;        // 3-D grids: n_z nodes along z (0 for a 2-D grid)
   int general = 0;           // non-uniform grid / per-direction eps: G holds K^{-1} diag(A), h = 1
+  int beta = 0;              // Eq. 3 with arbitrary coefficients: G holds -A^{-1}, h = 1
   double h = 0.0;
   int device = 0;
 
@@ -124,6 +125,7 @@ struct GeneralGrid {
   const double* eps_y;   // y-direction permittivity [ny][nx], or null (= eps_x)
   double* area;          // control volumes [n], written by the assembly (device scratch)
 };
+int32_t build_inverse_lu_device(pinv_op op, const double* beta_dev, const double* ub_dev, hipStream_t s);
 int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub_dev, const GeneralGrid* gen,
                              hipStream_t s);
 

@@ -46,7 +46,8 @@ class Info(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n", ctypes.c_int32), ("h", ctypes.c_double),
                 ("has_fp64", ctypes.c_int32), ("int8_slices", ctypes.c_int32), ("has_fp32", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("has_lift", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
-                ("nz", ctypes.c_int32), ("general", ctypes.c_int32)]
+                ("nz", ctypes.c_int32), ("general", ctypes.c_int32), ("beta", ctypes.c_int32),
+                ("_pad", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -64,6 +65,7 @@ def _load():
         "pinv_build_inverse": ([P(Grid), dp, dp, vp, P(vp)], i32),
         "pinv_build_inverse_3d": ([P(Grid3), dp, dp, vp, P(vp)], i32),
         "pinv_build_inverse_general": ([P(GridGeneral), dp, dp, dp, vp, P(vp)], i32),
+        "pinv_build_inverse_beta": ([P(Grid), dp, dp, vp, P(vp)], i32),
         "pinv_import_inverse": ([P(Grid), dp, i64, dp, dp, dp, vp, P(vp)], i32),
         "pinv_export_inverse": ([vp, dp, i64, dp, vp], i32),
         "pinv_quantize_inverse": ([vp, i32, i32, i32, vp], i32),
@@ -92,7 +94,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_build_inverse_general", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
+EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_build_inverse_general", "pinv_build_inverse_beta", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
             "pinv_prepare_split", "pinv_export_quantized", "pinv_apply_inverse", "pinv_apply_inverse_adjoint",
             "pinv_grad_eps", "pinv_apply_batched", "pinv_get_info", "pinv_destroy", "pinv_status_string",
             "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_int8_variants",
@@ -225,6 +227,20 @@ class PoissonInverse:
         out = ctypes.c_void_p()
         _check(lib.pinv_build_inverse_general(ctypes.byref(g), _ptr(ex), _ptr(ey), _ptr(ub), _stream(stream),
                                               ctypes.byref(out)), "pinv_build_inverse_general")
+        return cls(out, nx, ny, 1.0)
+
+    @classmethod
+    def build_beta(cls, nx, ny, beta, u_boundary=None, stream=None):
+        """Steps 1-2 for Eq. 3 with arbitrary coefficients beta [4, ny, nx]
+        (directions i-1, i+1, j-1, j+1): GPU LU inverse; the op's h is 1 and
+        apply gives u = A^{-1}(rho + b_B)."""
+        b = np.ascontiguousarray(np.asarray(beta, dtype=np.float64))
+        if b.shape != (4, ny, nx):
+            raise ValueError(f"beta must have shape (4, {ny}, {nx}), got {b.shape}")
+        ub = _host_nodal(u_boundary, nx, ny)
+        out = ctypes.c_void_p()
+        _check(lib.pinv_build_inverse_beta(ctypes.byref(Grid(nx, ny, 1.0)), _ptr(b), _ptr(ub), _stream(stream),
+                                           ctypes.byref(out)), "pinv_build_inverse_beta")
         return cls(out, nx, ny, 1.0)
 
     @classmethod

@@ -79,6 +79,15 @@ def test_host_side_argument_errors(pinv):
     gg = pinv.GridGeneral(2, 3, ctypes.cast(xs, ctypes.c_void_p), ctypes.cast(ys, ctypes.c_void_p))
     assert lib.pinv_build_inverse_general(ctypes.byref(gg), None, None, None, None,
                                           ctypes.byref(out)) == pinv.E_INVALID_ARG
+    gb = pinv.Grid(5, 4, 1.0)
+    assert lib.pinv_build_inverse_beta(ctypes.byref(gb), None, None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
+    assert lib.pinv_build_inverse_beta(None, None, None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
+    bad = (ctypes.c_double * (4 * 5 * 4))(*([1.0] * 79 + [float("nan")]))
+    assert lib.pinv_build_inverse_beta(ctypes.byref(gb), ctypes.cast(bad, ctypes.c_void_p), None, None,
+                                       ctypes.byref(out)) == pinv.E_INVALID_ARG
+    gb = pinv.Grid(2, 4, 1.0)
+    assert lib.pinv_build_inverse_beta(ctypes.byref(gb), ctypes.cast(bad, ctypes.c_void_p), None, None,
+                                       ctypes.byref(out)) == pinv.E_INVALID_ARG
     assert lib.pinv_int8_variants() >= 1
     assert lib.pinv_set_int8_variant(None, 16, 0) == pinv.E_INVALID_ARG
     assert lib.pinv_autotune_int8(None, 16, None, 0, 128, 1, None, 0, None, None) == pinv.E_INVALID_ARG
