@@ -185,3 +185,55 @@ def grad_eps_nodes_3d(nx, ny, nz, h, u_int, lam_int, ub_nodes=None):
                     out[k, i, j] += 0.5 * gf
                     out[a, b, c] += 0.5 * gf
     return out
+
+
+def grad_eps_general(x, y, u_int, lam_int, ub_nodes=None):
+    """dLoss/deps_x and dLoss/deps_y (nodal, [n_y][n_x] each) for the
+    finite-volume operator of :func:`grid.conservative_operator_general`.
+
+    There the solve is K u = -A rho + b_B with the stored inverse
+    G' = K^{-1} diag(A), so the adjoint output lambda = -G'^T g gives
+    mu = K^{-1} g = -lambda / A (per interior node).  Face f = (p, q) carries
+    c_f = eps_f * s_f with the geometric factor s_f = (cell height at the face's
+    row) / |x_q - x_p| for an x-face and (cell width at its column) / |y_q - y_p|
+    for a y-face, so, as for the uniform grid,
+        dLoss/dc_f = -sum_r (mu_p - mu_q)(u_p - u_q)
+                   = sum_r (lambda_p/A_p - lambda_q/A_q)(u_p - u_q)
+    (lambda = 0 and u = u_B on boundary nodes), and each end node of an x-face
+    receives s_f/2 of it in the x gradient (y-faces: the y gradient).
+    u_int, lam_int: [N, R] in interior order.  Returns (grad_x, grad_y)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    nx, ny = x.size, y.size
+    my, mx = ny - 2, nx - 2
+    u_int = np.asarray(u_int, dtype=np.float64).reshape(my * mx, -1)
+    lam_int = np.asarray(lam_int, dtype=np.float64).reshape(my * mx, -1)
+    R = u_int.shape[1]
+    U = np.zeros((ny, nx, R))
+    if ub_nodes is not None:
+        U[:, :, :] = np.asarray(ub_nodes, dtype=np.float64)[:, :, None]
+    U[1:-1, 1:-1, :] = u_int.reshape(my, mx, R)
+    M = np.zeros((ny, nx, R))       # lambda / A on interior nodes, 0 on the boundary
+    for i in range(1, ny - 1):
+        for j in range(1, nx - 1):
+            area = 0.5 * (x[j + 1] - x[j - 1]) * 0.5 * (y[i + 1] - y[i - 1])
+            M[i, j] = lam_int[(i - 1) * mx + (j - 1)] / area
+    gx = np.zeros((ny, nx))
+    gy = np.zeros((ny, nx))
+    for i in range(ny):
+        for j in range(nx - 1):           # x-faces (i, j)-(i, j+1)
+            if _grid.is_boundary(nx, ny, i, j) and _grid.is_boundary(nx, ny, i, j + 1):
+                continue
+            s = 0.5 * (y[i + 1] - y[i - 1]) / (x[j + 1] - x[j])
+            gf = s * float(np.sum((M[i, j] - M[i, j + 1]) * (U[i, j] - U[i, j + 1])))
+            gx[i, j] += 0.5 * gf
+            gx[i, j + 1] += 0.5 * gf
+    for i in range(ny - 1):               # y-faces (i, j)-(i+1, j)
+        for j in range(nx):
+            if _grid.is_boundary(nx, ny, i, j) and _grid.is_boundary(nx, ny, i + 1, j):
+                continue
+            s = 0.5 * (x[j + 1] - x[j - 1]) / (y[i + 1] - y[i])
+            gf = s * float(np.sum((M[i, j] - M[i + 1, j]) * (U[i, j] - U[i + 1, j])))
+            gy[i, j] += 0.5 * gf
+            gy[i + 1, j] += 0.5 * gf
+    return gx, gy
