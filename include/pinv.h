@@ -144,8 +144,9 @@ int32_t pinv_build_inverse_3d(const pinv_grid3* g, const double* eps_nodes,
  * adjoint applies the transpose of this G).
  *   eps_x, eps_y  host [n_y][n_x]; NULL eps_x = 1, NULL eps_y = eps_x.
  *   u_boundary    host [n_y][n_x]; only boundary entries are read.  NULL = 0.
- * pinv_grad_eps returns PINV_E_UNSUPPORTED for the op.  On a uniform grid with
- * eps_x = eps_y this builds h^2 times the G of pinv_build_inverse. */
+ * pinv_grad_eps returns PINV_E_UNSUPPORTED for the op (pinv_grad_eps_general
+ * gives its gradients).  On a uniform grid with eps_x = eps_y this builds h^2
+ * times the G of pinv_build_inverse. */
 typedef struct {
   int32_t nx, ny;
   const double* x;    /* host [n_x] */
@@ -248,6 +249,26 @@ int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits,
 int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u,
                       const double* lambda, int64_t ld_lambda, int32_t nrhs,
                       double* grad_nodes, void* stream);
+
+/* Per-direction permittivity gradients for an op from
+ * pinv_build_inverse_general (not in the paper).  There the solve is
+ * K u = -A rho + b_B and the adjoint output is lambda = -(K^{-1} diag(A))^T g,
+ * so mu = K^{-1} g = -lambda / A.  A face f = (p, q) has the coefficient
+ * eps_f * s_f (s_f = (y[i+1]-y[i-1])/2 / |x_q - x_p| for an x-face on row i,
+ * (x[j+1]-x[j-1])/2 / |y_q - y_p| for a y-face on column j), and
+ *   dLoss/d(eps_f s_f) = sum_r (lambda_p/A_p - lambda_q/A_q)(u_p - u_q)
+ * (lambda = 0 and u = u_B on the boundary); each end node receives s_f/2 of it,
+ * x-faces in grad_x and y-faces in grad_y.
+ *   grad_x, grad_y  device [n_y][n_x], overwritten.  grad_y NULL: grad_x
+ *                   receives the sum (the gradient with respect to one field
+ *                   used for both directions, as when the op was built with
+ *                   eps_y NULL).
+ * PINV_E_UNSUPPORTED for other ops.  Deterministic; for nrhs > 16 a
+ * stream-ordered scratch of 2 ceil(nrhs/16) doubles per node is taken from
+ * the device's memory pool for the duration of the call.  Asynchronous. */
+int32_t pinv_grad_eps_general(pinv_op op, const double* u, int64_t ld_u,
+                              const double* lambda, int64_t ld_lambda, int32_t nrhs,
+                              double* grad_x, double* grad_y, void* stream);
 
 /* Many solves against many ops in one call (batched uneven requests).
  * In PINV_INT8 mode the requests naming the same op are grouped and each group

@@ -135,6 +135,8 @@ void free_op(pinv_op op) {
   if (op->ub) (void)hipFree(op->ub);
   if (op->G32) (void)hipFree(op->G32);
   if (op->Gb) (void)hipFree(op->Gb);
+  if (op->xc) (void)hipFree(op->xc);
+  if (op->yc) (void)hipFree(op->yc);
   delete op;
 }
 
@@ -373,8 +375,15 @@ int32_t pinv_build_inverse_general(const pinv_grid_general* g, const double* eps
   gen.area = area_d;
   st = build_op(op, nodes, boundary_nonzero(&g2, u_boundary), eps_x, u_boundary, s, out, &gen);
   (void)hipStreamSynchronize(s);
-  (void)hipFree(x_d);
-  (void)hipFree(y_d);
+  if (st == PINV_OK) {
+    // the node coordinates stay with the op for the eps-gradient
+    (*out)->xc = x_d;
+    (*out)->yc = y_d;
+    (*out)->bytes += (int64_t)(g->nx + g->ny) * sizeof(double);
+  } else {
+    (void)hipFree(x_d);
+    (void)hipFree(y_d);
+  }
   if (ey_d) (void)hipFree(ey_d);
   (void)hipFree(area_d);
   return st;
@@ -694,6 +703,30 @@ int32_t pinv_grad_eps(pinv_op op, const double* u, int64_t ld_u, const double* l
     TraceScope ts("grad_eps", s);
     e = launch_grad_eps(op->nx, op->ny, op->nz, op->h, u, ld_u, lambda, ld_lambda, nrhs, op->ub, (double*)part, grad_nodes,
                         s);
+  }
+  const hipError_t e2 = part ? hipFreeAsync(part, s) : hipSuccess;
+  if (e != hipSuccess) return pinv_hip_status(e);
+  return pinv_hip_status(e2);
+}
+
+int32_t pinv_grad_eps_general(pinv_op op, const double* u, int64_t ld_u, const double* lambda, int64_t ld_lambda,
+                              int32_t nrhs, double* grad_x, double* grad_y, void* stream) {
+  if (!op || !grad_x || nrhs < 0 || grad_x == grad_y) return PINV_E_INVALID_ARG;
+  if (nrhs > 0 && (!u || !lambda || ld_u < op->n || ld_lambda < op->n)) return PINV_E_INVALID_ARG;
+  if (!op->general || !op->xc || !op->yc) return PINV_E_UNSUPPORTED;
+  hipStream_t s = as_stream(stream);
+  const int chunks = grad_eps_chunks(nrhs);
+  const size_t nodes = (size_t)op->nx * op->ny;
+  void* part = nullptr;
+  if (chunks > 1) {
+    configure_pool_once();
+    PINV_HIP_TRY(hipMallocAsync(&part, 2 * (size_t)chunks * nodes * sizeof(double), s));
+  }
+  hipError_t e;
+  {
+    TraceScope ts("grad_eps", s);
+    e = launch_grad_eps_general(op->nx, op->ny, op->xc, op->yc, u, ld_u, lambda, ld_lambda, nrhs, op->ub,
+                                (double*)part, grad_x, grad_y, s);
   }
   const hipError_t e2 = part ? hipFreeAsync(part, s) : hipSuccess;
   if (e != hipSuccess) return pinv_hip_status(e);

@@ -25,6 +25,8 @@ struct pinv_op_s {
   int nz = 0, mz = 1;        // 3-D grids: n_z nodes along z (0 for a 2-D grid)
   int general = 0;           // non-uniform grid / per-direction eps: G holds K^{-1} diag(A), h = 1
   int beta = 0;              // Eq. 3 with arbitrary coefficients: G holds -A^{-1}, h = 1
+  double* xc = nullptr;      // non-uniform grid: device node coordinates [nx], [ny]
+  double* yc = nullptr;
   double h = 0.0;
   int device = 0;
 
@@ -214,6 +216,11 @@ size_t split_scratch_bytes(int mode, const pinv_op_s* op, int nrhs);
 // nz = 0 for the 2-D operator.  part: scratch of grad_eps_chunks(nrhs) * (nodes)
 // doubles (unused when that is <= 1)
 int grad_eps_chunks(int nrhs);
+// non-uniform grid (x, y: device node coordinates): per-direction gradients
+// gx, gy [ny][nx], or their sum in gx when gy is null; part: 2 * chunks * nodes
+hipError_t launch_grad_eps_general(int nx, int ny, const double* x, const double* y, const double* u, int64_t ldu,
+                                   const double* lam, int64_t ldl, int nrhs, const double* ub, double* part,
+                                   double* gx, double* gy, hipStream_t s);
 hipError_t launch_grad_eps(int nx, int ny, int nz, double h, const double* u, int64_t ldu,
                            const double* lam, int64_t ldl, int nrhs, const double* ub,
                            double* part, double* grad, hipStream_t s);

@@ -98,6 +98,97 @@ __global__ __launch_bounds__(256) void grad_eps_reduce_kernel(int nodes, int chu
   grad[node] = 0.5 * total / (h * h);
 }
 
+// Non-uniform tensor grid with a permittivity per direction (the finite-volume
+// operator K u = -A rho + b_B, stored inverse K^{-1} diag(A)): the face
+// coefficient is eps_f times the geometric factor s_f (cell height / node
+// distance for an x-face, cell width / node distance for a y-face), and
+// mu = K^{-1} g = -lambda / A, so dLoss/dc_f = sum_r (lambda_p/A_p -
+// lambda_q/A_q)(u_p - u_q); each end node receives s_f/2 of it, x-faces in the
+// x gradient and y-faces in the y gradient.  Same chunking as above; the
+// partial sums go to part[0 (x) or 1 (y)][chunk][node].
+__global__ __launch_bounds__(256) void grad_eps_general_partial_kernel(
+    int nx, int ny, const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ u,
+    int64_t ldu, const double* __restrict__ lam, int64_t ldl, int nrhs, const double* __restrict__ ub,
+    double* __restrict__ part, double* __restrict__ gx, double* __restrict__ gy) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nodes = nx * ny;
+  if (node >= nodes) return;
+  const int r0 = blockIdx.y * RC;
+  const int r1 = min(nrhs, r0 + RC);
+  const int i = node / nx, j = node % nx;
+  const int mx = nx - 2;
+  auto boundary = [&](int a, int b) { return a == 0 || a == ny - 1 || b == 0 || b == nx - 1; };
+  auto area = [&](int a, int b) { return (0.5 * (x[b + 1] - x[b - 1])) * (0.5 * (y[a + 1] - y[a - 1])); };
+  const bool bp = boundary(i, j);
+  const int ni[4] = {i - 1, i + 1, i, i};
+  const int nj[4] = {j, j, j - 1, j + 1};
+  const int64_t pp = bp ? 0 : (int64_t)(i - 1) * mx + (j - 1);
+  const double inv_ap = bp ? 0.0 : 1.0 / area(i, j);
+  const double ubp = (bp && ub) ? ub[node] : 0.0;
+  bool use[4], bq[4];
+  int64_t qq[4];
+  double ubq[4], inv_aq[4], sf[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = ni[t], l = nj[t];
+    const bool inside = k >= 0 && k < ny && l >= 0 && l < nx;
+    bq[t] = !inside || boundary(k, l);
+    use[t] = inside && !(bp && bq[t]);
+    qq[t] = bq[t] ? 0 : (int64_t)(k - 1) * mx + (l - 1);
+    ubq[t] = (use[t] && bq[t] && ub) ? ub[(int64_t)k * nx + l] : 0.0;
+    inv_aq[t] = (use[t] && !bq[t]) ? 1.0 / area(k, l) : 0.0;
+    // a used face has an interior end, so the row (x-face) or column (y-face)
+    // it lies on is interior and its cell extent is defined
+    sf[t] = !use[t] ? 0.0
+            : t < 2 ? 0.5 * (x[j + 1] - x[j - 1]) / fabs(y[k] - y[i])
+                    : 0.5 * (y[i + 1] - y[i - 1]) / fabs(x[l] - x[j]);
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = r0; r < r1; ++r) {
+    const double* ur = u + (int64_t)r * ldu;
+    const double* lr = lam + (int64_t)r * ldl;
+    const double up = bp ? ubp : ur[pp];
+    const double mp = bp ? 0.0 : lr[pp] * inv_ap;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (!use[t]) continue;
+      const double uq = bq[t] ? ubq[t] : ur[qq[t]];
+      const double mq = bq[t] ? 0.0 : lr[qq[t]] * inv_aq[t];
+      acc[t] += (mp - mq) * (up - uq);
+    }
+  }
+  const double sy = sf[0] * acc[0] + sf[1] * acc[1];
+  const double sx = sf[2] * acc[2] + sf[3] * acc[3];
+  if (part) {
+    part[(int64_t)blockIdx.y * nodes + node] = sx;
+    part[((int64_t)gridDim.y + blockIdx.y) * nodes + node] = sy;
+  } else if (gy) {
+    gx[node] = 0.5 * sx;
+    gy[node] = 0.5 * sy;
+  } else {
+    gx[node] = 0.5 * (sx + sy);
+  }
+}
+
+__global__ __launch_bounds__(256) void grad_eps_general_reduce_kernel(int nodes, int chunks,
+                                                                     const double* __restrict__ part,
+                                                                     double* __restrict__ gx,
+                                                                     double* __restrict__ gy) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nodes) return;
+  double sx = 0.0, sy = 0.0;
+  for (int c = 0; c < chunks; ++c) {
+    sx += part[(int64_t)c * nodes + node];
+    sy += part[((int64_t)chunks + c) * nodes + node];
+  }
+  if (gy) {
+    gx[node] = 0.5 * sx;
+    gy[node] = 0.5 * sy;
+  } else {
+    gx[node] = 0.5 * (sx + sy);
+  }
+}
+
 }  // namespace
 
 int grad_eps_chunks(int nrhs) { return (nrhs + RC - 1) / RC; }
@@ -121,5 +212,24 @@ hipError_t launch_grad_eps(int nx, int ny, int nz, double h, const double* u, in
   hipError_t e = partial(dim3(blocks.x, chunks), part, 0);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(grad_eps_reduce_kernel, blocks, dim3(256), 0, s, nodes, chunks, h, part, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_eps_general(int nx, int ny, const double* x, const double* y, const double* u, int64_t ldu,
+                                   const double* lam, int64_t ldl, int nrhs, const double* ub, double* part,
+                                   double* gx, double* gy, hipStream_t s) {
+  const int nodes = nx * ny;
+  const int chunks = grad_eps_chunks(nrhs);
+  const dim3 blocks((nodes + 255) / 256);
+  if (chunks <= 1) {
+    hipLaunchKernelGGL(grad_eps_general_partial_kernel, dim3(blocks.x, 1), dim3(256), 0, s, nx, ny, x, y, u, ldu, lam,
+                       ldl, nrhs, ub, (double*)nullptr, gx, gy);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(grad_eps_general_partial_kernel, dim3(blocks.x, chunks), dim3(256), 0, s, nx, ny, x, y, u, ldu,
+                     lam, ldl, nrhs, ub, part, gx, gy);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(grad_eps_general_reduce_kernel, blocks, dim3(256), 0, s, nodes, chunks, part, gx, gy);
   return hipGetLastError();
 }
