@@ -117,10 +117,13 @@ __global__ __launch_bounds__(256) void transpose_planes_kernel(const int8_t* __r
 // One workgroup per column r of X (column-major n x nrhs, stride ldx): the
 // exponent of its largest magnitude, then its rows of the output
 // [SR][Rpad][P] (rows n..P-1 and columns r >= nrhs are written as zeros).
-// Each thread handles 4 consecutive k per pass (32-byte reads, 4-byte writes
-// per digit plane), so both the reads and the writes of a wave are contiguous.
+// Each thread handles 4 consecutive k of every 1024 (32-byte reads, 4-byte
+// writes per digit plane), so both the reads and the writes of a wave are
+// contiguous.  Columns of up to KR * 1024 entries are read once into registers
+// (all loads in flight together); longer ones are read twice, once for the
+// maximum and once for the digits.
 template <int SR>
-__device__ inline void quantize_col(const double* __restrict__ x, bool live, int n, int r, int Rpad, int64_t P,
+__device__ __attribute__((always_inline)) inline void quantize_col_two_pass(const double* __restrict__ x, bool live, int n, int r, int Rpad, int64_t P,
                                     const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
                                     int32_t* __restrict__ f, double* red) {
   // Loads are unconditional from clamped indices (k < n selects the value
@@ -167,6 +170,65 @@ __device__ inline void quantize_col(const double* __restrict__ x, bool live, int
       int word;
       __builtin_memcpy(&word, d[s], 4);
       *(int*)(Xq + ((int64_t)s * Rpad + r) * P + k0) = word;
+    }
+  }
+}
+
+constexpr int KR = 16;
+
+template <int SR>
+__device__ __attribute__((always_inline)) inline void quantize_col(const double* __restrict__ x, bool live, int n, int r, int Rpad, int64_t P,
+                                    const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
+                                    int32_t* __restrict__ f, double* red) {
+  if (n > KR * 1024) {
+    quantize_col_two_pass<SR>(x, live, n, r, Rpad, P, pre, Xq, f, red);
+    return;
+  }
+  // (chunk c is read when it holds entries; the condition is uniform, and the
+  // loads of a chunk are unconditional from clamped indices)
+  double v[KR][4];
+  double m = 0.0;
+#pragma unroll
+  for (int c = 0; c < KR; ++c) {
+    const int64_t k0 = (int64_t)c * 1024 + threadIdx.x * 4;
+    if (live && c * 1024 < n) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t k = min(k0 + t, (int64_t)n - 1);
+        v[c][t] = pre ? ldexp(x[k], pre[k]) : x[k];
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[c][t] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < KR; ++c)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) m = fmax(m, (int64_t)c * 1024 + threadIdx.x * 4 + t < n ? fabs(v[c][t]) : 0.0);
+  m = block_max_256(m, red);
+  const int fr = frexp_exp(m);
+  if (live && threadIdx.x == 0) f[r] = fr;
+  const double M = (double)(127LL * ((1LL << (8 * SR)) - 1) / 255);
+#pragma unroll
+  for (int c = 0; c < KR; ++c) {
+    const int64_t k0 = (int64_t)c * 1024 + threadIdx.x * 4;
+    if (k0 >= P) break;
+    int8_t d[SR][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      int q = 0;
+      if (live && k0 + t < n) q = (int)rint(ldexp(v[c][t], -fr) * M);
+      int8_t dd[SR];
+      digits<SR>(q, dd);
+#pragma unroll
+      for (int s2 = 0; s2 < SR; ++s2) d[s2][t] = dd[s2];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < SR; ++s2) {
+      int word;
+      __builtin_memcpy(&word, d[s2], 4);
+      *(int*)(Xq + ((int64_t)s2 * Rpad + r) * P + k0) = word;
     }
   }
 }
