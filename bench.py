@@ -94,7 +94,7 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--workload", default="quant_128",
-                    choices=["quant_128", "plain_32", "vareps_64", "grad_192", "batched", "coupled_32",
+                    choices=["quant_128", "plain_32", "vareps_64", "grad_192", "batched", "coupled_32", "gemv_128",
                              "poisson3d_26"],
                     help="quant_128 is the headline metric; the others measure the remaining paths")
     args = ap.parse_args()
@@ -424,6 +424,50 @@ def bench_poisson3d_26(args):
     return line
 
 
+def bench_gemv_128(args):
+    """One right-hand side per call at 126^2 unknowns: the apply is a pass over
+    the stored inverse (HBM-bound): FP64 GEMV (2.02 GB) and int8 digit planes
+    (24-bit: 0.76 GB)."""
+    import torch
+    from paper_1602_00001_amd import pinv, workloads
+    wl = workloads.quant_128(1)
+    n, h = wl["n"], wl["h"]
+    N = (n - 2) ** 2
+    op = pinv.PoissonInverse.build(n, n, h)
+    op.quantize(24)
+    rho = torch.from_numpy(wl["rho"]).cuda()
+    u64 = torch.empty_like(rho)
+    u8 = torch.empty_like(rho)
+    for _ in range(args.warmup):
+        op.apply(rho, "fp64", out=u64)
+        op.apply(rho, "int8", 16, out=u8)
+    torch.cuda.synchronize()
+    for k in ("gemv_f64", "gemm_i8", "quantize_cols"):
+        pinv.trace_read(k)
+    pinv.trace_enable(True)
+    dt64 = _timed(lambda: op.apply(rho, "fp64", out=u64), args.steps, 0)
+    dt8 = _timed(lambda: op.apply(rho, "int8", 16, out=u8), args.steps, 0)
+    pinv.trace_enable(False)
+    fms, fcnt = pinv.trace_read("gemv_f64")
+    ims, icnt = pinv.trace_read("gemm_i8")
+    err = float(torch.linalg.vector_norm(u8 - u64) / torch.linalg.vector_norm(u64))
+    op.close()
+    k64 = fms / max(fcnt, 1)
+    k8 = ims / max(icnt, 1)
+    gbs64 = (8.0 * N * N + 16.0 * N) / (k64 * 1e-3) / 1e9
+    gbs8 = (3.0 * N * N + 10.0 * N) / (k8 * 1e-3) / 1e9
+    line = _base("solves/sec at 126^2 unknowns, one RHS per call (FP64 GEMV over the stored inverse)", 1.0 / dt64,
+                 "solves/s", args, dt64 * 1e3, "f64",
+                 {"workload": f"gemv_128: 128x128 grid, {N} unknowns, eps=1, 1 uniform[-1,1] RHS per call"})
+    line["roofline"] = {"kernel": "gemv_f64_kernel<1>", "bound": "hbm", "achieved": gbs64, "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": gbs64 / PEAK_HBM_GBS, "traffic": None, "avg_launch_ms": k64}
+    line["int8"] = {"value": 1.0 / dt8, "unit": "solves/s", "ms_per_step": dt8 * 1e3, "rel_l2_vs_fp64": err,
+                    "roofline": {"kernel": "gemm_i8_kernel<3,2> (+ split-K epilogue)", "bound": "hbm",
+                                 "achieved": gbs8, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs8 / PEAK_HBM_GBS,
+                                 "avg_launch_ms": k8}}
+    return line
+
+
 def bench_vareps_64(args):
     """64x64 grid, variable eps, 256 drifting-blob time steps: FP64 against the
     FP32 and BF16 split forms."""
@@ -588,7 +632,8 @@ def bench_batched(args):
 
 
 OTHER = {"plain_32": bench_plain_32, "vareps_64": bench_vareps_64, "grad_192": bench_grad_192,
-         "batched": bench_batched, "coupled_32": bench_coupled_32, "poisson3d_26": bench_poisson3d_26}
+         "batched": bench_batched, "coupled_32": bench_coupled_32, "poisson3d_26": bench_poisson3d_26,
+         "gemv_128": bench_gemv_128}
 
 
 if __name__ == "__main__":

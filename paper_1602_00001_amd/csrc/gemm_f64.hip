@@ -304,7 +304,9 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64_nt_kernel(GemmF64Args a,
 }
 
 // One wave per row of G; lanes stride over k; up to 8 right-hand sides.
-template <int NR>
+// VEC: the row is read as 16-byte pairs (rows start 16-byte aligned), so one
+// load instruction of a wave covers 1 KB of the row.
+template <int NR, bool VEC>
 __global__ __launch_bounds__(256) void gemv_f64_kernel(const double* __restrict__ G, int64_t ldg, int n,
                                                       const double* __restrict__ x, int64_t ldx, double alpha,
                                                       const double* __restrict__ bias, double* __restrict__ u,
@@ -314,32 +316,49 @@ __global__ __launch_bounds__(256) void gemv_f64_kernel(const double* __restrict_
   if (row >= n) return;
   const double* g = G + (int64_t)row * ldg;
   // four independent partial sums per right-hand side, so the loads of four
-  // k blocks are in flight together (the row is short at small grids and the
-  // loop would otherwise wait for each load in turn)
+  // k blocks are in flight together (the loop would otherwise wait for each
+  // load in turn; eight measured no faster)
   constexpr int U = 4;
+  constexpr int W = VEC ? 2 : 1;           // doubles per lane and load
   double s[U][NR];
 #pragma unroll
   for (int q = 0; q < U; ++q)
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[q][r] = 0.0;
-  int k = lane;
-  for (; k + 64 * (U - 1) < n; k += 64 * U) {
-    double gv[U];
+  // whole blocks of 64 W U doubles (the same count for every lane), then the
+  // rest one double per lane
+  int b = 0;
+  for (; b + 64 * W * U <= n; b += 64 * W * U) {
+    const int k = b + lane * W;
+    double gv[U][W];
 #pragma unroll
-    for (int q = 0; q < U; ++q) gv[q] = g[k + 64 * q];
+    for (int q = 0; q < U; ++q) {
+      if constexpr (VEC) {
+        const double2 v = *(const double2*)(g + k + 64 * W * q);
+        gv[q][0] = v.x;
+        gv[q][W - 1] = v.y;
+      } else {
+        gv[q][0] = g[k + 64 * q];
+      }
+    }
 #pragma unroll
     for (int q = 0; q < U; ++q)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) s[q][r] = fma(gv[q], x[(int64_t)r * ldx + k + 64 * q], s[q][r]);
+      for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          s[q][r] = fma(gv[q][w], x[(int64_t)r * ldx + k + 64 * W * q + w], s[q][r]);
   }
-  for (; k < n; k += 64) {
+  for (int k = b + lane; k < n; k += 64) {
     const double gv = g[k];
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[0][r] = fma(gv, x[(int64_t)r * ldx + k], s[0][r]);
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    double v = ((s[0][r] + s[1][r]) + s[2][r]) + s[3][r];
+    double v = s[0][r];
+#pragma unroll
+    for (int q = 1; q < U; ++q) v += s[q][r];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     s[0][r] = v;
@@ -440,15 +459,20 @@ hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t s) {
 hipError_t launch_gemv_f64(const double* G, int64_t ldg, int n, const double* x, int64_t ldx, int nrhs,
                            double alpha, const double* bias, double* u, int64_t ldu, hipStream_t s) {
   const int grid = (n + 3) / 4;
+  const bool vec = ldg % 2 == 0 && (uintptr_t)G % 16 == 0;
   for (int r0 = 0; r0 < nrhs; r0 += 8) {
     const int nr = nrhs - r0 < 8 ? nrhs - r0 : 8;
     const double* xr = x + (int64_t)r0 * ldx;
     double* ur = u + (int64_t)r0 * ldu;
     switch (nr) {
-#define PINV_GEMV_CASE(R)                                                                               \
-  case R:                                                                                               \
-    hipLaunchKernelGGL((gemv_f64_kernel<R>), dim3(grid), dim3(256), 0, s, G, ldg, n, xr, ldx, alpha, bias, \
-                       ur, ldu);                                                                        \
+#define PINV_GEMV_CASE(R)                                                                                       \
+  case R:                                                                                                       \
+    if (vec)                                                                                                    \
+      hipLaunchKernelGGL((gemv_f64_kernel<R, true>), dim3(grid), dim3(256), 0, s, G, ldg, n, xr, ldx, alpha, bias, \
+                         ur, ldu);                                                                              \
+    else                                                                                                        \
+      hipLaunchKernelGGL((gemv_f64_kernel<R, false>), dim3(grid), dim3(256), 0, s, G, ldg, n, xr, ldx, alpha,     \
+                         bias, ur, ldu);                                                                        \
     break;
       PINV_GEMV_CASE(1) PINV_GEMV_CASE(2) PINV_GEMV_CASE(3) PINV_GEMV_CASE(4)
       PINV_GEMV_CASE(5) PINV_GEMV_CASE(6) PINV_GEMV_CASE(7) PINV_GEMV_CASE(8)
