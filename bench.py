@@ -435,22 +435,28 @@ def bench_gemv_128(args):
     N = (n - 2) ** 2
     op = pinv.PoissonInverse.build(n, n, h)
     op.quantize(24)
+    op.prepare_split("fp64_sym")
     rho = torch.from_numpy(wl["rho"]).cuda()
     u64 = torch.empty_like(rho)
     u8 = torch.empty_like(rho)
+    us = torch.empty_like(rho)
     for _ in range(args.warmup):
         op.apply(rho, "fp64", out=u64)
         op.apply(rho, "int8", 16, out=u8)
+        op.apply(rho, "fp64_sym", out=us)
     torch.cuda.synchronize()
-    for k in ("gemv_f64", "gemm_i8", "quantize_cols"):
+    for k in ("gemv_f64", "gemm_i8", "quantize_cols", "gemv_sym"):
         pinv.trace_read(k)
     pinv.trace_enable(True)
     dt64 = _timed(lambda: op.apply(rho, "fp64", out=u64), args.steps, 0)
     dt8 = _timed(lambda: op.apply(rho, "int8", 16, out=u8), args.steps, 0)
+    dts = _timed(lambda: op.apply(rho, "fp64_sym", out=us), args.steps, 0)
     pinv.trace_enable(False)
     fms, fcnt = pinv.trace_read("gemv_f64")
     ims, icnt = pinv.trace_read("gemm_i8")
+    sms, scnt = pinv.trace_read("gemv_sym")
     err = float(torch.linalg.vector_norm(u8 - u64) / torch.linalg.vector_norm(u64))
+    err_sym = float(torch.linalg.vector_norm(us - u64) / torch.linalg.vector_norm(u64))
     op.close()
     k64 = fms / max(fcnt, 1)
     k8 = ims / max(icnt, 1)
@@ -461,6 +467,14 @@ def bench_gemv_128(args):
                  {"workload": f"gemv_128: 128x128 grid, {N} unknowns, eps=1, 1 uniform[-1,1] RHS per call"})
     line["roofline"] = {"kernel": "gemv_f64_kernel<1>", "bound": "hbm", "achieved": gbs64, "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": gbs64 / PEAK_HBM_GBS, "traffic": None, "avg_launch_ms": k64}
+    nb = (N + 63) // 64
+    ks = sms / max(scnt, 1)
+    sym_bytes = 8.0 * (nb * (nb + 1) // 2) * 64 * 64 + 2 * 8.0 * nb * nb * 64 + 16.0 * N
+    line["fp64_sym"] = {"value": 1.0 / dts, "unit": "solves/s", "ms_per_step": dts * 1e3, "rel_l2_vs_fp64": err_sym,
+                        "roofline": {"kernel": "sym_block_kernel<1> + sym_reduce_kernel", "bound": "hbm",
+                                     "achieved": sym_bytes / (ks * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                     "frac": sym_bytes / (ks * 1e-3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": ks,
+                                     "bytes": "packed upper-triangle blocks + block partials written and read"}}
     line["int8"] = {"value": 1.0 / dt8, "unit": "solves/s", "ms_per_step": dt8 * 1e3, "rel_l2_vs_fp64": err,
                     "roofline": {"kernel": "gemm_i8_kernel<3,2> (+ split-K epilogue)", "bound": "hbm",
                                  "achieved": gbs8, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs8 / PEAK_HBM_GBS,

@@ -77,6 +77,7 @@ extern "C" {
 #define PINV_BF16X3  2
 #define PINV_BF16X6  3
 #define PINV_INT8    4
+#define PINV_FP64_SYM 5          /* FP64 from the symmetric-packed upper triangle */
 
 #define PINV_SCALE_ROW 0          /* one power-of-two exponent per row of G   */
 
@@ -99,7 +100,7 @@ typedef struct {
   int32_t nz;               /* n_z for a 3-D op, 0 for a 2-D op                 */
   int32_t general;          /* built by pinv_build_inverse_general (h = 1)      */
   int32_t beta;             /* built by pinv_build_inverse_beta (h = 1)         */
-  int32_t _pad;
+  int32_t has_sym;          /* symmetric-packed FP64 copy held                  */
 } pinv_info;
 
 /* Steps 1-2 of "The solution steps": assemble the interior operator K from the
@@ -204,7 +205,17 @@ int32_t pinv_quantize_inverse(pinv_op op, int32_t bits, int32_t scale_mode,
                               int32_t keep_fp64, void* stream);
 
 /* Materialise the FP32 copy (mode PINV_FP32) or the bfloat16 parts (PINV_BF16X3
- * or PINV_BF16X6) of G, from the FP64 G.  Synchronous. */
+ * or PINV_BF16X6) of G, from the FP64 G.  Synchronous.
+ * PINV_FP64_SYM: the symmetric-packed FP64 copy, for applies that are one pass
+ * over G (few right-hand sides, HBM-bound): the 64 x 64 blocks on and above
+ * the diagonal, about half the bytes of G.  G must be symmetric to within
+ * 1e-12 sqrt(|G_ii G_jj|) in every entry (true of the inverses built by
+ * pinv_build_inverse and pinv_build_inverse_3d, not of those from
+ * pinv_build_inverse_general or pinv_build_inverse_beta): PINV_E_UNSUPPORTED
+ * otherwise.  Applies in this mode use the upper triangle, and the adjoint
+ * equals the forward product; each pass of up to 8 right-hand sides takes a
+ * stream-ordered scratch of 8 N_b^2 64 doubles per right-hand side (N_b =
+ * ceil(N/64)) from the device's memory pool. */
 int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream);
 
 /* Export the int8 digit slices (host [S][N][N], most significant slice

@@ -135,6 +135,7 @@ void free_op(pinv_op op) {
   if (op->ub) (void)hipFree(op->ub);
   if (op->G32) (void)hipFree(op->G32);
   if (op->Gb) (void)hipFree(op->Gb);
+  if (op->Gsym) (void)hipFree(op->Gsym);
   if (op->xc) (void)hipFree(op->xc);
   if (op->yc) (void)hipFree(op->yc);
   delete op;
@@ -581,9 +582,31 @@ int32_t pinv_quantize_inverse(pinv_op op, int32_t bits, int32_t scale_mode, int3
 
 int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream) {
   if (!op) return PINV_E_INVALID_ARG;
-  if (mode != PINV_FP32 && mode != PINV_BF16X3 && mode != PINV_BF16X6) return PINV_E_INVALID_ARG;
+  if (mode != PINV_FP32 && mode != PINV_BF16X3 && mode != PINV_BF16X6 && mode != PINV_FP64_SYM)
+    return PINV_E_INVALID_ARG;
   if (!op->G) return PINV_E_STATE;
   hipStream_t s = as_stream(stream);
+  if (mode == PINV_FP64_SYM) {
+    // only an exactly symmetric G may be stored as its upper triangle
+    int* flag = nullptr;
+    PINV_HIP_TRY(hipMalloc(&flag, sizeof(int)));
+    int hflag = 0;
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
+    if (e == hipSuccess) e = launch_sym_check(op->G, op->ldg, op->n, flag, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(flag);
+    if (e != hipSuccess) return pinv_hip_status(e);
+    if (hflag) return PINV_E_UNSUPPORTED;
+    if (!op->Gsym) {
+      const size_t bytes = sym_packed_elems(op->n) * sizeof(double);
+      PINV_HIP_TRY(hipMalloc(&op->Gsym, bytes));
+      op->bytes += (int64_t)bytes;
+    }
+    PINV_HIP_TRY(launch_pack_upper(op->G, op->ldg, op->n, op->Gsym, s));
+    PINV_HIP_TRY(hipStreamSynchronize(s));
+    return PINV_OK;
+  }
   const int64_t P = pinv_pad_dim(op->n);
   const size_t elems = (size_t)P * P;  // zero-padded P x P planes
   if (mode == PINV_FP32) {
@@ -626,6 +649,25 @@ int32_t pinv_export_quantized(pinv_op op, int8_t* slices_host, int32_t* exponent
   return PINV_OK;
 }
 
+namespace {
+// u = -h^2 G x + bias from the symmetric-packed copy (also the adjoint: G = G^T)
+int32_t sym_apply(pinv_op op, const double* X, int64_t ldx, int nrhs, const double* bias, double* U, int64_t ldu,
+                  hipStream_t s) {
+  if (!op->Gsym) return PINV_E_STATE;
+  configure_pool_once();
+  void* Y = nullptr;
+  PINV_HIP_TRY(hipMallocAsync(&Y, sym_scratch_bytes(op->n, nrhs), s));
+  hipError_t e;
+  {
+    TraceScope ts("gemv_sym", s);
+    e = launch_gemv_sym(op->Gsym, op->n, X, ldx, nrhs, -(op->h * op->h), bias, U, ldu, (double*)Y, s);
+  }
+  const hipError_t e2 = hipFreeAsync(Y, s);
+  if (e != hipSuccess) return pinv_hip_status(e);
+  return pinv_hip_status(e2);
+}
+}  // namespace
+
 int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits, const double* rho, int64_t ld_rho,
                            int32_t nrhs, double* u, int64_t ld_u, void* stream) {
   int32_t st = check_vectors(op, rho, ld_rho, nrhs, u, ld_u);
@@ -635,6 +677,8 @@ int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits, const dou
     case PINV_FP64:
       if (!op->G) return PINV_E_STATE;
       return fp64_apply(op, false, rho, ld_rho, nrhs, op->w, u, ld_u, s);
+    case PINV_FP64_SYM:
+      return sym_apply(op, rho, ld_rho, nrhs, op->w, u, ld_u, s);
     case PINV_INT8: {
       const int SR = slices_of_bits(rho_bits);
       if (!SR) return PINV_E_INVALID_ARG;
@@ -673,6 +717,8 @@ int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits, con
     case PINV_FP64:
       if (!op->G) return PINV_E_STATE;
       return fp64_apply(op, true, g, ld_g, nrhs, nullptr, lambda, ld_lambda, s);
+    case PINV_FP64_SYM:
+      return sym_apply(op, g, ld_g, nrhs, nullptr, lambda, ld_lambda, s);
     case PINV_INT8: {
       const int SR = slices_of_bits(g_bits);
       if (!SR) return PINV_E_INVALID_ARG;
@@ -900,6 +946,7 @@ int32_t pinv_get_info(pinv_op op, pinv_info* info) {
   info->device_bytes = op->bytes;
   info->nz = op->nz;
   info->beta = op->beta;
+  info->has_sym = op->Gsym != nullptr;
   info->general = op->general;
   return PINV_OK;
 }

@@ -50,6 +50,9 @@ struct pinv_op_s {
   __bf16* Gb = nullptr;      // [nbf][P][P]
   int nbf = 0;               // number of bfloat16 parts held (2 or 3)
 
+  // symmetric-packed FP64 copy: upper-triangle 64 x 64 blocks
+  double* Gsym = nullptr;
+
   int64_t bytes = 0;
 };
 
@@ -211,6 +214,17 @@ hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int
                              int nrhs, double alpha, double* U, int64_t ldu, hipStream_t s,
                              void* scratch, size_t scratch_bytes);
 size_t split_scratch_bytes(int mode, const pinv_op_s* op, int nrhs);
+
+// ---- symmetric-packed FP64 ------------------------------------------------------
+int sym_blocks_per_side(int n);
+size_t sym_packed_elems(int n);
+// scratch for launch_gemv_sym (partials of up to 8 right-hand sides)
+size_t sym_scratch_bytes(int n, int nrhs);
+hipError_t launch_sym_check(const double* G, int64_t ld, int n, int* flag, hipStream_t s);
+hipError_t launch_pack_upper(const double* G, int64_t ld, int n, double* Gp, hipStream_t s);
+// U = alpha * G X + bias from the packed copy; Y: sym_scratch_bytes(n, nrhs)
+hipError_t launch_gemv_sym(const double* Gp, int n, const double* X, int64_t ldx, int nrhs, double alpha,
+                           const double* bias, double* U, int64_t ldu, double* Y, hipStream_t s);
 
 // ---- gradient ------------------------------------------------------------------
 // nz = 0 for the 2-D operator.  part: scratch of grad_eps_chunks(nrhs) * (nodes)

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libpinv.so")
 
 OK, E_INVALID_ARG, E_NOT_SPD, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
-MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8": 4}
+MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8": 4, "fp64_sym": 5}
 SCALE_ROW = 0
 
 
@@ -47,7 +47,7 @@ class Info(ctypes.Structure):
                 ("has_fp64", ctypes.c_int32), ("int8_slices", ctypes.c_int32), ("has_fp32", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("has_lift", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("nz", ctypes.c_int32), ("general", ctypes.c_int32), ("beta", ctypes.c_int32),
-                ("_pad", ctypes.c_int32)]
+                ("has_sym", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):

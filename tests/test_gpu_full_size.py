@@ -60,6 +60,19 @@ def test_quant_128_int8_bit_exact_and_accuracy(torch, pinv, case):
     assert err.max() <= 1e-4
 
 
+def test_quant_128_fp64_sym_one_rhs(torch, pinv, case):
+    """The symmetric-packed FP64 form at 126^2 unknowns, one and three
+    right-hand sides (the pass-over-G regime), against the oracle's product."""
+    wl, G = case
+    n, h, rho = wl["n"], wl["h"], wl["rho"]
+    announce(f"full size fp64_sym n={n} nrhs=1,3")
+    with pinv.PoissonInverse.from_inverse(n, n, h, G) as op:
+        op.prepare_split("fp64_sym")
+        for r in (1, 3):
+            u = host(op.apply(dev(rho[:r]), "fp64_sym"))
+            assert np.max(metrics.rel_l2_per_rhs(u.T, apply.plain_apply(G, rho[:r].T, h))) <= 1e-12
+
+
 def test_quant_128_build_inverse_matches_dst(torch, pinv, case):
     wl, G = case
     n, h = wl["n"], wl["h"]
