@@ -129,6 +129,35 @@ def test_int8_apply_bit_exact(torch, pinv, nx, ny, bits, rho_bits):
     assert np.array_equal(u.T, ref)
 
 
+@pytest.mark.parametrize("nx,ny", [(3, 3), (12, 9), (40, 33)])
+@pytest.mark.parametrize("nrhs", [1, 2, 7, 16, 17])
+@pytest.mark.parametrize("bits,rho_bits", [(24, 16), (16, 16), (8, 24)])
+def test_int8_few_rhs_bit_exact(torch, pinv, nx, ny, nrhs, bits, rho_bits):
+    """Few right-hand sides (one padded 128-column tile, k split over several
+    workgroups): forward and adjoint bit for bit against the oracle's integer
+    product."""
+    announce(f"int8 few rhs nx={nx} ny={ny} nrhs={nrhs} bits={bits} rho_bits={rho_bits}")
+    g = np.random.default_rng(nx * nrhs + bits)
+    ub = g.standard_normal((ny, nx))
+    h = 1.0 / (max(nx, ny) - 1)
+    G, w, _ = oracle_inverse(nx, ny, workloads.random_eps(nx, ny, g), ub)
+    N = G.shape[0]
+    rho = g.uniform(-1, 1, (nrhs, N))
+    if nrhs > 1:
+        rho[1] = 0.0
+    ref, _, _ = oracle_int8(G, bits // 8, rho.T, rho_bits // 8, h, w)
+    S, Sg = bits // 8, rho_bits // 8
+    qG, e = quant.quantize_rows(G, S)
+    qg, f = quant.quantize_cols(rho.T, Sg, pre_exponent=e)
+    ref_adj, _ = apply.integer_apply(qG.T, e, S, qg, f, Sg, h, None, row_exponent=False)
+    with pinv.PoissonInverse.from_inverse(nx, ny, h, G, None, ub, w) as op:
+        op.quantize(bits)
+        u = host(op.apply(dev(rho), "int8", rho_bits))
+        lam = host(op.apply_adjoint(dev(rho), "int8", rho_bits))
+    assert np.array_equal(u.T, ref)
+    assert np.array_equal(lam.T, ref_adj)
+
+
 @pytest.mark.parametrize("nx,ny", [(12, 9), (50, 37), (66, 66)])
 def test_int8_adjoint_bit_exact(torch, pinv, nx, ny):
     """(66, 66): P = 4096 with one tile column, so the product splits k."""
