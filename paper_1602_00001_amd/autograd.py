@@ -8,8 +8,9 @@ class PinvSolve(torch.autograd.Function):
     """u = PinvSolve.apply(rho, eps, op, mode, bits).
 
     rho: [nrhs, N] float64 CUDA tensor.  eps: the nodal permittivity tensor
-    [n_y, n_x] the op was built from (only its gradient is produced here; the
-    op is not rebuilt).  op: a PoissonInverse.  Returns u [nrhs, N].
+    [n_y, n_x] ([n_z, n_y, n_x] for a 3-D op) the op was built from (only its
+    gradient is produced here; the op is not rebuilt).  op: a PoissonInverse
+    built on a uniform grid.  Returns u [nrhs, N].
     Gradients: drho = lambda = -h^2 G^T g, deps = nodal eps-gradient.
     """
 
