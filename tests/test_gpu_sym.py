@@ -90,3 +90,28 @@ def test_sym_refuses_non_symmetric_inverses(torch, pinv):
         with pytest.raises(pinv.PinvError) as ei:
             op.prepare_split("fp64_sym")
         assert ei.value.status == pinv.E_UNSUPPORTED
+
+
+def test_sym_batched_equals_per_request(torch, pinv):
+    """apply_batched in the packed mode runs each request as a single apply."""
+    announce("apply_batched fp64_sym")
+    g = np.random.default_rng(12)
+    ops, reqs = [], []
+    try:
+        for (nx, ny) in ((14, 11), (23, 19)):
+            G, _, _ = oracle_inverse(nx, ny)
+            op = pinv.PoissonInverse.from_inverse(nx, ny, 1.0 / (nx - 1), G)
+            op.prepare_split("fp64_sym")
+            ops.append((op, G))
+        for k in range(6):
+            op, G = ops[k % 2]
+            rho = dev(g.uniform(-1, 1, (1 + k, op.n)))
+            reqs.append((op, rho, torch.empty_like(rho), G))
+        pinv.apply_batched([(op, rho, u) for (op, rho, u, _) in reqs], "fp64_sym")
+        for (op, rho, u, G) in reqs:
+            assert np.array_equal(host(u), host(op.apply(rho, "fp64_sym")))
+            ref = apply.plain_apply(G, host(rho).T, op.h)
+            assert np.max(metrics.rel_l2_per_rhs(host(u).T, ref)) <= 1e-12
+    finally:
+        for op, _ in ops:
+            op.close()
