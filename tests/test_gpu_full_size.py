@@ -113,3 +113,21 @@ def test_plain_32_and_vareps_64(torch, pinv):
             print(f"[vareps_64] {mode}: rel L2 vs fp64 max {err.max():.3e} median {np.median(err):.3e}", flush=True)
             assert np.all(err <= tol64)
             assert np.all(metrics.rel_l2_per_rhs(um.T, emu) <= tol_emu)
+
+
+def test_vareps_64_quantised_envelope(torch, pinv):
+    """The accuracy contract on the GPU-built 62^2 operator (eps = 1 + 0.5 sin
+    cos, the workload's 256 drifting-blob right-hand sides): b-bit entries with
+    right-hand sides rounded to max(b, 16) bits stay within 2^-(b-2) relative L2
+    of the FP64 solve, b = 8, 16, 24."""
+    wl = workloads.vareps_64()
+    announce("vareps_64 int8 8/16/24-bit envelope")
+    with pinv.PoissonInverse.build(wl["n"], wl["n"], wl["h"], wl["eps"]) as op:
+        rho = dev(wl["rho"])
+        u64 = host(op.apply(rho, "fp64"))
+        for bits in (8, 16, 24):
+            op.quantize(bits)
+            u = host(op.apply(rho, "int8", max(bits, 16)))
+            err = np.max(metrics.rel_l2_per_rhs(u.T, u64.T))
+            print(f"[vareps_64] {bits}-bit: max rel L2 {err:.3e} (bound {2.0 ** -(bits - 2):.3e})", flush=True)
+            assert err <= 2.0 ** -(bits - 2)
