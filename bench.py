@@ -212,6 +212,7 @@ def main():
         "quantize_rho_avg_ms": qc_ms / max(qc_n, 1),
         "setup_s": {"build_inverse": t_build, "quantize_inverse": t_quant, "autotune_int8": t_tune},
         "int8_variant": {"chosen": variant, "ms_per_launch": variant_ms},
+        "paper_operation_counts": _paper_counts(wl["n"], args.bits, args.rho_bits),
     }
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
@@ -249,6 +250,26 @@ def _autotune(op, args, rho_bits, rho):
     if args.no_autotune:
         return 0, None
     return op.autotune_int8(rho_bits, rho=rho, reps=5)
+
+
+def _paper_counts(n, bits, rho_bits):
+    """Operation counts per solve that the paper gives (context, not a target),
+    with its N = all n^2 grid nodes and m = 4 decimal digits (the 1e-4 accuracy
+    of the metric): Eq. 8 for SOR/Seidel, Eqs. 9-10 for the authors' fast
+    product, 2N^2 for a plain matrix-vector product (line 1 of Fig. 4); and the
+    integer operations this implementation executes (2 N_interior^2 per digit
+    pair)."""
+    import math
+    N = n * n
+    m = 4
+    ni = (n - 2) ** 2
+    return {"N_nodes": N, "m_digits": m,
+            "iterative_eq8": 10.0 * math.log(10.0) / math.pi * m * N * N,
+            "fast_product_eq9_eq10": (2.5 + 14.2) * m ** 2.5 * N,
+            "dense_matvec_fig4_line1": 2.0 * N * N,
+            "this_int8_slices": 2.0 * (bits // 8) * (rho_bits // 8) * ni * ni,
+            "note": "elementary operations per right-hand side; the int8 figure counts the 8-bit multiplies and "
+                    "adds done on the matrix cores, the paper's figures count scalar operations"}
 
 
 def _timed(fn, steps, warmup):
