@@ -422,12 +422,19 @@ hipError_t launch_splitk_reduce(const double* part, int ksplit, int M, int N, do
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t s) {
-  if (a.M <= 0 || a.N <= 0) return hipSuccess;
-  const int tilesM = (a.M + BM - 1) / BM, tilesN = (a.N + BN - 1) / BN;
+hipError_t launch_gemm_f64(const GemmF64Args& a_in, hipStream_t s) {
+  if (a_in.M <= 0 || a_in.N <= 0) return hipSuccess;
+  const int tilesM = (a_in.M + BM - 1) / BM, tilesN = (a_in.N + BN - 1) / BN;
   const int T = tilesM * tilesN;
   const int grid = ((T + 7) / 8) * 8;
-  if (a.a_kcontig && a.b_kcontig && !a.kdiag) {
+  // the NT kernel addresses a tile's rows with 32-bit element offsets
+  // (row in tile * ld + k); operands with larger strides take the generic
+  // kernel, unsplit
+  const uint64_t ldmax = (uint64_t)(a_in.lda > a_in.ldb ? a_in.lda : a_in.ldb);
+  const bool off32 = (uint64_t)(BM - 1) * ldmax + (uint64_t)a_in.K < (1ull << 32);
+  GemmF64Args a = a_in;
+  if (!off32) a.ksplit = 1;
+  if (a.a_kcontig && a.b_kcontig && !a.kdiag && off32) {
     const bool vec = (a.lda % 2 == 0) && (a.ldb % 2 == 0) && ((uintptr_t)a.A % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
     const bool split = a.ksplit > 1;
     if (split && (a.tri || !a.part || a.kchunk <= 0 || a.kchunk % BKK != 0 ||

@@ -129,6 +129,31 @@ def test_int8_apply_bit_exact(torch, pinv, nx, ny, bits, rho_bits):
     assert np.array_equal(u.T, ref)
 
 
+def test_apply_with_a_very_large_row_stride(torch, pinv):
+    """Right-hand sides 2^25 + 16 doubles apart (127 strides exceed 2^32
+    elements): the FP64 GEMM and the int8 path address them in 64 bits."""
+    announce("apply with row stride 2^25 + 16 (fp64 GEMM, int8)")
+    nx, ny = 12, 9
+    h = 1.0 / (nx - 1)
+    G, _, _ = oracle_inverse(nx, ny)
+    N = G.shape[0]
+    ld = (1 << 25) + 16
+    g = np.random.default_rng(21)
+    rho = g.uniform(-1, 1, (5, N))
+    big = torch.zeros((5, ld), dtype=torch.float64, device="cuda")
+    big[:, :N] = dev(rho)
+    out = torch.zeros((5, ld), dtype=torch.float64, device="cuda")
+    with pinv.PoissonInverse.from_inverse(nx, ny, h, G) as op:
+        op.apply(big[:, :N], "fp64", out=out[:, :N])
+        u = host(out[:, :N])
+        assert np.max(metrics.rel_l2_per_rhs(u.T, apply.plain_apply(G, rho.T, h))) <= 1e-12
+        op.quantize(24)
+        op.apply(big[:, :N], "int8", 16, out=out[:, :N])
+        ref, _, _ = oracle_int8(G, 3, rho.T, 2, h)
+        assert np.array_equal(host(out[:, :N]).T, ref)
+    del big, out
+
+
 @pytest.mark.parametrize("nx,ny", [(3, 3), (12, 9), (40, 33)])
 @pytest.mark.parametrize("nrhs", [1, 2, 7, 16, 17])
 @pytest.mark.parametrize("bits,rho_bits", [(24, 16), (16, 16), (8, 24)])
