@@ -231,8 +231,10 @@ int32_t pinv_export_quantized(pinv_op op, int8_t* slices_host, int32_t* exponent
  *   rho, u    device, column-major N x nrhs with strides ld_rho, ld_u >= N;
  *             must not overlap.  nrhs >= 0 (0 is a no-op).
  * Asynchronous.  PINV_E_STATE if the mode's representation is missing;
- * PINV_E_UNSUPPORTED if the int32 class accumulators could overflow
- * (N * 16384 * pairs-per-class >= 2^31) or N * M_S * M_Sr >= 2^63. */
+ * PINV_E_UNSUPPORTED in INT8 mode if N * M_S * M_Sr >= 2^63 (the exact int64
+ * recombination).  Where one int32 class sum over all of k could overflow
+ * (N * 16384 * pairs-per-class >= 2^31), k is split and the parts are added in
+ * int64, taking a stream-ordered scratch of the class sums from the pool. */
 int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits,
                            const double* rho, int64_t ld_rho, int32_t nrhs,
                            double* u, int64_t ld_u, void* stream);
@@ -290,7 +292,9 @@ int32_t pinv_grad_eps_general(pinv_op op, const double* u, int64_t ld_u,
  * one by one.  Every request is checked before anything is launched; requests
  * must not write into each other's rho or u.  The call waits for work already
  * queued on the stream once, to upload its column table; the products
- * themselves are asynchronous. */
+ * themselves are asynchronous.  In INT8 mode an op whose class sums over all
+ * of k could overflow int32 (N * 16384 * pairs-per-class >= 2^31; the grouped
+ * product does not split k) gives PINV_E_UNSUPPORTED, with nothing launched. */
 typedef struct {
   pinv_op        op;
   const double*  rho;     /* device, column-major N x nrhs, stride ld        */

@@ -169,12 +169,23 @@ int slices_of_bits(int bits) { return (bits == 8 || bits == 16 || bits == 24) ? 
 // int32 class headroom: the largest class has min(S, SR) slice pairs, each
 // contributing at most n * 128 * 128 in magnitude.  The int64 recombination
 // needs n * M_S * M_SR < 2^63.
+// The exact recombination in int64 holds while N M_S M_SR < 2^63.
+bool int8_total_ok(int n, int S, int SR) {
+  return (double)n * (double)pinv_max_mag(S) * (double)pinv_max_mag(SR) < 9.2e18;
+}
+
+// Largest k range one int32 class accumulator may cover: every term of a class
+// is at most 128 * 128 per digit pair, and at most min(S, SR) pairs share a
+// class, so k * 16384 * pairs must stay below 2^31.  A multiple of 256.
+int64_t int8_k_limit(int S, int SR) {
+  const int64_t pairs = S < SR ? S : SR;
+  return (2147483647LL / (16384LL * pairs)) / 256 * 256;
+}
+
+// The whole of k in one accumulation (the grouped launches do not split k).
 bool int8_headroom_ok(int n, int S, int SR) {
   const int pairs = S < SR ? S : SR;
-  const double cls = (double)n * 16384.0 * pairs;
-  if (cls >= 2147483648.0) return false;
-  const double tot = (double)n * (double)pinv_max_mag(S) * (double)pinv_max_mag(SR);
-  return tot < 9.2e18;
+  return (double)n * 16384.0 * pairs < 2147483648.0 && int8_total_ok(n, S, SR);
 }
 
 int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const int32_t* pre_exp, int SR,
@@ -184,6 +195,13 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
   const int variant = op->i8_variant[SR];
   int ksplit = 1, kchunk = (int)op->P;
   gemm_i8_split_plan(op->P, Rpad, variant, &ksplit, &kchunk);
+  // k is split (exact int64 sum of the parts) wherever one int32 accumulation
+  // over it could overflow
+  const int64_t klim = int8_k_limit(op->S, SR);
+  if (kchunk > klim) {
+    kchunk = (int)klim;
+    ksplit = (int)((op->P + klim - 1) / klim);
+  }
   const size_t xq_bytes = (size_t)SR * Rpad * op->P;
   const size_t f_bytes = ((size_t)Rpad * sizeof(int32_t) + 255) / 256 * 256;
   const size_t part_bytes = ksplit > 1 ? (size_t)ksplit * (op->S + SR - 1) * Rpad * op->P * sizeof(int32_t) : 0;
@@ -683,7 +701,7 @@ int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits, const dou
       const int SR = slices_of_bits(rho_bits);
       if (!SR) return PINV_E_INVALID_ARG;
       if (!op->S) return PINV_E_STATE;
-      if (!int8_headroom_ok(op->n, op->S, SR)) return PINV_E_UNSUPPORTED;
+      if (!int8_total_ok(op->n, op->S, SR)) return PINV_E_UNSUPPORTED;
       return int8_apply(op, op->Q, op->e, nullptr, SR, rho, ld_rho, nrhs, op->w, u, ld_u, s);
     }
     case PINV_FP32:
@@ -723,7 +741,7 @@ int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits, con
       const int SR = slices_of_bits(g_bits);
       if (!SR) return PINV_E_INVALID_ARG;
       if (!op->S) return PINV_E_STATE;
-      if (!int8_headroom_ok(op->n, op->S, SR)) return PINV_E_UNSUPPORTED;
+      if (!int8_total_ok(op->n, op->S, SR)) return PINV_E_UNSUPPORTED;
       return int8_apply(op, op->QT, nullptr, op->e, SR, g, ld_g, nrhs, nullptr, lambda, ld_lambda, s);
     }
     default:

@@ -1,9 +1,10 @@
-"""The largest operator the int8 path's headroom check admits at 16-bit
-digits: a 258 x 258 grid, N = 256^2 = 65536 interior unknowns, a 34 GB FP64
+"""A 258 x 258 grid, N = 256^2 = 65536 interior unknowns, a 34 GB FP64
 inverse built on the GPU.  FP64 applies against the oracle's banded-Cholesky
 solve; 8-bit entries x 16-bit right-hand sides within their envelope; 24-bit
-entries x 16-bit right-hand sides refused (two digit pairs share a class, and
-N * 128 * 128 * 2 reaches 2^31: the int32 class sums could overflow)."""
+entries x 16-bit right-hand sides, where two digit pairs share a class and
+N * 128 * 128 * 2 reaches 2^31, run with k split (int32 class sums per part,
+added in int64) within their envelope; the grouped batched product, which does
+not split k, refuses that op."""
 
 import numpy as np
 import pytest
@@ -36,6 +37,11 @@ def test_max_size_operator():
         print(f"[max size] 8-bit x 16-bit vs fp64: {err8:.3e}", flush=True)
         assert err8 <= 2.0 ** -6
         op.quantize(24)
+        u24 = host(op.apply(dev(rho), "int8", 16))
+        err24 = np.max(metrics.rel_l2_per_rhs(u24.T, u.T))
+        print(f"[max size] 24-bit x 16-bit (k split) vs fp64: {err24:.3e}", flush=True)
+        assert err24 <= 2.0 ** -14
+        x = dev(rho)
         with pytest.raises(pinv.PinvError) as ei:
-            op.apply(dev(rho), "int8", 16)
+            pinv.apply_batched([(op, x, torch.empty_like(x))], "int8", 16)
         assert ei.value.status == pinv.E_UNSUPPORTED
