@@ -29,17 +29,22 @@ __device__ inline void digits(int q, int8_t* d) {
   }
 }
 
-__device__ inline double block_max_256(double v, double* red) {
-  // wave reduction then across the 4 waves
+// maximum over the NW waves of the workgroup (red: NW doubles of LDS)
+template <int NW>
+__device__ inline double block_max(double v, double* red) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) red[wave] = v;
   __syncthreads();
-  v = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  v = red[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) v = fmax(v, red[w]);
   __syncthreads();
   return v;
 }
+
+__device__ inline double block_max_256(double v, double* red) { return block_max<4>(v, red); }
 
 // One wave per row: e[i] = exponent of max_k |G[i][k]| (0 for padding rows).
 __global__ __launch_bounds__(256) void row_exponent_kernel(const double* __restrict__ G, int64_t ldg, int n,
@@ -117,11 +122,11 @@ __global__ __launch_bounds__(256) void transpose_planes_kernel(const int8_t* __r
 // One workgroup per column r of X (column-major n x nrhs, stride ldx): the
 // exponent of its largest magnitude, then its rows of the output
 // [SR][Rpad][P] (rows n..P-1 and columns r >= nrhs are written as zeros).
-// Each thread handles 4 consecutive k of every 1024 (32-byte reads, 4-byte
-// writes per digit plane), so both the reads and the writes of a wave are
-// contiguous.  Columns of up to KR * 1024 entries are read once into registers
-// (all loads in flight together); longer ones are read twice, once for the
-// maximum and once for the digits.
+// Each thread handles 4 consecutive k of every 4 x (threads) (32-byte reads,
+// 4-byte writes per digit plane), so both the reads and the writes of a wave
+// are contiguous.  Columns of up to 16384 entries (256 threads) or 40960
+// (1024 threads) are read once into registers (all loads in flight together);
+// longer ones are read twice, once for the maximum and once for the digits.
 template <int SR>
 __device__ __attribute__((always_inline)) inline void quantize_col_two_pass(const double* __restrict__ x, bool live, int n, int r, int Rpad, int64_t P,
                                     const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
@@ -174,24 +179,21 @@ __device__ __attribute__((always_inline)) inline void quantize_col_two_pass(cons
   }
 }
 
-constexpr int KR = 16;
-
-template <int SR>
-__device__ __attribute__((always_inline)) inline void quantize_col(const double* __restrict__ x, bool live, int n, int r, int Rpad, int64_t P,
-                                    const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
-                                    int32_t* __restrict__ f, double* red) {
-  if (n > KR * 1024) {
-    quantize_col_two_pass<SR>(x, live, n, r, Rpad, P, pre, Xq, f, red);
-    return;
-  }
+// Column in registers: NT threads, KR chunks of 4 NT entries (thread t holds
+// entries 4t .. 4t+3 of every chunk); for columns of up to 4 NT KR entries.
+template <int SR, int NT, int KR>
+__device__ __attribute__((always_inline)) inline void quantize_col_regs(
+    const double* __restrict__ x, bool live, int n, int r, int Rpad, int64_t P, const int32_t* __restrict__ pre,
+    int8_t* __restrict__ Xq, int32_t* __restrict__ f, double* red) {
+  constexpr int STR = 4 * NT;
   // (chunk c is read when it holds entries; the condition is uniform, and the
   // loads of a chunk are unconditional from clamped indices)
   double v[KR][4];
   double m = 0.0;
 #pragma unroll
   for (int c = 0; c < KR; ++c) {
-    const int64_t k0 = (int64_t)c * 1024 + threadIdx.x * 4;
-    if (live && c * 1024 < n) {
+    const int64_t k0 = (int64_t)c * STR + threadIdx.x * 4;
+    if (live && c * STR < n) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t k = min(k0 + t, (int64_t)n - 1);
@@ -205,14 +207,14 @@ __device__ __attribute__((always_inline)) inline void quantize_col(const double*
 #pragma unroll
   for (int c = 0; c < KR; ++c)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) m = fmax(m, (int64_t)c * 1024 + threadIdx.x * 4 + t < n ? fabs(v[c][t]) : 0.0);
-  m = block_max_256(m, red);
+    for (int t = 0; t < 4; ++t) m = fmax(m, (int64_t)c * STR + threadIdx.x * 4 + t < n ? fabs(v[c][t]) : 0.0);
+  m = block_max<NT / 64>(m, red);
   const int fr = frexp_exp(m);
   if (live && threadIdx.x == 0) f[r] = fr;
   const double M = (double)(127LL * ((1LL << (8 * SR)) - 1) / 255);
 #pragma unroll
   for (int c = 0; c < KR; ++c) {
-    const int64_t k0 = (int64_t)c * 1024 + threadIdx.x * 4;
+    const int64_t k0 = (int64_t)c * STR + threadIdx.x * 4;
     if (k0 >= P) break;
     int8_t d[SR][4];
 #pragma unroll
@@ -233,6 +235,24 @@ __device__ __attribute__((always_inline)) inline void quantize_col(const double*
   }
 }
 
+// 256 threads: columns of up to 16384 entries in registers, longer ones in
+// two passes
+constexpr int KR = 16;
+
+template <int SR>
+__device__ __attribute__((always_inline)) inline void quantize_col(const double* __restrict__ x, bool live, int n, int r, int Rpad, int64_t P,
+                                    const int32_t* __restrict__ pre, int8_t* __restrict__ Xq,
+                                    int32_t* __restrict__ f, double* red) {
+  if (n > KR * 1024) {
+    quantize_col_two_pass<SR>(x, live, n, r, Rpad, P, pre, Xq, f, red);
+    return;
+  }
+  quantize_col_regs<SR, 256, KR>(x, live, n, r, Rpad, P, pre, Xq, f, red);
+}
+
+// 1024 threads: columns of 16385 to KRW * 4096 entries in registers
+constexpr int KRW = 10;
+
 template <int SR>
 __global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __restrict__ X, int64_t ldx,
                                                            const double* const* __restrict__ xcols, int n,
@@ -244,6 +264,19 @@ __global__ __launch_bounds__(256) void quantize_cols_kernel(const double* __rest
   const bool live = r < nrhs;
   const double* x = live ? (xcols ? xcols[r] : X + (int64_t)r * ldx) : X;
   quantize_col<SR>(x, live, n, r, Rpad, P, pre, Xq, f, red);
+}
+
+template <int SR>
+__global__ __launch_bounds__(1024) void quantize_cols_wide_kernel(const double* __restrict__ X, int64_t ldx,
+                                                                 const double* const* __restrict__ xcols, int n,
+                                                                 int nrhs, int Rpad, int64_t P,
+                                                                 const int32_t* __restrict__ pre,
+                                                                 int8_t* __restrict__ Xq, int32_t* __restrict__ f) {
+  __shared__ double red[16];
+  const int r = blockIdx.x;
+  const bool live = r < nrhs;
+  const double* x = live ? (xcols ? xcols[r] : X + (int64_t)r * ldx) : X;
+  quantize_col_regs<SR, 1024, KRW>(x, live, n, r, Rpad, P, pre, Xq, f, red);
 }
 
 // Grouped form: workgroup b serves group g with g.col0 <= b < next group's
@@ -322,6 +355,15 @@ hipError_t launch_transpose_planes(const int8_t* Q, int8_t* QT, int S, int64_t P
 hipError_t launch_quantize_cols(const double* X, int64_t ldx, const double* const* xcols, int n, int nrhs, int Rpad,
                                 int SR, int64_t P, const int32_t* pre_exp, int8_t* Xq, int32_t* f, hipStream_t s) {
   const dim3 grid((unsigned)Rpad);
+  if (n > KR * 1024 && n <= KRW * 4096) {
+    switch (SR) {
+      case 1: hipLaunchKernelGGL(quantize_cols_wide_kernel<1>, grid, dim3(1024), 0, s, X, ldx, xcols, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
+      case 2: hipLaunchKernelGGL(quantize_cols_wide_kernel<2>, grid, dim3(1024), 0, s, X, ldx, xcols, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
+      case 3: hipLaunchKernelGGL(quantize_cols_wide_kernel<3>, grid, dim3(1024), 0, s, X, ldx, xcols, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (SR) {
     case 1: hipLaunchKernelGGL(quantize_cols_kernel<1>, grid, dim3(256), 0, s, X, ldx, xcols, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
     case 2: hipLaunchKernelGGL(quantize_cols_kernel<2>, grid, dim3(256), 0, s, X, ldx, xcols, n, nrhs, Rpad, P, pre_exp, Xq, f); break;

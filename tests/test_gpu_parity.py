@@ -323,3 +323,23 @@ def test_invalid_arguments(torch, pinv):
             op.apply(x, "fp64")
         assert ei.value.status == pinv.E_STATE
         assert op.apply(x, "int8", 16).shape == x.shape
+
+
+def test_int8_apply_long_columns_bit_exact(torch, pinv):
+    """Right-hand sides of 16500 entries take the 1024-thread quantiser (columns
+    of 16385-40960 entries held in registers): bit for bit against the oracle's
+    integer apply, on an imported random inverse."""
+    nx, ny = 1652, 12                       # N = 1650 * 10 = 16500
+    N = (nx - 2) * (ny - 2)
+    announce(f"int8 apply, long columns N={N}")
+    g = np.random.default_rng(23)
+    G = g.standard_normal((N, N))
+    rho = g.uniform(-1, 1, (3, N))
+    rho[1] *= 1e-5
+    h = 0.01
+    ref, _, _ = oracle_int8(G, 3, rho.T, 2, h)
+    with pinv.PoissonInverse.from_inverse(nx, ny, h, G) as op:
+        del G
+        op.quantize(24, keep_fp64=False)
+        u = host(op.apply(dev(rho), "int8", 16))
+    assert np.array_equal(u.T, ref)
