@@ -1,7 +1,8 @@
-"""The FP64 GEMV apply (at most 4 right-hand sides) allocates nothing and
-records no memset, so a time loop of applies can be captured in a HIP graph:
-every replay, with eager work and synchronisations in between, gives the eager
-result bit for bit."""
+"""Applies captured in a HIP graph: the FP64 GEMV apply (at most 4 right-hand
+sides; allocates nothing), the int8 apply (its stream-ordered scratch becomes
+alloc and free nodes; the split-K epilogue at 64^2) and the symmetric-packed
+FP64 apply.  Every replay, with eager work and synchronisations in between,
+gives the eager result bit for bit."""
 
 import numpy as np
 import pytest
@@ -50,4 +51,40 @@ def test_graph_replay_of_fp64_gemv_apply(torch, nrhs):
             torch.cuda.synchronize()
             del other
         assert np.max(np.abs(host(u).T - ref)) <= 1e-12 * np.max(np.abs(ref))
+        del graph
+
+
+@pytest.mark.parametrize("nx,nrhs,mode", [(32, 200, "int8"), (66, 200, "int8"), (40, 3, "fp64_sym")])
+def test_graph_replay_of_int8_and_packed_applies(torch, nx, nrhs, mode):
+    from paper_1602_00001_amd import pinv
+    announce(f"HIP graph of 4 {mode} applies nx={nx} nrhs={nrhs}")
+    h = 1.0 / (nx - 1)
+    G, _, _ = oracle_inverse(nx, nx)
+    g = np.random.default_rng(nx + nrhs)
+    with pinv.PoissonInverse.from_inverse(nx, nx, h, G) as op:
+        if mode == "int8":
+            op.quantize(24)
+        else:
+            op.prepare_split("fp64_sym")
+        rho = dev(g.uniform(-1, 1, (nrhs, G.shape[0])))
+        eager = op.apply(rho, mode, 16)
+        u = torch.full_like(rho, float("nan"))
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            op.apply(rho, mode, 16, out=u)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for _ in range(4):
+                op.apply(rho, mode, 16, out=u)
+        for rep in range(4):
+            u.fill_(float("nan"))
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(u, eager), rep
+            other = op.apply(dev(g.uniform(-1, 1, (nrhs, G.shape[0]))), mode, 16)
+            torch.cuda.synchronize()
+            del other
         del graph
