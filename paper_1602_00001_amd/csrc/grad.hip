@@ -7,13 +7,14 @@
 // values, so a node receives half of the gradient of each face it touches.
 // Faces that join two boundary nodes are not part of the operator.
 //
-// The right-hand sides are split into chunks of RC; workgroup (b, c) takes 256
-// nodes and chunk c, one thread per node: for each of its right-hand sides the
-// thread reads its own (u, lambda) and those of its 4 (2-D) or 6 (3-D)
-// neighbours (the threads of a wave read consecutive nodes, so the loads are
-// coalesced and the neighbours' come from cache) and adds the face products.  Each chunk's
-// partial sums go to scratch; a second kernel adds the chunks in order and
-// scales.  Every sum has a fixed order, so the result is deterministic.
+// The right-hand sides are split into chunks of RC; a workgroup takes 256
+// nodes and one chunk, one thread per node, and for each right-hand side adds
+// the products of the node's faces.  The 3-D form reads each node's own
+// (u, lambda) and its 6 neighbours' from global memory (the threads of a wave
+// read consecutive nodes, so the loads are coalesced and the neighbours' come
+// from cache); the 2-D form stages a tile with its halo in LDS first.  Each
+// chunk's partial sums go to scratch; a second kernel adds the chunks in order
+// and scales.  Every sum has a fixed order, so the result is deterministic.
 
 #include "common.h"
 
@@ -86,6 +87,96 @@ __global__ __launch_bounds__(256) void grad_eps_partial_kernel(int nx, int ny, i
     out[node] = 0.5 * total / (h * h);
   else
     out[(int64_t)blockIdx.y * nodes + node] = total;
+}
+
+// 2-D form with the right-hand side's values staged in LDS: a workgroup takes
+// a tile of TY rows x TX columns of nodes; for each right-hand side of its
+// chunk the tile and a one-node halo of (u, lambda) are loaded once into LDS
+// (u_B and 0 on boundary nodes; coalesced row segments), then each thread
+// forms the face products of its node from LDS.  Two LDS buffers alternate,
+// so one barrier per right-hand side suffices.  Same products, same order of
+// summation as the node kernel above, so the results are identical.
+constexpr int TX = 64, TY = 4;
+constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
+
+__global__ __launch_bounds__(256) void grad_eps_tile_kernel(int nx, int ny, double h, const double* __restrict__ u,
+                                                           int64_t ldu, const double* __restrict__ lam, int64_t ldl,
+                                                           int nrhs, const double* __restrict__ ub,
+                                                           double* __restrict__ out, int final_scale) {
+  __shared__ double su[2][HN], sl[2][HN];
+  const int tilesX = (nx + TX - 1) / TX;
+  const int tx0 = (int)(blockIdx.x % tilesX) * TX, ty0 = (int)(blockIdx.x / tilesX) * TY;
+  const int r0 = blockIdx.y * RC;
+  const int r1 = min(nrhs, r0 + RC);
+  const int tid = threadIdx.x;
+  const int mx = nx - 2;
+  auto boundary = [&](int a, int b) { return a == 0 || a == ny - 1 || b == 0 || b == nx - 1; };
+
+  // staged nodes of this thread: e = tid and tid + 256 (of HN = 396)
+  constexpr int SPT = (HN + 255) / 256;
+  int64_t off[SPT];
+  bool inter[SPT], live[SPT];
+  double ubv[SPT];
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    const int e = tid + 256 * k;
+    const int gi = ty0 - 1 + e / HX, gj = tx0 - 1 + e % HX;
+    live[k] = e < HN;
+    const bool valid = live[k] && gi >= 0 && gi < ny && gj >= 0 && gj < nx;
+    inter[k] = valid && !boundary(gi, gj);
+    off[k] = inter[k] ? (int64_t)(gi - 1) * mx + (gj - 1) : 0;
+    ubv[k] = (valid && !inter[k] && ub) ? ub[(int64_t)gi * nx + gj] : 0.0;
+  }
+
+  // this thread's node and its faces (the node kernel's rule)
+  const int li = tid / TX, lj = tid % TX;
+  const int i = ty0 + li, j = tx0 + lj;
+  const bool mine = i < ny && j < nx;
+  const bool bp = mine && boundary(i, j);
+  const int ni[4] = {i - 1, i + 1, i, i};
+  const int nj[4] = {j, j, j - 1, j + 1};
+  const int slot_p = (li + 1) * HX + (lj + 1);
+  const int dslot[4] = {-HX, HX, -1, 1};
+  bool use[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = ni[t], l = nj[t];
+    const bool inside = k >= 0 && k < ny && l >= 0 && l < nx;
+    const bool bq = !inside || boundary(k, l);
+    use[t] = mine && inside && !(bp && bq);
+  }
+
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = r0; r < r1; ++r) {
+    const int b = (r - r0) & 1;
+    const double* ur = u + (int64_t)r * ldu;
+    const double* lr = lam + (int64_t)r * ldl;
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      // (unconditional loads from a valid offset; the value is selected after)
+      const double uv = ur[off[k]];
+      const double lv = lr[off[k]];
+      if (live[k]) {
+        su[b][tid + 256 * k] = inter[k] ? uv : ubv[k];
+        sl[b][tid + 256 * k] = inter[k] ? lv : 0.0;
+      }
+    }
+    __syncthreads();
+    const double up = su[b][slot_p], lp = sl[b][slot_p];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (!use[t]) continue;
+      const double uq = su[b][slot_p + dslot[t]], lq = sl[b][slot_p + dslot[t]];
+      acc[t] += (lp - lq) * (up - uq);
+    }
+  }
+  if (!mine) return;
+  const int node = i * nx + j;
+  const double total = ((acc[0] + acc[1]) + acc[2]) + acc[3];
+  if (final_scale)
+    out[node] = 0.5 * total / (h * h);
+  else
+    out[(int64_t)blockIdx.y * nx * ny + node] = total;
 }
 
 __global__ __launch_bounds__(256) void grad_eps_reduce_kernel(int nodes, int chunks, double h,
@@ -203,8 +294,8 @@ hipError_t launch_grad_eps(int nx, int ny, int nz, double h, const double* u, in
       hipLaunchKernelGGL(grad_eps_partial_kernel<3>, grid, dim3(256), 0, s, nx, ny, nz, h, u, ldu, lam, ldl, nrhs,
                          ub, dst, final_scale);
     else
-      hipLaunchKernelGGL(grad_eps_partial_kernel<2>, grid, dim3(256), 0, s, nx, ny, 0, h, u, ldu, lam, ldl, nrhs, ub,
-                         dst, final_scale);
+      hipLaunchKernelGGL(grad_eps_tile_kernel, dim3(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY), grid.y), dim3(256), 0,
+                         s, nx, ny, h, u, ldu, lam, ldl, nrhs, ub, dst, final_scale);
     return hipGetLastError();
   };
   // zero or one chunk: the partial kernel writes the scaled result directly
