@@ -28,6 +28,9 @@
  *
  * Precision modes of the apply (inputs and outputs are FP64 in every mode):
  *   PINV_FP64   G in FP64, FP64 matrix-core product.
+ *   PINV_FP64_SYM  the same values from a symmetric-packed copy of G (the
+ *               64 x 64 blocks on and above the diagonal): one pass over about
+ *               half the bytes, for few right-hand sides.
  *   PINV_FP32   G and rho rounded to FP32, FP32 products, FP32 accumulation.
  *   PINV_BF16X3 G and rho split into 2 bfloat16 parts each; hi*hi + hi*lo +
  *               lo*hi with FP32 accumulation.
