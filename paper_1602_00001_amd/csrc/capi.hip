@@ -880,11 +880,14 @@ int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
   std::memcpy(host.data(), cols.data(), cols.size() * sizeof(void*));
   QuantColsGroup* hq = (QuantColsGroup*)(host.data() + cols_bytes);
   GemmI8Group* hg = (GemmI8Group*)(host.data() + cols_bytes + qg_bytes);
-  struct Launch { int S, g0, ng, cols, tiles, variant; };
+  // per digit count: one grouped GEMM launch over all its groups, and two
+  // grouped quantisation launches (groups with 16385-40960-entry columns,
+  // which take 1024-thread workgroups, placed after the others)
+  struct Launch { int S, g0, ng, cols, tiles, variant, nn, cols_w; };
   std::vector<Launch> launches;
   int slot = 0;
   for (int S = 1; S <= 3; ++S) {
-    Launch L{S, slot, 0, 0, 0, 0};
+    Launch L{S, slot, 0, 0, 0, 0, 0, 0};
     double most = -1.0;
     for (int g = 0; g < ng; ++g)
       if (ops[g]->S == S) {
@@ -895,8 +898,9 @@ int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
         }
       }
     const int rows = gemm_i8_tile_rows(L.variant);
+    for (int pass = 0; pass < 2; ++pass)
     for (int g = 0; g < ng; ++g) {
-      if (ops[g]->S != S) continue;
+      if (ops[g]->S != S || quantize_cols_wide(ops[g]->n) != (pass == 1)) continue;
       pinv_op op = ops[g];
       QuantColsGroup& q = hq[slot];
       q.xcols = (const double* const*)(dcols + first[g]);
@@ -906,7 +910,7 @@ int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
       q.n = op->n;
       q.nrhs = (int)count[g];
       q.Rpad = (int)Rpad[g];
-      q.col0 = L.cols;
+      q.col0 = pass == 0 ? L.cols : L.cols_w;
       GemmI8Group& G = hg[slot];
       G.a.Q = op->Q; G.a.S = op->S;
       G.a.X = q.Xq; G.a.SR = SR;
@@ -921,7 +925,12 @@ int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
       G.tilesM = (int)(op->P / rows);
       G.tilesN = (int)(Rpad[g] / 128);
       G.tile0 = L.tiles;
-      L.cols += (int)Rpad[g];
+      if (pass == 0) {
+        L.cols += (int)Rpad[g];
+        ++L.nn;
+      } else {
+        L.cols_w += (int)Rpad[g];
+      }
       L.tiles += G.tilesM * G.tilesN;
       ++L.ng;
       ++slot;
@@ -937,7 +946,8 @@ int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
     if (e != hipSuccess) break;
     {
       TraceScope ts("quantize_cols", s);
-      e = launch_quantize_cols_grouped(dq + L.g0, L.ng, L.cols, SR, s);
+      e = launch_quantize_cols_grouped(dq + L.g0, L.nn, L.cols, SR, false, s);
+      if (e == hipSuccess) e = launch_quantize_cols_grouped(dq + L.g0 + L.nn, L.ng - L.nn, L.cols_w, SR, true, s);
     }
     if (e != hipSuccess) break;
     TraceScope ts("gemm_i8", s);

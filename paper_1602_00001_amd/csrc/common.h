@@ -202,7 +202,10 @@ struct QuantColsGroup {
   int64_t P;
   int n, nrhs, Rpad, col0;
 };
-hipError_t launch_quantize_cols_grouped(const QuantColsGroup* groups, int ngroups, int total_cols, int SR,
+// wide: every group's columns hold 16385 .. 40960 entries (quantize_cols_wide),
+// read by 1024-thread workgroups; otherwise 256-thread workgroups
+bool quantize_cols_wide(int n);
+hipError_t launch_quantize_cols_grouped(const QuantColsGroup* groups, int ngroups, int total_cols, int SR, bool wide,
                                         hipStream_t s);
 hipError_t launch_fill_random_i8(int8_t* p, size_t n, uint32_t seed, hipStream_t s);
 

@@ -298,6 +298,25 @@ __global__ __launch_bounds__(256) void quantize_cols_grouped_kernel(const QuantC
   quantize_col<SR>(x, live, g.n, r, g.Rpad, g.P, nullptr, g.Xq, g.f, red);
 }
 
+// Grouped form with 1024 threads, for groups whose columns hold 16385 to
+// KRW * 4096 entries.
+template <int SR>
+__global__ __launch_bounds__(1024) void quantize_cols_grouped_wide_kernel(const QuantColsGroup* __restrict__ groups,
+                                                                         int ngroups) {
+  __shared__ double red[16];
+  const int b = blockIdx.x;
+  int lo = 0, hi = ngroups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].col0 <= b) lo = mid; else hi = mid - 1;
+  }
+  const QuantColsGroup g = groups[lo];
+  const int r = b - g.col0;
+  const bool live = r < g.nrhs;
+  const double* x = live ? g.xcols[r] : nullptr;
+  quantize_col_regs<SR, 1024, KRW>(x, live, g.n, r, g.Rpad, g.P, nullptr, g.Xq, g.f, red);
+}
+
 __global__ void fill_random_i8_kernel(int8_t* __restrict__ p, size_t n, uint32_t seed) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -317,10 +336,21 @@ hipError_t launch_fill_random_i8(int8_t* p, size_t n, uint32_t seed, hipStream_t
 
 int64_t pinv_max_mag(int S) { return 127LL * ((1LL << (8 * S)) - 1) / 255; }
 
-hipError_t launch_quantize_cols_grouped(const QuantColsGroup* groups, int ngroups, int total_cols, int SR,
+bool quantize_cols_wide(int n) { return n > KR * 1024 && n <= KRW * 4096; }
+
+hipError_t launch_quantize_cols_grouped(const QuantColsGroup* groups, int ngroups, int total_cols, int SR, bool wide,
                                         hipStream_t s) {
   if (ngroups <= 0 || total_cols <= 0) return hipSuccess;
   const dim3 grid((unsigned)total_cols);
+  if (wide) {
+    switch (SR) {
+      case 1: hipLaunchKernelGGL(quantize_cols_grouped_wide_kernel<1>, grid, dim3(1024), 0, s, groups, ngroups); break;
+      case 2: hipLaunchKernelGGL(quantize_cols_grouped_wide_kernel<2>, grid, dim3(1024), 0, s, groups, ngroups); break;
+      case 3: hipLaunchKernelGGL(quantize_cols_grouped_wide_kernel<3>, grid, dim3(1024), 0, s, groups, ngroups); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (SR) {
     case 1: hipLaunchKernelGGL(quantize_cols_grouped_kernel<1>, grid, dim3(256), 0, s, groups, ngroups); break;
     case 2: hipLaunchKernelGGL(quantize_cols_grouped_kernel<2>, grid, dim3(256), 0, s, groups, ngroups); break;
@@ -355,7 +385,7 @@ hipError_t launch_transpose_planes(const int8_t* Q, int8_t* QT, int S, int64_t P
 hipError_t launch_quantize_cols(const double* X, int64_t ldx, const double* const* xcols, int n, int nrhs, int Rpad,
                                 int SR, int64_t P, const int32_t* pre_exp, int8_t* Xq, int32_t* f, hipStream_t s) {
   const dim3 grid((unsigned)Rpad);
-  if (n > KR * 1024 && n <= KRW * 4096) {
+  if (quantize_cols_wide(n)) {
     switch (SR) {
       case 1: hipLaunchKernelGGL(quantize_cols_wide_kernel<1>, grid, dim3(1024), 0, s, X, ldx, xcols, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
       case 2: hipLaunchKernelGGL(quantize_cols_wide_kernel<2>, grid, dim3(1024), 0, s, X, ldx, xcols, n, nrhs, Rpad, P, pre_exp, Xq, f); break;
