@@ -169,3 +169,27 @@ def test_quantised_solve_error_envelope():
         errs[S] = np.max(metrics.rel_l2_per_rhs(u, ref))
     assert errs[1] > errs[2] > errs[3]
     assert errs[3] < 1e-4
+
+
+@pytest.mark.parametrize("S,tile", [(1, 3), (2, 4), (3, 5)])
+def test_quantize_tiles_brute_force(S, tile):
+    """2-D tile scales (one exponent per tile x tile block, ragged edge tiles):
+    every block quantised exactly like one row holding all of the block's
+    entries; an all-zero block gets exponent 0."""
+    g = np.random.default_rng(10 + S)
+    G = g.standard_normal((11, 13)) * np.exp(g.uniform(-6, 2, (11, 13)))
+    G[:tile, :tile] = 0.0
+    q, e = quant.quantize_tiles(G, S, tile)
+    tn, tk = -(-11 // tile), -(-13 // tile)
+    assert e.shape == (tn, tk)
+    for a in range(tn):
+        for b in range(tk):
+            blk = G[a * tile:(a + 1) * tile, b * tile:(b + 1) * tile]
+            qb, eb = _brute_quantize_row(blk.reshape(-1), S)
+            assert e[a, b] == eb
+            assert list(q[a * tile:(a + 1) * tile, b * tile:(b + 1) * tile].reshape(-1)) == qb
+    assert e[0, 0] == 0 and np.all(q[:tile, :tile] == 0)
+    # a tile as large as the matrix is one exponent for all of it
+    q1, e1 = quant.quantize_tiles(G, S, 16)
+    qb, eb = _brute_quantize_row(G.reshape(-1), S)
+    assert e1.shape == (1, 1) and e1[0, 0] == eb and list(q1.reshape(-1)) == qb
