@@ -24,21 +24,6 @@ def plain_apply(G, rho, h, w=None):
     return u
 
 
-def naive_apply(G, rho, h, w=None):
-    """The same product with in-order FP64 dot products, one row at a time
-    (used only to time the plain method on the CPU and on small cases)."""
-    G = np.asarray(G, dtype=np.float64)
-    rho = np.asarray(rho, dtype=np.float64)
-    N, R = G.shape[0], rho.shape[1]
-    u = np.empty((N, R), dtype=np.float64)
-    for i in range(N):
-        u[i] = G[i] @ rho
-    u *= -(h * h)
-    if w is not None:
-        u += np.asarray(w, dtype=np.float64)[:, None]
-    return u
-
-
 def integer_product(qG, qR):
     """acc[i, r] = sum_k qG[i, k] * qR[k, r], exact in int64."""
     return np.asarray(qG, dtype=np.int64) @ np.asarray(qR, dtype=np.int64)
@@ -67,11 +52,6 @@ def integer_apply(qG, e, S, qR, f, Sr, h, w=None, row_exponent=True):
     if w is not None:
         u = u + np.asarray(w, dtype=np.float64)[:, None]
     return u, acc
-
-
-def integer_apply_rows(qG_rows, e_rows, S, qR, f, Sr, h, w_rows=None):
-    """:func:`integer_apply` for a subset of rows (sampled checks)."""
-    return integer_apply(qG_rows, e_rows, S, qR, f, Sr, h, w_rows)
 
 
 def slice_pair_products(dG, dR):

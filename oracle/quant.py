@@ -29,12 +29,6 @@ def max_mag(S):
     return 127 * (256 ** S - 1) // 255
 
 
-def bits_to_slices(bits):
-    if bits not in (8, 16, 24):
-        raise ValueError("bits must be 8, 16 or 24")
-    return bits // 8
-
-
 def frexp_exponent(x):
     """Exponent e with |x| < 2^e (frexp convention), 0 for x == 0."""
     _, e = np.frexp(np.asarray(x, dtype=np.float64))
