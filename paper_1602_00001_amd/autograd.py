@@ -31,3 +31,33 @@ class PinvSolve(torch.autograd.Function):
         if ctx.needs_input_grad[1]:
             deps = op.grad_eps(u, lam)
         return lam, deps, None, None, None
+
+
+class PinvSolveGeneral(torch.autograd.Function):
+    """u = PinvSolveGeneral.apply(rho, eps_x, eps_y, op, mode, bits) for an op
+    from PoissonInverse.build_general (non-uniform grid, permittivity per
+    direction).  eps_y may be None when the op was built with one field for
+    both directions; eps_x then receives the whole gradient.
+    Gradients: drho = lambda = -(K^{-1} diag(A))^T g; deps_x, deps_y from the
+    x- and y-faces (pinv_grad_eps_general)."""
+
+    @staticmethod
+    def forward(ctx, rho, eps_x, eps_y, op, mode="fp64", bits=16):
+        u = op.apply(rho.contiguous(), mode=mode, rho_bits=bits)
+        ctx.op, ctx.mode, ctx.bits = op, mode, bits
+        ctx.split = eps_y is not None
+        ctx.save_for_backward(u)
+        return u
+
+    @staticmethod
+    def backward(ctx, g):
+        (u,) = ctx.saved_tensors
+        op = ctx.op
+        lam = op.apply_adjoint(g.contiguous(), mode=ctx.mode, g_bits=ctx.bits)
+        gx = gy = None
+        if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
+            if ctx.split:
+                gx, gy = op.grad_eps_general(u, lam, split=True)
+            else:
+                gx = op.grad_eps_general(u, lam, split=False)
+        return lam, gx, gy, None, None, None
