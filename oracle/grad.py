@@ -237,3 +237,27 @@ def grad_eps_general(x, y, u_int, lam_int, ub_nodes=None):
             gy[i, j] += 0.5 * gf
             gy[i + 1, j] += 0.5 * gf
     return gx, gy
+
+
+def grad_beta(nx, ny, u_int, lam_int, ub_nodes=None):
+    """dLoss/dbeta for Eq. 3's operator (:func:`grid.beta_operator`), where
+    u = A^{-1}(rho + b_B), A[p,q_d] = -beta_d(p)/4 and b_B[p] carries
+    beta_d(p)/4 u_B(q_d) for boundary neighbours.  With lambda = dLoss/drho =
+    A^{-T} g (the adjoint output), dLoss/dbeta_d(p) = lambda^T (db/dbeta -
+    dA/dbeta u) = (1/4) sum_r lambda_p U_{q_d}, U_q = u_q at interior q and
+    u_B(q) on the boundary.  Returns [4][n_y][n_x] (zero off the interior)."""
+    my, mx = ny - 2, nx - 2
+    u_int = np.asarray(u_int, dtype=np.float64).reshape(my * mx, -1)
+    lam_int = np.asarray(lam_int, dtype=np.float64).reshape(my * mx, -1)
+    R = u_int.shape[1]
+    U = np.zeros((ny, nx, R))
+    if ub_nodes is not None:
+        U[:, :, :] = np.asarray(ub_nodes, dtype=np.float64)[:, :, None]
+    U[1:-1, 1:-1, :] = u_int.reshape(my, mx, R)
+    out = np.zeros((4, ny, nx))
+    for i in range(1, ny - 1):
+        for j in range(1, nx - 1):
+            lp = lam_int[(i - 1) * mx + (j - 1)]
+            for d, (di, dj) in enumerate(_grid.BETA_DIRECTIONS):
+                out[d, i, j] = 0.25 * float(np.sum(lp * U[i + di, j + dj]))
+    return out

@@ -214,3 +214,36 @@ def test_grad_eps_general_matches_central_differences():
     gx, gy = grad.grad_eps_general(t, t, uu, ll, None)
     ref = grad.grad_eps_nodes(n, n, h, uu, ll, None)
     assert np.allclose(gx + gy, ref, rtol=1e-12, atol=1e-12 * np.max(np.abs(ref)))
+
+
+def test_grad_beta_matches_central_differences():
+    """Eq. 3 with arbitrary coefficients: dLoss/dbeta against central
+    differences of the dense re-solved loss (the adjoint output is A^{-T} g)."""
+    g = np.random.default_rng(71)
+    nx, ny = 8, 7
+    beta = g.uniform(0.2, 1.0, (4, ny, nx))
+    ub = g.standard_normal((ny, nx))
+    N = (nx - 2) * (ny - 2)
+    rho = g.standard_normal((N, 2))
+    sample = np.sort(g.choice(N, 9, replace=False))
+    d = 0.01 * g.standard_normal((9, 2))
+
+    def solve(b):
+        A, bB = grid.beta_operator(nx, ny, b, ub)
+        return np.linalg.solve(A, rho + bB[:, None]), A
+
+    def loss(b):
+        u, _ = solve(b)
+        r = u[sample] - d
+        return float(np.sum(r * r))
+
+    u, A = solve(beta)
+    gu = grad.sampling_loss_grad_u(u, sample, d)
+    lam = np.linalg.solve(A.T, gu)
+    gb = grad.grad_beta(nx, ny, u, lam, ub)
+    assert np.all(gb[:, 0, :] == 0) and np.all(gb[:, :, -1] == 0)
+    for _ in range(3):
+        v = g.standard_normal((4, ny, nx))
+        fd = grad.central_difference(loss, beta, v, 1e-6)
+        an = float(np.sum(gb * v))
+        assert abs(fd - an) <= 1e-6 * abs(fd), (fd, an)
