@@ -286,6 +286,21 @@ int32_t pinv_grad_eps_general(pinv_op op, const double* u, int64_t ld_u,
                               const double* lambda, int64_t ld_lambda, int32_t nrhs,
                               double* grad_x, double* grad_y, void* stream);
 
+/* Gradient with respect to Eq. 3's coefficients (not in the paper), for an op
+ * from pinv_build_inverse_beta: with u = A^{-1}(rho + b_B) the forward
+ * solutions and lambda = A^{-T} g the adjoint outputs of the same loss
+ * (pinv_apply_inverse_adjoint on the op),
+ *   dLoss/dbeta_d(p) = (1/4) sum_r lambda_p U_{q_d},
+ * U = u at interior nodes and u_B on the boundary (q_d: the neighbour of p in
+ * direction d, in the order of pinv_build_inverse_beta).
+ *   grad_beta  device [4][n_y][n_x], overwritten; zero at boundary nodes.
+ * PINV_E_UNSUPPORTED for other ops.  Deterministic; for nrhs > 16 a
+ * stream-ordered scratch of 4 ceil(nrhs/16) doubles per node is taken from the
+ * device's memory pool for the duration of the call.  Asynchronous. */
+int32_t pinv_grad_beta(pinv_op op, const double* u, int64_t ld_u,
+                       const double* lambda, int64_t ld_lambda, int32_t nrhs,
+                       double* grad_beta, void* stream);
+
 /* Many solves against many ops in one call (batched uneven requests).
  * In PINV_INT8 mode the requests naming the same op are grouped and each group
  * runs as one product over all of its right-hand sides: one rho quantisation

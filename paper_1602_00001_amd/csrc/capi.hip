@@ -797,6 +797,29 @@ int32_t pinv_grad_eps_general(pinv_op op, const double* u, int64_t ld_u, const d
   return pinv_hip_status(e2);
 }
 
+int32_t pinv_grad_beta(pinv_op op, const double* u, int64_t ld_u, const double* lambda, int64_t ld_lambda,
+                       int32_t nrhs, double* grad_beta, void* stream) {
+  if (!op || !grad_beta || nrhs < 0) return PINV_E_INVALID_ARG;
+  if (nrhs > 0 && (!u || !lambda || ld_u < op->n || ld_lambda < op->n)) return PINV_E_INVALID_ARG;
+  if (!op->beta) return PINV_E_UNSUPPORTED;
+  hipStream_t s = as_stream(stream);
+  const int chunks = grad_eps_chunks(nrhs);
+  const size_t nodes = (size_t)op->nx * op->ny;
+  void* part = nullptr;
+  if (chunks > 1) {
+    configure_pool_once();
+    PINV_HIP_TRY(hipMallocAsync(&part, 4 * (size_t)chunks * nodes * sizeof(double), s));
+  }
+  hipError_t e;
+  {
+    TraceScope ts("grad_eps", s);
+    e = launch_grad_beta(op->nx, op->ny, u, ld_u, lambda, ld_lambda, nrhs, op->ub, (double*)part, grad_beta, s);
+  }
+  const hipError_t e2 = part ? hipFreeAsync(part, s) : hipSuccess;
+  if (e != hipSuccess) return pinv_hip_status(e);
+  return pinv_hip_status(e2);
+}
+
 int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode, int32_t rho_bits, void* stream) {
   if (nreq < 0 || (nreq > 0 && !reqs)) return PINV_E_INVALID_ARG;
   // every request is checked before anything is launched

@@ -233,6 +233,9 @@ hipError_t launch_gemv_sym(const double* Gp, int n, const double* X, int64_t ldx
 // nz = 0 for the 2-D operator.  part: scratch of grad_eps_chunks(nrhs) * (nodes)
 // doubles (unused when that is <= 1)
 int grad_eps_chunks(int nrhs);
+// Eq. 3: dLoss/dbeta [4][ny][nx]; part: 4 * chunks * nodes doubles
+hipError_t launch_grad_beta(int nx, int ny, const double* u, int64_t ldu, const double* lam, int64_t ldl, int nrhs,
+                            const double* ub, double* part, double* grad, hipStream_t s);
 // non-uniform grid (x, y: device node coordinates): per-direction gradients
 // gx, gy [ny][nx], or their sum in gx when gy is null; part: 2 * chunks * nodes
 hipError_t launch_grad_eps_general(int nx, int ny, const double* x, const double* y, const double* u, int64_t ldu,

@@ -280,6 +280,69 @@ __global__ __launch_bounds__(256) void grad_eps_general_reduce_kernel(int nodes,
   }
 }
 
+// Eq. 3's coefficients: dLoss/dbeta_d(p) = (1/4) sum_r lambda_p U_{q_d}
+// (lambda = A^{-T} g is the adjoint output; U is u at interior nodes and u_B on
+// the boundary).  One thread per node and a chunk of RC right-hand sides per
+// workgroup as above; part[chunk][d][node], or the scaled result directly.
+__global__ __launch_bounds__(256) void grad_beta_partial_kernel(int nx, int ny, const double* __restrict__ u,
+                                                               int64_t ldu, const double* __restrict__ lam,
+                                                               int64_t ldl, int nrhs, const double* __restrict__ ub,
+                                                               double* __restrict__ out, int final_scale) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nodes = nx * ny;
+  if (node >= nodes) return;
+  const int r0 = blockIdx.y * RC;
+  const int r1 = min(nrhs, r0 + RC);
+  const int i = node / nx, j = node % nx;
+  const int mx = nx - 2;
+  auto boundary = [&](int a, int b) { return a == 0 || a == ny - 1 || b == 0 || b == nx - 1; };
+  const bool bp = boundary(i, j);
+  const int ni[4] = {i - 1, i + 1, i, i};
+  const int nj[4] = {j, j, j - 1, j + 1};
+  bool bq[4];
+  int64_t qq[4];
+  double ubq[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = ni[t], l = nj[t];
+    bq[t] = bp || boundary(k, l);  // (unused when p is a boundary node)
+    qq[t] = bq[t] ? 0 : (int64_t)(k - 1) * mx + (l - 1);
+    ubq[t] = (!bp && bq[t] && ub) ? ub[(int64_t)k * nx + l] : 0.0;
+  }
+  const int64_t pp = bp ? 0 : (int64_t)(i - 1) * mx + (j - 1);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!bp) {
+    for (int r = r0; r < r1; ++r) {
+      const double* ur = u + (int64_t)r * ldu;
+      const double lp = lam[(int64_t)r * ldl + pp];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double uq = bq[t] ? ubq[t] : ur[qq[t]];
+        acc[t] += lp * uq;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (final_scale)
+      out[(int64_t)t * nodes + node] = 0.25 * acc[t];
+    else
+      out[((int64_t)blockIdx.y * 4 + t) * nodes + node] = acc[t];
+  }
+}
+
+__global__ __launch_bounds__(256) void grad_beta_reduce_kernel(int nodes, int chunks, const double* __restrict__ part,
+                                                              double* __restrict__ grad) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nodes) return;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += part[((int64_t)c * 4 + t) * nodes + node];
+    grad[(int64_t)t * nodes + node] = 0.25 * s;
+  }
+}
+
 }  // namespace
 
 int grad_eps_chunks(int nrhs) { return (nrhs + RC - 1) / RC; }
@@ -322,5 +385,23 @@ hipError_t launch_grad_eps_general(int nx, int ny, const double* x, const double
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(grad_eps_general_reduce_kernel, blocks, dim3(256), 0, s, nodes, chunks, part, gx, gy);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_beta(int nx, int ny, const double* u, int64_t ldu, const double* lam, int64_t ldl, int nrhs,
+                            const double* ub, double* part, double* grad, hipStream_t s) {
+  const int nodes = nx * ny;
+  const int chunks = grad_eps_chunks(nrhs);
+  const dim3 blocks((nodes + 255) / 256);
+  if (chunks <= 1) {
+    hipLaunchKernelGGL(grad_beta_partial_kernel, dim3(blocks.x, 1), dim3(256), 0, s, nx, ny, u, ldu, lam, ldl, nrhs,
+                       ub, grad, 1);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(grad_beta_partial_kernel, dim3(blocks.x, chunks), dim3(256), 0, s, nx, ny, u, ldu, lam, ldl,
+                     nrhs, ub, part, 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(grad_beta_reduce_kernel, blocks, dim3(256), 0, s, nodes, chunks, part, grad);
   return hipGetLastError();
 }

@@ -75,6 +75,7 @@ def _load():
         "pinv_apply_inverse_adjoint": ([vp, i32, i32, dp, i64, i32, dp, i64, vp], i32),
         "pinv_grad_eps": ([vp, dp, i64, dp, i64, i32, dp, vp], i32),
         "pinv_grad_eps_general": ([vp, dp, i64, dp, i64, i32, dp, dp, vp], i32),
+        "pinv_grad_beta": ([vp, dp, i64, dp, i64, i32, dp, vp], i32),
         "pinv_apply_batched": ([P(Request), i32, i32, i32, vp], i32),
         "pinv_get_info": ([vp, P(Info)], i32),
         "pinv_destroy": ([vp], i32),
@@ -95,7 +96,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_build_inverse_general", "pinv_build_inverse_beta", "pinv_grad_eps_general", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
+EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_build_inverse_general", "pinv_build_inverse_beta", "pinv_grad_eps_general", "pinv_grad_beta", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
             "pinv_prepare_split", "pinv_export_quantized", "pinv_apply_inverse", "pinv_apply_inverse_adjoint",
             "pinv_grad_eps", "pinv_apply_batched", "pinv_get_info", "pinv_destroy", "pinv_status_string",
             "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_int8_variants",
@@ -344,6 +345,19 @@ class PoissonInverse:
                                          ctypes.c_void_p(gy.data_ptr()) if split else None, _stream(stream)),
                "pinv_grad_eps_general")
         return (gx, gy) if split else gx
+
+    def grad_beta(self, u, lam, stream=None):
+        """dLoss/dbeta [4, n_y, n_x] for an op from :meth:`build_beta`, from forward
+        solutions u and adjoint outputs lam (= A^{-T} g)."""
+        import torch
+        p_u, ld_u, nu = _vectors(u, self.n, "u")
+        p_l, ld_l, nl = _vectors(lam, self.n, "lambda")
+        if nu != nl:
+            raise ValueError("u and lambda must have the same number of rows")
+        out = torch.empty((4, self.ny, self.nx), dtype=torch.float64, device=u.device)
+        _check(lib.pinv_grad_beta(self._h, p_u, ld_u, p_l, ld_l, nu, ctypes.c_void_p(out.data_ptr()),
+                                  _stream(stream)), "pinv_grad_beta")
+        return out
 
     def set_int8_variant(self, rho_bits, variant):
         _check(lib.pinv_set_int8_variant(self._h, int(rho_bits), int(variant)), "pinv_set_int8_variant")

@@ -111,3 +111,44 @@ def test_gpu_lu_build_reports_a_zero_pivot(torch):
     with pytest.raises(pinv.PinvError) as ei:
         pinv.PoissonInverse.build_beta(nx, ny, beta)
     assert ei.value.status == pinv.E_NOT_SPD
+
+
+@pytest.mark.parametrize("nx,ny,R,with_ub", [(12, 9, 37, True), (40, 31, 5, False), (9, 8, 0, True)])
+def test_grad_beta_matches_oracle(torch, nx, ny, R, with_ub):
+    """dLoss/dbeta on a GPU-built Eq. 3 op against the oracle's formula on the
+    same (u, lambda): 1 and 3 chunks of right-hand sides, R = 0; and the whole
+    chain (GPU forward, adjoint, gradient) against central differences."""
+    from paper_1602_00001_amd import pinv
+    announce(f"grad_beta nx={nx} ny={ny} R={R} ub={with_ub}")
+    g = np.random.default_rng(nx * ny + R)
+    beta = g.uniform(0.2, 1.0, (4, ny, nx))
+    ub = g.standard_normal((ny, nx)) if with_ub else None
+    N = (nx - 2) * (ny - 2)
+    u = g.standard_normal((R, N))
+    lam = g.standard_normal((R, N))
+    ref = grad.grad_beta(nx, ny, u.T, lam.T, ub)
+    with pinv.PoissonInverse.build_beta(nx, ny, beta, ub) as op:
+        got = host(op.grad_beta(dev(u), dev(lam)))
+        assert got.shape == (4, ny, nx)
+        if R == 0:
+            assert np.all(got == 0.0)
+            return
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+        # the chain through the GPU forward and adjoint, against re-solved losses
+        rho = g.standard_normal((3, N))
+        sample = np.sort(g.choice(N, 11, replace=False))
+        d = 0.01 * g.standard_normal((11, 3))
+        uf = op.apply(dev(rho), "fp64")
+        gu = grad.sampling_loss_grad_u(host(uf).T, sample, d)
+        lf = op.apply_adjoint(dev(gu.T), "fp64")
+        gb = host(op.grad_beta(uf, lf))
+
+    def loss(b):
+        A, bB = grid.beta_operator(nx, ny, b, ub)
+        uu = np.linalg.solve(A, rho.T + bB[:, None])
+        res = uu[sample] - d
+        return float(np.sum(res * res))
+
+    v = g.standard_normal((4, ny, nx))
+    fd = grad.central_difference(loss, beta, v, 1e-6)
+    assert abs(fd - float(np.sum(gb * v))) <= 1e-6 * abs(fd)
