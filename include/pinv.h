@@ -168,18 +168,18 @@ int32_t pinv_build_inverse_general(const pinv_grid_general* g, const double* eps
  * d over the neighbours (i-1, j), (i+1, j), (i, j-1), (i, j+1) in that order;
  * a boundary neighbour's Dirichlet value moves to the right-hand side
  * (b_B[p] += beta[d][i][j] / 4 * u_B(q_d)), so u = A^{-1} (rho + b_B).  The
- * inverse is formed on the GPU by a blocked LU factorization without row
- * exchanges (it exists and is stable when A is an M-matrix, e.g. beta >= 0 with
- * sum_d beta_d <= 4 in every row, as for beta_d = 4 eps_f / sum of the node's
- * face eps_f), then A^{-1} = U^{-1} L^{-1}.  The op stores G = -A^{-1} with h = 1,
+ * inverse is formed on the GPU by a blocked LU factorization with partial
+ * pivoting, P A = L U (row exchanges chosen column by column: the first row of
+ * largest magnitude), then A^{-1} = U^{-1} L^{-1} P.  The op stores G = -A^{-1} with h = 1,
  * so pinv_apply_inverse gives u = -G rho + w = A^{-1} rho + w with the lift
  * w = A^{-1} b_B; the adjoint applies the transpose.
  *   g           grid (host); g->h is not used (the op's h is 1).
  *   beta        host [4][n_y][n_x], finite; only interior nodes are read.
  *   u_boundary  host [n_y][n_x]; only boundary entries are read.  NULL = 0.
- * PINV_E_NOT_SPD if the factorization meets a zero or non-finite pivot;
- * pinv_grad_eps returns PINV_E_UNSUPPORTED for the op.  Synchronous; device
- * memory about 2 N^2 doubles at peak, N^2 afterwards. */
+ * PINV_E_NOT_SPD if A is singular (a column with no non-zero finite pivot
+ * candidate); pinv_grad_eps returns PINV_E_UNSUPPORTED for the op (the
+ * coefficient gradient is pinv_grad_beta).  Synchronous; device memory about
+ * 2 N^2 doubles at peak, N^2 afterwards. */
 int32_t pinv_build_inverse_beta(const pinv_grid* g, const double* beta,
                                 const double* u_boundary, void* stream, pinv_op* out);
 

@@ -17,11 +17,14 @@
 // that the host reads once at the end.
 //
 // Eq. 3 with arbitrary neighbour coefficients gives a unit-diagonal matrix
-// that is not symmetric: it is factored A = L U (L unit lower) by the same
-// right-looking blocking without row exchanges (the diagonal block's L, U and
-// both triangular inverses in LDS, panels and trailing update as GEMMs), then
-// X = L^{-1} by the forward substitution above and A^{-1} = U^{-1} X by block
-// back substitution, bottom block row first.
+// that is not symmetric and, for mixed-sign coefficients, not diagonally
+// dominant: it is factored P A = L U (L unit lower) with partial pivoting by
+// the same right-looking blocking (each 64-column panel column by column:
+// pivot search and row exchange, multipliers and the panel update; then the
+// diagonal block's triangular inverses in LDS, the U panel and the trailing
+// update as GEMMs), then X = L^{-1} by the forward substitution above,
+// (P A)^{-1} = U^{-1} X by block back substitution, bottom block row first,
+// and A^{-1} = (P A)^{-1} P by a column permutation.
 
 #include "common.h"
 
@@ -226,44 +229,18 @@ __global__ void assemble_beta_kernel(int nx, int ny, const double* __restrict__ 
   bB[p] = b;
 }
 
-// Factor the kn x kn diagonal block at (k0, k0) as L U without row exchanges
-// (L unit lower, stored below the diagonal; U on and above it), and write
-// L^{-1} (unit lower) to Wl and U^{-1} (upper) to Wu, 64 x 64, zero padded.
-// A zero or non-finite pivot sets *flag (and is replaced by 1 so the
-// remaining arithmetic stays finite).
-__global__ __launch_bounds__(256) void lu_diag_block_kernel(double* __restrict__ A, int64_t lda, int k0, int kn,
-                                                            double* __restrict__ Wl, double* __restrict__ Wu,
-                                                            int* __restrict__ flag) {
+// The kn x kn diagonal block at (k0, k0) holds its L (unit lower, below the
+// diagonal) and U (on and above it); write L^{-1} (unit lower) to Wl and U^{-1}
+// (upper) to Wu, 64 x 64, zero padded.
+__global__ __launch_bounds__(256) void lu_diag_inverse_kernel(const double* __restrict__ A, int64_t lda, int k0,
+                                                              int kn, double* __restrict__ Wl,
+                                                              double* __restrict__ Wu) {
   __shared__ double F[NB][NB + 1];
   __shared__ double tmp[NB];
   const int tid = threadIdx.x;
   for (int idx = tid; idx < NB * NB; idx += 256) {
     const int i = idx / NB, j = idx % NB;
     F[i][j] = (i < kn && j < kn) ? A[(int64_t)(k0 + i) * lda + k0 + j] : 0.0;
-  }
-  __syncthreads();
-  for (int j = 0; j < kn; ++j) {
-    if (tid == 0) {
-      const double d = F[j][j];
-      if (!(fabs(d) > 0.0 && fabs(d) < INFINITY)) {
-        *flag = 1;
-        F[j][j] = 1.0;
-      }
-    }
-    __syncthreads();
-    const double piv = F[j][j];
-    for (int i = j + 1 + tid; i < kn; i += 256) F[i][j] = F[i][j] / piv;
-    __syncthreads();
-    const int rem = kn - j - 1;
-    for (int idx = tid; idx < rem * rem; idx += 256) {
-      const int i = j + 1 + idx / rem, c = j + 1 + idx % rem;
-      F[i][c] -= F[i][j] * F[j][c];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < kn * kn; idx += 256) {
-    const int i = idx / kn, j = idx % kn;
-    A[(int64_t)(k0 + i) * lda + k0 + j] = F[i][j];
   }
   __syncthreads();
   // L^{-1} in place below the diagonal, last column first:
@@ -300,6 +277,100 @@ __global__ __launch_bounds__(256) void lu_diag_block_kernel(double* __restrict__
     Wl[idx] = in ? (i == j ? 1.0 : (j < i ? F[i][j] : 0.0)) : 0.0;
     Wu[idx] = (in && j >= i) ? F[i][j] : 0.0;
   }
+}
+
+// Partial pivoting at column c (LU with row exchanges, the standard way of
+// inverting a general matrix): the pivot row p is the first row r >= c of
+// largest |A[r][c]|; rows c and p are exchanged over all n columns (the L
+// columns already formed to their left included, so the factors end up those
+// of P A) and perm[c], perm[p] with them.  No finite non-zero candidate (a
+// singular matrix) sets *flag and puts 1 on the diagonal so the remaining
+// arithmetic stays finite.  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void lu_pivot_kernel(double* __restrict__ A, int64_t lda, int n, int c,
+                                                        int* __restrict__ perm, int* __restrict__ flag) {
+  __shared__ double sv[16];
+  __shared__ int si[16];
+  __shared__ int sp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double best = -1.0;
+  int bi = n;
+  for (int r = c + tid; r < n; r += 1024) {
+    const double v = fabs(A[(int64_t)r * lda + c]);
+    if (v > best) {  // rows ascend per thread: the first of equal values is kept
+      best = v;
+      bi = r;
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double ov = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > best || (ov == best && oi < bi)) {
+      best = ov;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    sv[wave] = best;
+    si[wave] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 16; ++w)
+      if (sv[w] > best || (sv[w] == best && si[w] < bi)) {
+        best = sv[w];
+        bi = si[w];
+      }
+    if (!(best > 0.0 && best < INFINITY) || bi >= n) {
+      *flag = 1;
+      A[(int64_t)c * lda + c] = 1.0;
+      bi = c;
+    }
+    sp = bi;
+    if (bi != c) {
+      const int t = perm[c];
+      perm[c] = perm[bi];
+      perm[bi] = t;
+    }
+  }
+  __syncthreads();
+  const int p = sp;
+  if (p == c) return;
+  double* rc = A + (int64_t)c * lda;
+  double* rp = A + (int64_t)p * lda;
+  for (int j = tid; j < n; j += 1024) {
+    const double t = rc[j];
+    rc[j] = rp[j];
+    rp[j] = t;
+  }
+}
+
+// Column c of the panel whose columns end at cend: every row r > c gets its
+// multiplier l = A[r][c] / A[c][c] (stored in place) and the rank-one update
+// A[r][j] -= l A[c][j] of the panel's columns right of c.  One thread per row.
+__global__ __launch_bounds__(256) void lu_panel_column_kernel(double* __restrict__ A, int64_t lda, int n, int c,
+                                                              int cend) {
+  const int r = c + 1 + blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  double* row = A + (int64_t)r * lda;
+  const double* prow = A + (int64_t)c * lda;
+  const double l = row[c] / prow[c];
+  row[c] = l;
+  for (int j = c + 1; j < cend; ++j) row[j] -= l * prow[j];
+}
+
+__global__ void iota_kernel(int* __restrict__ perm, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) perm[i] = i;
+}
+
+// G[:, perm[i]] = -Y[:, i]: with P A = L U and Y = U^{-1} L^{-1} = (P A)^{-1},
+// A^{-1} = Y P and G = -A^{-1}.
+__global__ void permute_negate_kernel(const double* __restrict__ Y, int64_t ld, int n, const int* __restrict__ perm,
+                                      double* __restrict__ G) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int r = (int)(idx / n), i = (int)(idx % n);
+  G[(int64_t)r * ld + perm[i]] = -Y[(int64_t)r * ld + i];
 }
 
 // G = -G (n x n, row stride ld)
@@ -461,14 +532,19 @@ done:
 
 // Eq. 3: fills op->G with -A^{-1} (so that u = -G rho + w = A^{-1}(rho + b_B)
 // with h = 1) and op->w = A^{-1} b_B when ub_dev is given.  beta_dev: device
-// [4][n_y][n_x].  PINV_E_NOT_SPD if the factorization without row exchanges
-// meets a zero or non-finite pivot.
+// [4][n_y][n_x].  P A = L U by a blocked right-looking factorization with
+// partial pivoting: per 64-column panel, a pivot search and row exchange
+// (lu_pivot_kernel) and a column update (lu_panel_column_kernel) per column,
+// then the diagonal block's triangular inverses, the U panel L11^{-1} A12 and
+// the trailing update as FP64 GEMMs.  PINV_E_NOT_SPD if A is singular (a
+// column with no non-zero finite pivot).
 int32_t build_inverse_lu_device(pinv_op op, const double* beta_dev, const double* ub_dev, hipStream_t s) {
   const int n = op->n;
   const int64_t ld = op->ldg;
   const int nblk = (n + NB - 1) / NB;
   double *Kb = nullptr, *Wb = nullptr, *Wl = nullptr, *Wu = nullptr, *bB = nullptr;
   int* flag = nullptr;
+  int* perm = nullptr;
   int32_t st = PINV_OK;
   hipError_t e;
   const size_t mat_bytes = (size_t)n * (size_t)ld * sizeof(double);
@@ -488,29 +564,37 @@ int32_t build_inverse_lu_device(pinv_op op, const double* beta_dev, const double
   PINV_BAIL(hipMalloc(&Wu, (size_t)nblk * NB * NB * sizeof(double)));
   PINV_BAIL(hipMalloc(&bB, (size_t)n * sizeof(double)));
   PINV_BAIL(hipMalloc(&flag, sizeof(int)));
+  PINV_BAIL(hipMalloc(&perm, (size_t)n * sizeof(int)));
   PINV_BAIL(hipMemsetAsync(flag, 0, sizeof(int), s));
   PINV_BAIL(hipMemsetAsync(Kb, 0, mat_bytes, s));
   PINV_BAIL(hipMemsetAsync(Wb, 0, mat_bytes, s));
+  hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, s, perm, n);
+  PINV_BAIL(hipGetLastError());
   hipLaunchKernelGGL(assemble_beta_kernel, dim3((n + 255) / 256), dim3(256), 0, s, op->nx, op->ny, beta_dev, ub_dev, Kb,
                      ld, bB);
   PINV_BAIL(hipGetLastError());
 
-  // A = L U in place: L below the diagonal (unit diagonal implied), U on and above
+  // P A = L U in place: L below the diagonal (unit diagonal implied), U on and above
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * NB, kn = (n - k0 < NB) ? n - k0 : NB;
     double* wl = Wl + (size_t)kb * NB * NB;
     double* wu = Wu + (size_t)kb * NB * NB;
-    hipLaunchKernelGGL(lu_diag_block_kernel, dim3(1), dim3(256), 0, s, Kb, ld, k0, kn, wl, wu, flag);
+    // the panel's columns, one at a time: pivot and exchange, then multipliers
+    // and the update of the panel's columns to the right (L21 is complete
+    // after the last column)
+    for (int c = k0; c < k0 + kn; ++c) {
+      hipLaunchKernelGGL(lu_pivot_kernel, dim3(1), dim3(1024), 0, s, Kb, ld, n, c, perm, flag);
+      PINV_BAIL(hipGetLastError());
+      if (c + 1 < n) {
+        hipLaunchKernelGGL(lu_panel_column_kernel, dim3((n - c - 1 + 255) / 256), dim3(256), 0, s, Kb, ld, n, c,
+                           k0 + kn);
+        PINV_BAIL(hipGetLastError());
+      }
+    }
+    hipLaunchKernelGGL(lu_diag_inverse_kernel, dim3(1), dim3(256), 0, s, Kb, ld, k0, kn, wl, wu);
     PINV_BAIL(hipGetLastError());
     const int r0 = k0 + kn, rn = n - r0;
     if (rn <= 0) continue;
-    // L panel: A[r0:, k] <- A[r0:, k] U_kk^{-1} (in place: one 128-wide column tile holds all kn <= 64 columns)
-    GemmF64Args p{};
-    p.A = Kb + (int64_t)r0 * ld + k0; p.lda = ld; p.a_kcontig = 1;
-    p.B = wu; p.ldb = NB; p.b_kcontig = 0;
-    p.C = Kb + (int64_t)r0 * ld + k0; p.csm = ld; p.csn = 1;
-    p.M = rn; p.N = kn; p.K = kn; p.alpha = 1.0; p.beta = 0.0;
-    PINV_BAIL(launch_gemm_f64(p, s));
     // U panel: A[k, r0:] <- L_kk^{-1} A[k, r0:] (in place: one 128-row tile holds all kn <= 64 rows)
     GemmF64Args q{};
     q.A = wl; q.lda = NB; q.a_kcontig = 1;
@@ -568,13 +652,15 @@ int32_t build_inverse_lu_device(pinv_op op, const double* beta_dev, const double
     PINV_BAIL(launch_gemm_f64(b, s));
   }
 
+  // G = -(P A)^{-1} P, into Kb (its factors are no longer read); w = -G b_B
+  hipLaunchKernelGGL(permute_negate_kernel, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, s, Wb, ld,
+                     n, perm, Kb);
+  PINV_BAIL(hipGetLastError());
   if (ub_dev) {
     PINV_BAIL(hipMalloc(&op->w, (size_t)n * sizeof(double)));
     op->bytes += (int64_t)n * sizeof(double);
-    PINV_BAIL(launch_gemv_f64(Wb, ld, n, bB, n, 1, 1.0, nullptr, op->w, n, s));
+    PINV_BAIL(launch_gemv_f64(Kb, ld, n, bB, n, 1, -1.0, nullptr, op->w, n, s));
   }
-  hipLaunchKernelGGL(negate_kernel, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, s, Wb, ld, n);
-  PINV_BAIL(hipGetLastError());
   {
     int hflag = 0;
     PINV_BAIL(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -584,9 +670,9 @@ int32_t build_inverse_lu_device(pinv_op op, const double* beta_dev, const double
       goto done;
     }
   }
-  op->G = Wb;
+  op->G = Kb;
   op->bytes += (int64_t)mat_bytes;
-  Wb = nullptr;
+  Kb = nullptr;
 
 done:
 #undef PINV_BAIL
@@ -597,5 +683,6 @@ done:
   if (Wu) (void)hipFree(Wu);
   if (bB) (void)hipFree(bB);
   if (flag) (void)hipFree(flag);
+  if (perm) (void)hipFree(perm);
   return st;
 }

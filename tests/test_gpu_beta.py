@@ -65,7 +65,7 @@ def _paper_beta(nx, ny, g):
 
 @pytest.mark.parametrize("nx,ny,kind", [(12, 9, "paper"), (40, 31, "paper"), (37, 22, "dominant")])
 def test_gpu_lu_build_matches_oracle(torch, nx, ny, kind):
-    """The GPU LU build of Eq. 3's matrix (no row exchanges) against the oracle's
+    """The GPU LU build of Eq. 3's matrix (partial pivoting) against the oracle's
     pivoted LU inverse: the paper's row-normalised coefficients, and a strictly
     diagonally dominant non-symmetric set with mixed signs; N = 70, 1102, 700
     (ragged last 64-block); FP64 apply and adjoint on the built op."""
@@ -97,11 +97,61 @@ def test_gpu_lu_build_matches_oracle(torch, nx, ny, kind):
         assert ei.value.status == pinv.E_UNSUPPORTED
 
 
+def test_gpu_lu_build_needs_row_exchanges(torch):
+    """A = [[1, -1, 0], [-1, 1, -1], [0, -1, 1]] (3 interior nodes in a row, all
+    four inner coefficients 4): elimination in natural order meets a zero second
+    pivot, but A is regular (det = -1) with the integer inverse -M,
+    M = [[0, 1, 1], [1, 1, 1], [1, 1, 0]]; with row exchanges every operation is
+    on small integers, so G = -A^{-1} = M exactly."""
+    from paper_1602_00001_amd import pinv
+    announce("Eq. 3 GPU LU build with a row exchange (3 unknowns)")
+    nx, ny = 5, 3
+    beta = np.zeros((4, ny, nx))
+    beta[3, 1, 1] = 4.0     # (1,1) -> (1,2)
+    beta[2, 1, 2] = 4.0     # (1,2) -> (1,1)
+    beta[3, 1, 2] = 4.0     # (1,2) -> (1,3)
+    beta[2, 1, 3] = 4.0     # (1,3) -> (1,2)
+    A, _ = grid.beta_operator(nx, ny, beta)
+    assert np.array_equal(A, np.array([[1.0, -1.0, 0.0], [-1.0, 1.0, -1.0], [0.0, -1.0, 1.0]]))
+    M = np.array([[0.0, 1.0, 1.0], [1.0, 1.0, 1.0], [1.0, 1.0, 0.0]])
+    with pinv.PoissonInverse.build_beta(nx, ny, beta) as op:
+        Gg, _ = op.export_inverse()
+    assert np.array_equal(Gg, M)
+
+
+@pytest.mark.parametrize("nx,ny,lo,hi", [(40, 31, -3.0, 3.0), (37, 22, -4.0, 4.0), (12, 9, -4.0, 4.0)])
+def test_gpu_lu_build_mixed_sign_coefficients(torch, nx, ny, lo, hi):
+    """Coefficients uniform in (lo, hi), neither dominant nor of one sign: the
+    factorization needs row exchanges (without them the pivots fall to 1e-3 and
+    the entries grow by up to ~900).  The GPU inverse against the oracle's
+    pivoted LU inverse within 64 cond(A) eps (both are backward stable), and its
+    residual |A X - I| within 1e-12 |A| |X| (max norms); the lift likewise."""
+    from paper_1602_00001_amd import pinv
+    announce(f"Eq. 3 GPU LU build, mixed-sign beta in ({lo}, {hi}) nx={nx} ny={ny}")
+    g = np.random.default_rng(nx * ny + 7)
+    beta = g.uniform(lo, hi, (4, ny, nx))
+    ub = g.standard_normal((ny, nx))
+    A, bB = grid.beta_operator(nx, ny, beta, ub)
+    Ainv = inverse.lu_inverse(A)
+    cond = np.linalg.norm(A, 2) * np.linalg.norm(Ainv, 2)
+    tol = 64.0 * cond * np.finfo(np.float64).eps
+    w = apply.lift(Ainv, bB)
+    with pinv.PoissonInverse.build_beta(nx, ny, beta, ub) as op:
+        Gg, wg = op.export_inverse()
+    X = -Gg
+    assert np.max(np.abs(X - Ainv)) <= tol * np.max(np.abs(Ainv))
+    assert np.max(np.abs(wg - w)) <= tol * np.max(np.abs(w))
+    res = A @ X - np.eye(A.shape[0])
+    assert np.max(np.abs(res)) <= 1e-12 * np.max(np.abs(A)) * np.max(np.abs(X)) * A.shape[0] ** 0.5
+
+
 def test_gpu_lu_build_reports_a_zero_pivot(torch):
     """A = [[1, -1, 0], [-1, 1, 0], [0, 0, 1]] (3 interior nodes in a row, two
-    coefficients of 4): the second pivot is 0, reported as PINV_E_NOT_SPD."""
+    coefficients of 4) is singular: after the first column (rows 0 and 1 tie,
+    row 0 is kept) the second column has no non-zero candidate, reported as
+    PINV_E_NOT_SPD."""
     from paper_1602_00001_amd import pinv
-    announce("Eq. 3 GPU LU build with a zero pivot -> E_NOT_SPD")
+    announce("Eq. 3 GPU LU build of a singular matrix -> E_NOT_SPD")
     nx, ny = 5, 3
     beta = np.zeros((4, ny, nx))
     beta[3, 1, 1] = 4.0     # (1,1) -> (1,2)
@@ -152,3 +202,70 @@ def test_grad_beta_matches_oracle(torch, nx, ny, R, with_ub):
     v = g.standard_normal((4, ny, nx))
     fd = grad.central_difference(loss, beta, v, 1e-6)
     assert abs(fd - float(np.sum(gb * v))) <= 1e-6 * abs(fd)
+
+
+def _stencil(nx, ny, beta, X):
+    """Eq. 3's matrix applied to the columns of X [N, R] without forming it:
+    (A x)_p = x_p - sum_d beta_d(p) / 4 x_{q_d}, interior neighbours only."""
+    my, mx = ny - 2, nx - 2
+    R = X.shape[1]
+    U = np.zeros((ny, nx, R))
+    U[1:-1, 1:-1] = X.reshape(my, mx, R)
+    out = X.reshape(my, mx, R).copy()
+    for d, (di, dj) in enumerate(grid.BETA_DIRECTIONS):
+        out -= 0.25 * beta[d, 1:-1, 1:-1, None] * U[1 + di:ny - 1 + di, 1 + dj:nx - 1 + dj]
+    return out.reshape(my * mx, R)
+
+
+def _boundary_rhs(nx, ny, beta, ub):
+    """b_B[p] = sum_d beta_d(p) / 4 u_B(q_d) over the boundary neighbours."""
+    B = np.array(ub, dtype=np.float64)
+    B[1:-1, 1:-1] = 0.0
+    out = np.zeros((ny - 2, nx - 2))
+    for d, (di, dj) in enumerate(grid.BETA_DIRECTIONS):
+        out += 0.25 * beta[d, 1:-1, 1:-1] * B[1 + di:ny - 1 + di, 1 + dj:nx - 1 + dj]
+    return out.reshape(-1)
+
+
+def test_stencil_helpers_match_the_oracle_operator():
+    """The full-size test's matrix-free stencil and boundary term equal the
+    oracle's dense Eq. 3 matrix and b_B on a small grid."""
+    g = np.random.default_rng(5)
+    nx, ny = 9, 7
+    beta = g.uniform(-2.0, 2.0, (4, ny, nx))
+    ub = g.standard_normal((ny, nx))
+    A, bB = grid.beta_operator(nx, ny, beta, ub)
+    assert np.array_equal(_stencil(nx, ny, beta, np.eye(A.shape[0])), A)
+    assert np.allclose(_boundary_rhs(nx, ny, beta, ub), bB, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("kind", ["paper", "mixed"])
+def test_gpu_lu_build_full_size(torch, kind):
+    """128 x 128 grid (N = 15876): the paper's row-normalised coefficients, and
+    mixed-sign ones in (-3, 3) that need row exchanges.  No dense reference at
+    this size: 18 columns of A^{-1} (first, last, 16 random) from the FP64
+    apply of unit vectors satisfy A x = e_j to 1e-12 |A| |X| sqrt(N) (max
+    norms), and the lift satisfies A w = b_B likewise."""
+    import time
+    from paper_1602_00001_amd import pinv
+    nx = ny = 128
+    announce(f"Eq. 3 GPU LU build at 128x128 ({kind})")
+    g = np.random.default_rng(128)
+    beta = _paper_beta(nx, ny, g) if kind == "paper" else g.uniform(-3.0, 3.0, (4, ny, nx))
+    ub = g.standard_normal((ny, nx))
+    N = (nx - 2) * (ny - 2)
+    cols = np.concatenate([[0, N - 1], g.choice(np.arange(1, N - 1), 16, replace=False)])
+    E = np.zeros((cols.size, N))
+    E[np.arange(cols.size), cols] = 1.0
+    t0 = time.perf_counter()
+    with pinv.PoissonInverse.build_beta(nx, ny, beta, ub) as op:
+        t_build = time.perf_counter() - t0
+        u = host(op.apply(dev(E), "fp64"))
+        w = host(op.apply(dev(np.zeros((1, N))), "fp64"))[0]     # -G 0 + w
+    print(f"build_beta 128x128 {kind}: {t_build:.2f} s")
+    X = (u - w[None, :]).T
+    res = _stencil(nx, ny, beta, X) - E.T
+    amax = 1.0 + 0.25 * np.max(np.sum(np.abs(beta[:, 1:-1, 1:-1]), axis=0))
+    assert np.max(np.abs(res)) <= 1e-12 * amax * np.max(np.abs(X)) * N ** 0.5
+    rw = _stencil(nx, ny, beta, w[:, None])[:, 0] - _boundary_rhs(nx, ny, beta, ub)
+    assert np.max(np.abs(rw)) <= 1e-12 * amax * np.max(np.abs(w)) * N ** 0.5
