@@ -60,3 +60,26 @@ def slice_pair_products(dG, dR):
     equals the full integer product."""
     S, Sr = dG.shape[0], dR.shape[0]
     return np.stack([np.stack([dG[s] @ dR[t] for t in range(Sr)]) for s in range(S)])
+
+
+def tile_apply(q, e, S, tile, rho, h, w=None):
+    """Solve with 2-D tile scales (the rounding of Table 1 with one exponent
+    per tile x tile block of G instead of one per row):
+        u_i = -h^2 / M_S * sum_b 2^(e_ab) * sum_(k in tile b) q_ik rho_k + w_i,
+    a = the row's tile.  Each tile's product is a float64 matmul of the stored
+    integers with rho; the tile sums are scaled by their power of two (exact)
+    and added over b in increasing order.  Returns float64 [N, R]."""
+    q = np.asarray(q, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    e = np.asarray(e, dtype=np.int64)
+    N, K = q.shape
+    acc = np.zeros((N, rho.shape[1]))
+    for a in range(e.shape[0]):
+        rows = slice(a * tile, min(N, (a + 1) * tile))
+        for b in range(e.shape[1]):
+            cols = slice(b * tile, min(K, (b + 1) * tile))
+            acc[rows] += np.ldexp(q[rows, cols] @ rho[cols], int(e[a, b]))
+    u = (-(h * h) / float(max_mag(S))) * acc
+    if w is not None:
+        u = u + np.asarray(w, dtype=np.float64)[:, None]
+    return u

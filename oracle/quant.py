@@ -104,3 +104,11 @@ def quantize_tiles(G, S, tile):
             e[a, b] = ee
             q[a * tile:(a + 1) * tile, b * tile:(b + 1) * tile] = np.rint(np.ldexp(blk, -ee) * M).astype(np.int64)
     return q, e
+
+
+def dequantize_tiles(q, e, S, tile):
+    """G^ = q * 2^e_ab / M_S with e_ab the exponent of the entry's tile (float64)."""
+    q = np.asarray(q, dtype=np.float64)
+    N, K = q.shape
+    E = np.repeat(np.repeat(np.asarray(e, dtype=np.int64), tile, axis=0), tile, axis=1)[:N, :K]
+    return np.ldexp(q / float(max_mag(S)), E)
