@@ -31,6 +31,10 @@
  *   PINV_FP64_SYM  the same values from a symmetric-packed copy of G (the
  *               64 x 64 blocks on and above the diagonal): one pass over about
  *               half the bytes, for few right-hand sides.
+ *   PINV_FIX16_TILE  G rounded to 16-bit fixed point with one power-of-two
+ *               exponent per 64 x 64 tile (2-D tile scales instead of one per
+ *               row), stored as int16: 2 bytes per entry; the stored integers
+ *               times rho in FP64, for few right-hand sides.  Forward only.
  *   PINV_FP32   G and rho rounded to FP32, FP32 products, FP32 accumulation.
  *   PINV_BF16X3 G and rho split into 2 bfloat16 parts each; hi*hi + hi*lo +
  *               lo*hi with FP32 accumulation.
@@ -81,6 +85,7 @@ extern "C" {
 #define PINV_BF16X6  3
 #define PINV_INT8    4
 #define PINV_FP64_SYM 5          /* FP64 from the symmetric-packed upper triangle */
+#define PINV_FIX16_TILE 6        /* 16-bit fixed point, one exponent per 64 x 64 tile */
 
 #define PINV_SCALE_ROW 0          /* one power-of-two exponent per row of G   */
 
@@ -104,6 +109,7 @@ typedef struct {
   int32_t general;          /* built by pinv_build_inverse_general (h = 1)      */
   int32_t beta;             /* built by pinv_build_inverse_beta (h = 1)         */
   int32_t has_sym;          /* symmetric-packed FP64 copy held                  */
+  int32_t has_tile16;       /* 16-bit tile-scaled copy held                     */
 } pinv_info;
 
 /* Steps 1-2 of "The solution steps": assemble the interior operator K from the
@@ -218,8 +224,22 @@ int32_t pinv_quantize_inverse(pinv_op op, int32_t bits, int32_t scale_mode,
  * otherwise.  Applies in this mode use the upper triangle, and the adjoint
  * equals the forward product; each pass of up to 8 right-hand sides takes a
  * stream-ordered scratch of 8 N_b^2 64 doubles per right-hand side (N_b =
- * ceil(N/64)) from the device's memory pool. */
+ * ceil(N/64)) from the device's memory pool.
+ * PINV_FIX16_TILE (the rounding of Table 1 in binary with 2-D tile scales):
+ * for each 64 x 64 tile (a, b), e_ab = the frexp exponent of its largest
+ * |G_ik| (|G| < 2^e_ab; 0 for an all-zero tile) and
+ * q_ik = rint(2^-e_ab G_ik M), M = 32639 (16-bit balanced fixed point, as
+ * PINV_INT8 with 16 bits), held as int16 (N rows of 64 ceil(N/64) entries)
+ * with the exponents; the apply forms u_i = -h^2 / M sum_b 2^e_(i/64,b)
+ * sum_(k in b) q_ik rho_k + w_i in FP64 (deterministic order; within
+ * 1e-12 of the exact value of that sum).  Applies in this mode allocate
+ * nothing; the adjoint returns PINV_E_UNSUPPORTED. */
 int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream);
+
+/* Export the 16-bit tile-scaled copy: q (host [N][N] int16, row-major) and
+ * the tile exponents (host [ceil(N/64)][ceil(N/64)] int32, row-major).  Either
+ * may be NULL.  Synchronous.  PINV_E_STATE if it was not prepared. */
+int32_t pinv_export_tile16(pinv_op op, int16_t* q_host, int32_t* exponents_host, void* stream);
 
 /* Export the int8 digit slices (host [S][N][N], most significant slice
  * first, row-major) and the per-row exponents (host [N]).  Either may be NULL.

@@ -136,6 +136,8 @@ void free_op(pinv_op op) {
   if (op->G32) (void)hipFree(op->G32);
   if (op->Gb) (void)hipFree(op->Gb);
   if (op->Gsym) (void)hipFree(op->Gsym);
+  if (op->Gt16) (void)hipFree(op->Gt16);
+  if (op->Et16) (void)hipFree(op->Et16);
   if (op->xc) (void)hipFree(op->xc);
   if (op->yc) (void)hipFree(op->yc);
   delete op;
@@ -600,10 +602,28 @@ int32_t pinv_quantize_inverse(pinv_op op, int32_t bits, int32_t scale_mode, int3
 
 int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream) {
   if (!op) return PINV_E_INVALID_ARG;
-  if (mode != PINV_FP32 && mode != PINV_BF16X3 && mode != PINV_BF16X6 && mode != PINV_FP64_SYM)
+  if (mode != PINV_FP32 && mode != PINV_BF16X3 && mode != PINV_BF16X6 && mode != PINV_FP64_SYM &&
+      mode != PINV_FIX16_TILE)
     return PINV_E_INVALID_ARG;
   if (!op->G) return PINV_E_STATE;
   hipStream_t s = as_stream(stream);
+  if (mode == PINV_FIX16_TILE) {
+    if (!op->Gt16) {
+      const size_t qb = (size_t)op->n * (size_t)tile16_ld(op->n) * sizeof(int16_t);
+      const size_t eb = (size_t)tile16_tiles(op->n) * (size_t)tile16_tiles(op->n) * sizeof(int32_t);
+      PINV_HIP_TRY(hipMalloc(&op->Gt16, qb));
+      const hipError_t e = hipMalloc(&op->Et16, eb);
+      if (e != hipSuccess) {
+        (void)hipFree(op->Gt16);
+        op->Gt16 = nullptr;
+        return pinv_hip_status(e);
+      }
+      op->bytes += (int64_t)(qb + eb);
+    }
+    PINV_HIP_TRY(launch_quantize_tiles16(op->G, op->ldg, op->n, op->Gt16, op->Et16, s));
+    PINV_HIP_TRY(hipStreamSynchronize(s));
+    return PINV_OK;
+  }
   if (mode == PINV_FP64_SYM) {
     // only an exactly symmetric G may be stored as its upper triangle
     int* flag = nullptr;
@@ -648,6 +668,21 @@ int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream) {
     }
     PINV_HIP_TRY(launch_make_bf16_parts(op->G, op->ldg, op->n, op->nbf, op->Gb, s));
   }
+  PINV_HIP_TRY(hipStreamSynchronize(s));
+  return PINV_OK;
+}
+
+int32_t pinv_export_tile16(pinv_op op, int16_t* q_host, int32_t* exponents_host, void* stream) {
+  if (!op) return PINV_E_INVALID_ARG;
+  if (!op->Gt16) return PINV_E_STATE;
+  hipStream_t s = as_stream(stream);
+  const int n = op->n, tk = tile16_tiles(n);
+  if (q_host)
+    PINV_HIP_TRY(hipMemcpy2DAsync(q_host, (size_t)n * sizeof(int16_t), op->Gt16,
+                                  (size_t)tile16_ld(n) * sizeof(int16_t), (size_t)n * sizeof(int16_t), n,
+                                  hipMemcpyDeviceToHost, s));
+  if (exponents_host)
+    PINV_HIP_TRY(hipMemcpyAsync(exponents_host, op->Et16, (size_t)tk * tk * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   PINV_HIP_TRY(hipStreamSynchronize(s));
   return PINV_OK;
 }
@@ -697,6 +732,12 @@ int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits, const dou
       return fp64_apply(op, false, rho, ld_rho, nrhs, op->w, u, ld_u, s);
     case PINV_FP64_SYM:
       return sym_apply(op, rho, ld_rho, nrhs, op->w, u, ld_u, s);
+    case PINV_FIX16_TILE: {
+      if (!op->Gt16) return PINV_E_STATE;
+      TraceScope ts("gemv_tile16", s);
+      return pinv_hip_status(
+          launch_gemv_tile16(op->Gt16, op->Et16, op->n, rho, ld_rho, nrhs, op->h, op->w, u, ld_u, s));
+    }
     case PINV_INT8: {
       const int SR = slices_of_bits(rho_bits);
       if (!SR) return PINV_E_INVALID_ARG;
@@ -737,6 +778,8 @@ int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits, con
       return fp64_apply(op, true, g, ld_g, nrhs, nullptr, lambda, ld_lambda, s);
     case PINV_FP64_SYM:
       return sym_apply(op, g, ld_g, nrhs, nullptr, lambda, ld_lambda, s);
+    case PINV_FIX16_TILE:
+      return PINV_E_UNSUPPORTED;
     case PINV_INT8: {
       const int SR = slices_of_bits(g_bits);
       if (!SR) return PINV_E_INVALID_ARG;
@@ -998,6 +1041,7 @@ int32_t pinv_get_info(pinv_op op, pinv_info* info) {
   info->nz = op->nz;
   info->beta = op->beta;
   info->has_sym = op->Gsym != nullptr;
+  info->has_tile16 = op->Gt16 != nullptr;
   info->general = op->general;
   return PINV_OK;
 }

@@ -1,0 +1,178 @@
+// 16-bit fixed point with 2-D tile scales: a storage variant of the rounded
+// inverse for the pass-over-G regime (few right-hand sides, bound by HBM
+// bandwidth).  The rounding of Table 1 in binary, with one power-of-two
+// exponent per 64 x 64 tile of G instead of one per row:
+//   e_ab = frexp exponent of max |G| over tile (a, b)   (|G| < 2^e_ab),
+//   q_ik = rint(2^-e_ab G_ik M),  M = 127 (256^2 - 1) / 255 = 32639,
+// so |q| <= M fits int16 and G^_ik = 2^e_ab q_ik / M.  Entries far from the
+// diagonal are smaller than their row's maximum, so their tiles keep more
+// significant bits than a row scale would give them: at 16 bits the error of
+// G^ rho drops about fourfold, and 2 bytes per entry meet a 1e-4 relative
+// bound that per-row scaling needs 3 bytes for.
+//
+// Storage: q as int16, N rows with row stride ldq = 64 ceil(N/64) (zero past
+// column N), exponents int32 [ceil(N/64)][ceil(N/64)].
+//
+// Apply: u_i = alpha sum_b 2^e_(i/64, b) sum_(k in b) q_ik x_k + bias_i with
+// alpha = -h^2 / M, in FP64: each lane forms the sum over its 8 entries of one
+// tile (exact integers times FP64 values, fused multiply-adds in k order),
+// scales it by 2^e exactly and adds it to its running sum; the 64 lanes' sums
+// are then added in a fixed butterfly order.
+
+#include "common.h"
+
+namespace {
+
+constexpr int T16 = 64;          // tile edge
+constexpr double M16 = 32639.0;  // 127 (256^2 - 1) / 255
+
+// one workgroup per tile (a, b) = (blockIdx.y, blockIdx.x); thread t holds
+// row t / 4, columns 16 (t % 4) .. + 15 of the tile
+__global__ __launch_bounds__(256) void quantize_tiles16_kernel(const double* __restrict__ G, int64_t ldg, int n,
+                                                               int tk, int16_t* __restrict__ Q, int64_t ldq,
+                                                               int* __restrict__ E) {
+  __shared__ double wmax[4];
+  const int a = blockIdx.y, b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int i = a * T16 + (tid >> 2);
+  const int j0 = b * T16 + (tid & 3) * 16;
+  const bool row_in = i < n;
+  const double* g = G + (int64_t)(row_in ? i : 0) * ldg;
+  double v[16];
+  double m = 0.0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int j = j0 + t;
+    v[t] = (row_in && j < n) ? g[j] : 0.0;
+    m = fmax(m, fabs(v[t]));
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((tid & 63) == 0) wmax[tid >> 6] = m;
+  __syncthreads();
+  m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+  int e = 0;
+  (void)frexp(m, &e);  // m == 0 gives e = 0
+  if (tid == 0) E[a * tk + b] = e;
+  if (!row_in) return;
+  int16_t* q = Q + (int64_t)i * ldq + j0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const double s = ldexp(v[t], -e) * M16;
+    q[t] = (int16_t)rint(s);
+  }
+}
+
+// 4 rows per wave (one 16-byte load of each row per lane and step serves the
+// same 8 x values), NR right-hand sides.  Whole 512-column steps first (no
+// bounds checks: k + 8 <= n for every lane), then one bounded step.
+template <int NR>
+__global__ __launch_bounds__(256) void gemv_tile16_kernel(const int16_t* __restrict__ Q, int64_t ldq,
+                                                          const int* __restrict__ E, int tk, int n,
+                                                          const double* __restrict__ X, int64_t ldx, double alpha,
+                                                          const double* __restrict__ bias, double* __restrict__ U,
+                                                          int64_t ldu) {
+  constexpr int RW = 4;
+  const int lane = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RW;  // multiple of 4: one row tile
+  if (row0 >= n) return;
+  const int* er = E + (int64_t)(row0 / T16) * tk;
+  const int16_t* q[RW];
+#pragma unroll
+  for (int u = 0; u < RW; ++u) q[u] = Q + (int64_t)min(row0 + u, n - 1) * ldq;  // rows past n: row n-1, not stored
+  double s[RW][NR];
+#pragma unroll
+  for (int u = 0; u < RW; ++u)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s[u][r] = 0.0;
+
+  auto step = [&](int k, bool bounded) {
+    const int e = er[k / T16];
+    double xv[NR][8];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        const int kk = k + w;
+        xv[r][w] = bounded ? (kk < n ? X[(int64_t)r * ldx + min(kk, n - 1)] : 0.0) : X[(int64_t)r * ldx + kk];
+      }
+#pragma unroll
+    for (int u = 0; u < RW; ++u) {
+      const int4 raw = *(const int4*)(q[u] + k);  // 8 int16, in bounds: k + 8 <= ldq
+      const int words[4] = {raw.x, raw.y, raw.z, raw.w};
+      double qd[8];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        qd[2 * w] = (double)(int16_t)(words[w] & 0xffff);
+        qd[2 * w + 1] = (double)(int16_t)(words[w] >> 16);
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        double p = qd[0] * xv[r][0];
+#pragma unroll
+        for (int w = 1; w < 8; ++w) p = fma(qd[w], xv[r][w], p);
+        s[u][r] += ldexp(p, e);
+      }
+    }
+  };
+
+  int b = 0;
+  for (; b + 512 <= n; b += 512) step(b + lane * 8, false);
+  if (b + lane * 8 < n) step(b + lane * 8, true);
+
+#pragma unroll
+  for (int u = 0; u < RW; ++u)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double v = s[u][r];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+      s[u][r] = v;
+    }
+  // lane u * NR + r writes row row0 + u of right-hand side r
+#pragma unroll
+  for (int u = 0; u < RW; ++u)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (lane == u * NR + r && row0 + u < n) {
+        double v = alpha * s[u][r];
+        if (bias) v += bias[row0 + u];
+        U[(int64_t)r * ldu + row0 + u] = v;
+      }
+}
+
+}  // namespace
+
+int64_t tile16_ld(int n) { return (int64_t)((n + T16 - 1) / T16) * T16; }
+
+int tile16_tiles(int n) { return (n + T16 - 1) / T16; }
+
+hipError_t launch_quantize_tiles16(const double* G, int64_t ldg, int n, int16_t* Q, int* E, hipStream_t s) {
+  const int tk = tile16_tiles(n);
+  if (tk == 0) return hipSuccess;
+  hipLaunchKernelGGL(quantize_tiles16_kernel, dim3(tk, tk), dim3(256), 0, s, G, ldg, n, tk, Q, tile16_ld(n), E);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_tile16(const int16_t* Q, const int* E, int n, const double* X, int64_t ldx, int nrhs,
+                              double h, const double* bias, double* U, int64_t ldu, hipStream_t s) {
+  const int tk = tile16_tiles(n);
+  const int64_t ldq = tile16_ld(n);
+  const double alpha = -(h * h) / M16;
+  const int waves = (n + 3) / 4;
+  const dim3 grid((waves + 3) / 4);
+  for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    const int nr = nrhs - r0 < 4 ? nrhs - r0 : 4;
+    const double* xr = X + (int64_t)r0 * ldx;
+    double* ur = U + (int64_t)r0 * ldu;
+    switch (nr) {
+      case 1: hipLaunchKernelGGL(gemv_tile16_kernel<1>, grid, dim3(256), 0, s, Q, ldq, E, tk, n, xr, ldx, alpha, bias, ur, ldu); break;
+      case 2: hipLaunchKernelGGL(gemv_tile16_kernel<2>, grid, dim3(256), 0, s, Q, ldq, E, tk, n, xr, ldx, alpha, bias, ur, ldu); break;
+      case 3: hipLaunchKernelGGL(gemv_tile16_kernel<3>, grid, dim3(256), 0, s, Q, ldq, E, tk, n, xr, ldx, alpha, bias, ur, ldu); break;
+      default: hipLaunchKernelGGL(gemv_tile16_kernel<4>, grid, dim3(256), 0, s, Q, ldq, E, tk, n, xr, ldx, alpha, bias, ur, ldu); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}

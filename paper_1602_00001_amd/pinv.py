@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libpinv.so")
 
 OK, E_INVALID_ARG, E_NOT_SPD, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
-MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8": 4, "fp64_sym": 5}
+MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8": 4, "fp64_sym": 5, "fix16_tile": 6}
 SCALE_ROW = 0
 
 
@@ -47,7 +47,8 @@ class Info(ctypes.Structure):
                 ("has_fp64", ctypes.c_int32), ("int8_slices", ctypes.c_int32), ("has_fp32", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("has_lift", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("nz", ctypes.c_int32), ("general", ctypes.c_int32), ("beta", ctypes.c_int32),
-                ("has_sym", ctypes.c_int32)]
+                ("has_sym", ctypes.c_int32),
+                ("has_tile16", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -71,6 +72,7 @@ def _load():
         "pinv_quantize_inverse": ([vp, i32, i32, i32, vp], i32),
         "pinv_prepare_split": ([vp, i32, vp], i32),
         "pinv_export_quantized": ([vp, vp, vp, vp], i32),
+        "pinv_export_tile16": ([vp, vp, vp, vp], i32),
         "pinv_apply_inverse": ([vp, i32, i32, dp, i64, i32, dp, i64, vp], i32),
         "pinv_apply_inverse_adjoint": ([vp, i32, i32, dp, i64, i32, dp, i64, vp], i32),
         "pinv_grad_eps": ([vp, dp, i64, dp, i64, i32, dp, vp], i32),
@@ -97,7 +99,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_build_inverse_general", "pinv_build_inverse_beta", "pinv_grad_eps_general", "pinv_grad_beta", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
-            "pinv_prepare_split", "pinv_export_quantized", "pinv_apply_inverse", "pinv_apply_inverse_adjoint",
+            "pinv_prepare_split", "pinv_export_quantized", "pinv_export_tile16", "pinv_apply_inverse", "pinv_apply_inverse_adjoint",
             "pinv_grad_eps", "pinv_apply_batched", "pinv_get_info", "pinv_destroy", "pinv_status_string",
             "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_int8_variants",
             "pinv_set_int8_variant", "pinv_autotune_int8")
@@ -285,6 +287,15 @@ class PoissonInverse:
         e = np.empty(self.n, dtype=np.int32)
         _check(lib.pinv_export_quantized(self._h, _ptr(Q), _ptr(e), _stream(stream)), "pinv_export_quantized")
         return Q, e
+
+    def export_tile16(self, stream=None):
+        """(q int16 [N, N], tile exponents int32 [T, T]) of the 16-bit copy with
+        64 x 64 tile scales (after ``prepare_split("fix16_tile")``)."""
+        T = -(-self.n // 64)
+        q = np.empty((self.n, self.n), dtype=np.int16)
+        e = np.empty((T, T), dtype=np.int32)
+        _check(lib.pinv_export_tile16(self._h, _ptr(q), _ptr(e), _stream(stream)), "pinv_export_tile16")
+        return q, e
 
     # -- the solve and its derivatives ----------------------------------------
     def apply(self, rho, mode="fp64", rho_bits=16, out=None, stream=None):

@@ -65,6 +65,8 @@ def test_host_side_argument_errors(pinv):
     assert lib.pinv_grad_eps_general(None, None, 0, None, 0, 1, None, None, None) == pinv.E_INVALID_ARG
     assert lib.pinv_grad_beta(None, None, 0, None, 0, 1, None, None) == pinv.E_INVALID_ARG
     assert lib.pinv_quantize_inverse(None, 16, 0, 1, None) == pinv.E_INVALID_ARG
+    assert lib.pinv_export_tile16(None, None, None, None) == pinv.E_INVALID_ARG
+    assert lib.pinv_prepare_split(None, 6, None) == pinv.E_INVALID_ARG
     assert lib.pinv_get_info(None, None) == pinv.E_INVALID_ARG
     assert lib.pinv_apply_batched(None, 3, 4, 16, None) == pinv.E_INVALID_ARG
     assert lib.pinv_apply_batched(None, 0, 4, 16, None) == pinv.OK
