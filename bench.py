@@ -447,8 +447,9 @@ def bench_poisson3d_26(args):
 
 def bench_gemv_128(args):
     """One right-hand side per call at 126^2 unknowns: the apply is a pass over
-    the stored inverse (HBM-bound): FP64 GEMV (2.02 GB) and int8 digit planes
-    (24-bit: 0.76 GB)."""
+    the stored inverse (HBM-bound): FP64 GEMV (2.02 GB), the symmetric-packed
+    FP64 copy (1.02 GB), int8 digit planes (24-bit: 0.76 GB) and 16-bit fixed
+    point with 64 x 64 tile scales (0.50 GB)."""
     import torch
     from paper_1602_00001_amd import pinv, workloads
     wl = workloads.quant_128(1)
@@ -457,27 +458,33 @@ def bench_gemv_128(args):
     op = pinv.PoissonInverse.build(n, n, h)
     op.quantize(24)
     op.prepare_split("fp64_sym")
+    op.prepare_split("fix16_tile")
     rho = torch.from_numpy(wl["rho"]).cuda()
     u64 = torch.empty_like(rho)
     u8 = torch.empty_like(rho)
     us = torch.empty_like(rho)
+    ut = torch.empty_like(rho)
     for _ in range(args.warmup):
         op.apply(rho, "fp64", out=u64)
         op.apply(rho, "int8", 16, out=u8)
         op.apply(rho, "fp64_sym", out=us)
+        op.apply(rho, "fix16_tile", out=ut)
     torch.cuda.synchronize()
-    for k in ("gemv_f64", "gemm_i8", "quantize_cols", "gemv_sym"):
+    for k in ("gemv_f64", "gemm_i8", "quantize_cols", "gemv_sym", "gemv_tile16"):
         pinv.trace_read(k)
     pinv.trace_enable(True)
     dt64 = _timed(lambda: op.apply(rho, "fp64", out=u64), args.steps, 0)
     dt8 = _timed(lambda: op.apply(rho, "int8", 16, out=u8), args.steps, 0)
     dts = _timed(lambda: op.apply(rho, "fp64_sym", out=us), args.steps, 0)
+    dtt = _timed(lambda: op.apply(rho, "fix16_tile", out=ut), args.steps, 0)
     pinv.trace_enable(False)
     fms, fcnt = pinv.trace_read("gemv_f64")
     ims, icnt = pinv.trace_read("gemm_i8")
     sms, scnt = pinv.trace_read("gemv_sym")
+    tms, tcnt = pinv.trace_read("gemv_tile16")
     err = float(torch.linalg.vector_norm(u8 - u64) / torch.linalg.vector_norm(u64))
     err_sym = float(torch.linalg.vector_norm(us - u64) / torch.linalg.vector_norm(u64))
+    err_t = float(torch.linalg.vector_norm(ut - u64) / torch.linalg.vector_norm(u64))
     op.close()
     k64 = fms / max(fcnt, 1)
     k8 = ims / max(icnt, 1)
@@ -496,6 +503,14 @@ def bench_gemv_128(args):
                                      "achieved": sym_bytes / (ks * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                      "frac": sym_bytes / (ks * 1e-3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": ks,
                                      "bytes": "packed upper-triangle blocks + block partials written and read"}}
+    kt = tms / max(tcnt, 1)
+    t16_bytes = 2.0 * N * N + 4.0 * nb * nb + 16.0 * N
+    line["fix16_tile"] = {"value": 1.0 / dtt, "unit": "solves/s", "ms_per_step": dtt * 1e3, "rel_l2_vs_fp64": err_t,
+                          "roofline": {"kernel": "gemv_tile16_kernel<1>", "bound": "hbm",
+                                       "achieved": t16_bytes / (kt * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                                       "unit": "GB/s", "frac": t16_bytes / (kt * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                       "avg_launch_ms": kt,
+                                       "bytes": "int16 entries + tile exponents + rho read + u written"}}
     line["int8"] = {"value": 1.0 / dt8, "unit": "solves/s", "ms_per_step": dt8 * 1e3, "rel_l2_vs_fp64": err,
                     "roofline": {"kernel": "gemm_i8_kernel<3,2> (+ split-K epilogue)", "bound": "hbm",
                                  "achieved": gbs8, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs8 / PEAK_HBM_GBS,
