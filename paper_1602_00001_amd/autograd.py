@@ -61,3 +61,27 @@ class PinvSolveGeneral(torch.autograd.Function):
             else:
                 gx = op.grad_eps_general(u, lam, split=False)
         return lam, gx, gy, None, None, None
+
+
+class PinvSolveBeta(torch.autograd.Function):
+    """u = PinvSolveBeta.apply(rho, beta, op, mode, bits) for an op from
+    PoissonInverse.build_beta (Eq. 3 with arbitrary neighbour coefficients,
+    u = A^{-1}(rho + b_B)).  beta: the [4, n_y, n_x] tensor the op was built
+    from (only its gradient is produced here).
+    Gradients: drho = lambda = A^{-T} g; dbeta = (1/4) sum_r lambda_p U_q
+    (pinv_grad_beta)."""
+
+    @staticmethod
+    def forward(ctx, rho, beta, op, mode="fp64", bits=16):
+        u = op.apply(rho.contiguous(), mode=mode, rho_bits=bits)
+        ctx.op, ctx.mode, ctx.bits = op, mode, bits
+        ctx.save_for_backward(u)
+        return u
+
+    @staticmethod
+    def backward(ctx, g):
+        (u,) = ctx.saved_tensors
+        op = ctx.op
+        lam = op.apply_adjoint(g.contiguous(), mode=ctx.mode, g_bits=ctx.bits)
+        dbeta = op.grad_beta(u, lam) if ctx.needs_input_grad[1] else None
+        return lam, dbeta, None, None, None
