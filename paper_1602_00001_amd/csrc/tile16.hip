@@ -65,7 +65,11 @@ __global__ __launch_bounds__(256) void quantize_tiles16_kernel(const double* __r
 
 // 4 rows per wave (one 16-byte load of each row per lane and step serves the
 // same 8 x values), NR right-hand sides.  Whole 512-column steps first (no
-// bounds checks: k + 8 <= n for every lane), then one bounded step.
+// bounds checks: k + 8 <= n for every lane), then one bounded step.  Each
+// step's 512 x values per right-hand side are loaded coalesced (lane l reads
+// x[b + l + 64 j]) into the wave's own LDS slice and read back as each lane's
+// 8 consecutive values; the slice holds 10 doubles per 8 (value j at
+// j + 2 (j / 8)), so the 16 lanes of a 128-bit read hit distinct banks.
 template <int NR>
 __global__ __launch_bounds__(256) void gemv_tile16_kernel(const int16_t* __restrict__ Q, int64_t ldq,
                                                           const int* __restrict__ E, int tk, int n,
@@ -73,8 +77,11 @@ __global__ __launch_bounds__(256) void gemv_tile16_kernel(const int16_t* __restr
                                                           const double* __restrict__ bias, double* __restrict__ U,
                                                           int64_t ldu) {
   constexpr int RW = 4;
+  constexpr int XS = 640;  // 512 values + padding
+  __shared__ __attribute__((aligned(16))) double xs[4][NR][XS];
   const int lane = threadIdx.x & 63;
-  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RW;  // multiple of 4: one row tile
+  const int wave = threadIdx.x >> 6;
+  const int row0 = (blockIdx.x * 4 + wave) * RW;  // multiple of 4: one row tile
   if (row0 >= n) return;
   const int* er = E + (int64_t)(row0 / T16) * tk;
   const int16_t* q[RW];
@@ -85,21 +92,51 @@ __global__ __launch_bounds__(256) void gemv_tile16_kernel(const int16_t* __restr
   for (int u = 0; u < RW; ++u)
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[u][r] = 0.0;
+  double(*xw)[XS] = xs[wave];
 
-  auto step = [&](int k, bool bounded) {
-    const int e = er[k / T16];
+  auto step = [&](int b, bool bounded) {
+    const int k = b + lane * 8;
+    // coalesced x loads into registers, then into the wave's LDS slice
+    double xl[NR][8];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int kk = b + lane + 64 * j;
+        xl[r][j] = bounded ? (kk < n ? X[(int64_t)r * ldx + min(kk, n - 1)] : 0.0) : X[(int64_t)r * ldx + kk];
+      }
+    int4 raw[RW];
+    const bool live = !bounded || k < n;
+    if (live) {
+#pragma unroll
+      for (int u = 0; u < RW; ++u) raw[u] = *(const int4*)(q[u] + k);  // 8 int16, in bounds: k + 8 <= ldq
+    }
+    const int e = live ? er[k / T16] : 0;
+    // (the previous step's reads of the slice were issued before these
+    // writes, and one wave's LDS operations complete in order)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int jj = lane + 64 * j;
+        xw[r][jj + 2 * (jj >> 3)] = xl[r][j];
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double xv[NR][8];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int w = 0; w < 8; ++w) {
-        const int kk = k + w;
-        xv[r][w] = bounded ? (kk < n ? X[(int64_t)r * ldx + min(kk, n - 1)] : 0.0) : X[(int64_t)r * ldx + kk];
+      for (int w = 0; w < 8; w += 2) {
+        const double2 v = *(const double2*)(&xw[r][10 * lane + w]);
+        xv[r][w] = v.x;
+        xv[r][w + 1] = v.y;
       }
+    if (!live) return;
 #pragma unroll
     for (int u = 0; u < RW; ++u) {
-      const int4 raw = *(const int4*)(q[u] + k);  // 8 int16, in bounds: k + 8 <= ldq
-      const int words[4] = {raw.x, raw.y, raw.z, raw.w};
+      const int words[4] = {raw[u].x, raw[u].y, raw[u].z, raw[u].w};
       double qd[8];
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
@@ -117,8 +154,8 @@ __global__ __launch_bounds__(256) void gemv_tile16_kernel(const int16_t* __restr
   };
 
   int b = 0;
-  for (; b + 512 <= n; b += 512) step(b + lane * 8, false);
-  if (b + lane * 8 < n) step(b + lane * 8, true);
+  for (; b + 512 <= n; b += 512) step(b, false);
+  if (b < n) step(b, true);
 
 #pragma unroll
   for (int u = 0; u < RW; ++u)
