@@ -34,7 +34,9 @@
  *   PINV_FIX16_TILE  G rounded to 16-bit fixed point with one power-of-two
  *               exponent per 64 x 64 tile (2-D tile scales instead of one per
  *               row), stored as int16: 2 bytes per entry; the stored integers
- *               times rho in FP64, for few right-hand sides.  Forward only.
+ *               times rho in FP64, for few right-hand sides.  The adjoint
+ *               uses G^T quantised the same way, which is exactly the
+ *               transpose of G's integers and exponents.
  *   PINV_FP32   G and rho rounded to FP32, FP32 products, FP32 accumulation.
  *   PINV_BF16X3 G and rho split into 2 bfloat16 parts each; hi*hi + hi*lo +
  *               lo*hi with FP32 accumulation.
@@ -232,8 +234,11 @@ int32_t pinv_quantize_inverse(pinv_op op, int32_t bits, int32_t scale_mode,
  * PINV_INT8 with 16 bits), held as int16 (N rows of 64 ceil(N/64) entries)
  * with the exponents; the apply forms u_i = -h^2 / M sum_b 2^e_(i/64,b)
  * sum_(k in b) q_ik rho_k + w_i in FP64 (deterministic order; within
- * 1e-12 of the exact value of that sum).  Applies in this mode allocate
- * nothing; the adjoint returns PINV_E_UNSUPPORTED. */
+ * 1e-12 of the exact value of that sum).  G^T is quantised alike into a
+ * second copy for the adjoint (lambda = -h^2 G^T g in the same form; the
+ * transposed tiles have the same maxima, so its integers and exponents are
+ * exactly the transposes of G's): 4 N (64 ceil(N/64)) bytes in all.  Applies
+ * and adjoints in this mode allocate nothing. */
 int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream);
 
 /* Export the 16-bit tile-scaled copy: q (host [N][N] int16, row-major) and

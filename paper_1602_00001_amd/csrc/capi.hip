@@ -138,6 +138,8 @@ void free_op(pinv_op op) {
   if (op->Gsym) (void)hipFree(op->Gsym);
   if (op->Gt16) (void)hipFree(op->Gt16);
   if (op->Et16) (void)hipFree(op->Et16);
+  if (op->Gt16T) (void)hipFree(op->Gt16T);
+  if (op->Et16T) (void)hipFree(op->Et16T);
   if (op->xc) (void)hipFree(op->xc);
   if (op->yc) (void)hipFree(op->yc);
   delete op;
@@ -608,19 +610,26 @@ int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream) {
   if (!op->G) return PINV_E_STATE;
   hipStream_t s = as_stream(stream);
   if (mode == PINV_FIX16_TILE) {
+    // G's integers and exponents for the apply, G^T's for the adjoint
     if (!op->Gt16) {
       const size_t qb = (size_t)op->n * (size_t)tile16_ld(op->n) * sizeof(int16_t);
       const size_t eb = (size_t)tile16_tiles(op->n) * (size_t)tile16_tiles(op->n) * sizeof(int32_t);
-      PINV_HIP_TRY(hipMalloc(&op->Gt16, qb));
-      const hipError_t e = hipMalloc(&op->Et16, eb);
+      void* p[4] = {nullptr, nullptr, nullptr, nullptr};
+      hipError_t e = hipSuccess;
+      for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipMalloc(&p[k], (k & 1) ? eb : qb);
       if (e != hipSuccess) {
-        (void)hipFree(op->Gt16);
-        op->Gt16 = nullptr;
+        for (void* q : p)
+          if (q) (void)hipFree(q);
         return pinv_hip_status(e);
       }
-      op->bytes += (int64_t)(qb + eb);
+      op->Gt16 = (int16_t*)p[0];
+      op->Et16 = (int32_t*)p[1];
+      op->Gt16T = (int16_t*)p[2];
+      op->Et16T = (int32_t*)p[3];
+      op->bytes += (int64_t)(2 * (qb + eb));
     }
-    PINV_HIP_TRY(launch_quantize_tiles16(op->G, op->ldg, op->n, op->Gt16, op->Et16, s));
+    PINV_HIP_TRY(launch_quantize_tiles16(op->G, op->ldg, op->n, 0, op->Gt16, op->Et16, s));
+    PINV_HIP_TRY(launch_quantize_tiles16(op->G, op->ldg, op->n, 1, op->Gt16T, op->Et16T, s));
     PINV_HIP_TRY(hipStreamSynchronize(s));
     return PINV_OK;
   }
@@ -778,8 +787,12 @@ int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits, con
       return fp64_apply(op, true, g, ld_g, nrhs, nullptr, lambda, ld_lambda, s);
     case PINV_FP64_SYM:
       return sym_apply(op, g, ld_g, nrhs, nullptr, lambda, ld_lambda, s);
-    case PINV_FIX16_TILE:
-      return PINV_E_UNSUPPORTED;
+    case PINV_FIX16_TILE: {
+      if (!op->Gt16T) return PINV_E_STATE;
+      TraceScope ts("gemv_tile16", s);
+      return pinv_hip_status(
+          launch_gemv_tile16(op->Gt16T, op->Et16T, op->n, g, ld_g, nrhs, op->h, nullptr, lambda, ld_lambda, s));
+    }
     case PINV_INT8: {
       const int SR = slices_of_bits(g_bits);
       if (!SR) return PINV_E_INVALID_ARG;

@@ -57,6 +57,8 @@ struct pinv_op_s {
   // (ldq = 64 ceil(n/64)), exponents [ceil(n/64)]^2
   int16_t* Gt16 = nullptr;
   int32_t* Et16 = nullptr;
+  int16_t* Gt16T = nullptr;  // the same for G^T (the adjoint's operand)
+  int32_t* Et16T = nullptr;
 
   int64_t bytes = 0;
 };
@@ -217,7 +219,8 @@ hipError_t launch_fill_random_i8(int8_t* p, size_t n, uint32_t seed, hipStream_t
 // ---- split precision ----------------------------------------------------------
 int64_t tile16_ld(int n);
 int tile16_tiles(int n);
-hipError_t launch_quantize_tiles16(const double* G, int64_t ldg, int n, int16_t* Q, int* E, hipStream_t s);
+hipError_t launch_quantize_tiles16(const double* G, int64_t ldg, int n, int trans, int16_t* Q, int* E,
+                                   hipStream_t s);
 hipError_t launch_gemv_tile16(const int16_t* Q, const int* E, int n, const double* X, int64_t ldx, int nrhs,
                               double h, const double* bias, double* U, int64_t ldu, hipStream_t s);
 hipError_t launch_make_fp32(const double* G, int64_t ldg, int n, float* G32, hipStream_t s);

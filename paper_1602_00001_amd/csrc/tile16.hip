@@ -27,10 +27,13 @@ constexpr int T16 = 64;          // tile edge
 constexpr double M16 = 32639.0;  // 127 (256^2 - 1) / 255
 
 // one workgroup per tile (a, b) = (blockIdx.y, blockIdx.x); thread t holds
-// row t / 4, columns 16 (t % 4) .. + 15 of the tile
+// row t / 4, columns 16 (t % 4) .. + 15 of the tile.  trans != 0 quantises
+// G^T (entry (i, j) read from G[j][i]): its tile (a, b) has the maximum of
+// G's tile (b, a) and the same entries, so the result is exactly the
+// transpose of G's integers and exponents (the adjoint's operand).
 __global__ __launch_bounds__(256) void quantize_tiles16_kernel(const double* __restrict__ G, int64_t ldg, int n,
                                                                int tk, int16_t* __restrict__ Q, int64_t ldq,
-                                                               int* __restrict__ E) {
+                                                               int* __restrict__ E, int trans) {
   __shared__ double wmax[4];
   const int a = blockIdx.y, b = blockIdx.x;
   const int tid = threadIdx.x;
@@ -43,7 +46,7 @@ __global__ __launch_bounds__(256) void quantize_tiles16_kernel(const double* __r
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int j = j0 + t;
-    v[t] = (row_in && j < n) ? g[j] : 0.0;
+    v[t] = (row_in && j < n) ? (trans ? G[(int64_t)j * ldg + i] : g[j]) : 0.0;
     m = fmax(m, fabs(v[t]));
   }
 #pragma unroll
@@ -184,10 +187,12 @@ int64_t tile16_ld(int n) { return (int64_t)((n + T16 - 1) / T16) * T16; }
 
 int tile16_tiles(int n) { return (n + T16 - 1) / T16; }
 
-hipError_t launch_quantize_tiles16(const double* G, int64_t ldg, int n, int16_t* Q, int* E, hipStream_t s) {
+hipError_t launch_quantize_tiles16(const double* G, int64_t ldg, int n, int trans, int16_t* Q, int* E,
+                                   hipStream_t s) {
   const int tk = tile16_tiles(n);
   if (tk == 0) return hipSuccess;
-  hipLaunchKernelGGL(quantize_tiles16_kernel, dim3(tk, tk), dim3(256), 0, s, G, ldg, n, tk, Q, tile16_ld(n), E);
+  hipLaunchKernelGGL(quantize_tiles16_kernel, dim3(tk, tk), dim3(256), 0, s, G, ldg, n, tk, Q, tile16_ld(n), E,
+                     trans);
   return hipGetLastError();
 }
 

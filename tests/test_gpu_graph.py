@@ -54,7 +54,8 @@ def test_graph_replay_of_fp64_gemv_apply(torch, nrhs):
         del graph
 
 
-@pytest.mark.parametrize("nx,nrhs,mode", [(32, 200, "int8"), (66, 200, "int8"), (40, 3, "fp64_sym")])
+@pytest.mark.parametrize("nx,nrhs,mode", [(32, 200, "int8"), (66, 200, "int8"), (40, 3, "fp64_sym"),
+                                          (40, 5, "fix16_tile")])
 def test_graph_replay_of_int8_and_packed_applies(torch, nx, nrhs, mode):
     from paper_1602_00001_amd import pinv
     announce(f"HIP graph of 4 {mode} applies nx={nx} nrhs={nrhs}")
@@ -65,7 +66,7 @@ def test_graph_replay_of_int8_and_packed_applies(torch, nx, nrhs, mode):
         if mode == "int8":
             op.quantize(24)
         else:
-            op.prepare_split("fp64_sym")
+            op.prepare_split(mode)
         rho = dev(g.uniform(-1, 1, (nrhs, G.shape[0])))
         eager = op.apply(rho, mode, 16)
         u = torch.full_like(rho, float("nan"))

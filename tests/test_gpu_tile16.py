@@ -50,7 +50,8 @@ def test_tile16_apply_matches_oracle(torch, nx, ny, R, lift, pad):
     """u = -h^2/M sum_b 2^e q rho + w against the oracle on the oracle's own
     integers: 1-9 right-hand sides (chunks of 4 and a ragged chunk), strided
     vectors (ld = N + pad), with and without a lift; N = 56 (only the bounded
-    step), 1102, 4096 (whole 512-column steps), 594."""
+    step), 1102, 4096 (whole 512-column steps), 594; and the adjoint
+    lambda = -h^2 G^T g on the transposed integers and exponents."""
     from paper_1602_00001_amd import pinv
     announce(f"tile16 apply nx={nx} ny={ny} R={R} lift={lift} pad={pad}")
     N = (nx - 2) * (ny - 2)
@@ -64,13 +65,18 @@ def test_tile16_apply_matches_oracle(torch, nx, ny, R, lift, pad):
     ref = apply.tile_apply(q, e, 2, 64, rho, h, w)
     X = np.zeros((R, N + pad))
     X[:, :N] = rho.T
+    gv = g.standard_normal((N, R))
+    ref_adj = apply.tile_apply(q.T, e.T, 2, 64, gv, h)
     with pinv.PoissonInverse.from_inverse(nx, ny, h, G, None, ub, w) as op:
         op.prepare_split("fix16_tile")
         u = host(op.apply(dev(X)[:, :N], "fix16_tile"))
-        with pytest.raises(pinv.PinvError) as ei:
-            op.apply_adjoint(dev(rho.T), "fix16_tile")
-        assert ei.value.status == pinv.E_UNSUPPORTED
+        lam = host(op.apply_adjoint(dev(gv.T), "fix16_tile"))
     assert np.max(np.abs(u.T - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # the adjoint is the exact transpose of the rounded matrix (the oracle's
+    # transposed integers and exponents); on these non-symmetric matrices the
+    # forward copy would miss by far more
+    assert np.max(np.abs(lam.T - ref_adj)) <= 1e-12 * np.max(np.abs(ref_adj))
+    assert np.max(np.abs(apply.tile_apply(q, e, 2, 64, gv, h) - ref_adj)) > 1e-3 * np.max(np.abs(ref_adj))
 
 
 def test_tile16_requires_prepare(torch):
