@@ -74,7 +74,7 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------- */
 #define PINV_OK               0
 #define PINV_E_INVALID_ARG   -1  /* bad size, NULL pointer, ld < N, bad enum   */
-#define PINV_E_NOT_SPD       -2  /* Cholesky met a non-positive pivot (LU: zero pivot) */
+#define PINV_E_NOT_SPD       -2  /* Cholesky met a non-positive pivot (LU: singular matrix) */
 #define PINV_E_OOM           -3  /* device allocation failed or would not fit  */
 #define PINV_E_HIP           -4  /* a HIP runtime call failed                  */
 #define PINV_E_UNSUPPORTED   -5  /* size beyond the integer headroom limits, or an operation the op does not support */

@@ -105,3 +105,18 @@ def test_binding_rejects_missing_library(tmp_path, monkeypatch, pinv):
     monkeypatch.setattr(os.path, "exists", lambda p: False)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+def test_header_constants_match_the_binding(pinv):
+    """Every precision mode and status code #defined in include/pinv.h has the
+    same value in the binding's tables."""
+    src = open(os.path.join(ROOT, "include", "pinv.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define PINV_(\w+)\s+(-?\d+)", src)}
+    modes = {"FP64": "fp64", "FP32": "fp32", "BF16X3": "bf16x3", "BF16X6": "bf16x6", "INT8": "int8",
+             "FP64_SYM": "fp64_sym", "FIX16_TILE": "fix16_tile"}
+    for c, name in modes.items():
+        assert defs[c] == pinv.MODES[name], c
+    assert set(pinv.MODES) == set(modes.values())
+    for c in ("OK", "E_INVALID_ARG", "E_NOT_SPD", "E_OOM", "E_HIP", "E_UNSUPPORTED", "E_STATE"):
+        assert defs[c] == getattr(pinv, c), c
+    assert defs["SCALE_ROW"] == pinv.SCALE_ROW
