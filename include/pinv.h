@@ -211,7 +211,8 @@ int32_t pinv_export_inverse(pinv_op op, double* G_host, int64_t ldg, double* w_h
  * fixed point with bits = 8, 16 or 24 (S = bits/8 int8 digit slices).
  * Replaces any previous quantisation.  keep_fp64 = 0 frees the FP64 G
  * afterwards (FP64/FP32/BF16 applies then return PINV_E_STATE).
- * scale_mode must be PINV_SCALE_ROW.  Synchronous. */
+ * scale_mode must be PINV_SCALE_ROW (64 x 64 tile scales are the separate
+ * 16-bit storage PINV_FIX16_TILE of pinv_prepare_split).  Synchronous. */
 int32_t pinv_quantize_inverse(pinv_op op, int32_t bits, int32_t scale_mode,
                               int32_t keep_fp64, void* stream);
 
