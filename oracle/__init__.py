@@ -15,12 +15,16 @@ Method for Fast Solution of Partial Integro-Differential Equations"):
                   standard method (dense LU with partial pivoting), plus the
                   closed-form DST inverse used to pin it.
 * ``quant``    -- the rounding of the inverse's entries (the rounding experiment
-                  behind Table 1), restated in binary fixed point.
+                  behind Table 1), restated in binary fixed point with one
+                  exponent per row or per 2-D tile.
 * ``apply``    -- step 3: multiply the (rounded) inverse by the right-hand side,
-                  in FP64 and as an exact integer product.
+                  in FP64, as an exact integer product, and with 2-D tile
+                  scales.
 * ``split``    -- BF16/FP32 split-precision emulation with exact products.
-* ``grad``     -- adjoint, eps-gradient and central finite differences (not in
-                  the paper; the derivative of the step-3 map).
+* ``grad``     -- adjoint, eps-gradients (2-D, 3-D, per direction on
+                  non-uniform grids), Eq. 3 coefficient gradient and central
+                  finite differences (not in the paper; the derivative of the
+                  step-3 map).
 * ``table1``   -- Eq. 4-6 and the Table 1 experiment.
 * ``metrics``  -- relative L2 per right-hand side and the Eq. 6 error.
 
