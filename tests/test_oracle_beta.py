@@ -5,7 +5,7 @@ operator, exactly."""
 
 import numpy as np
 
-from oracle import grid
+from oracle import grid, inverse
 
 
 def test_beta_one_is_the_interior_of_fig3():
@@ -58,3 +58,28 @@ def test_m_matrix_invariants_without_symmetry():
     S = Ainv / np.diag(K)[None, :]
     assert np.max(np.abs(S - S.T)) <= 1e-13 * np.max(np.abs(S))
     assert np.allclose(Ainv @ bB, 1.0, rtol=0, atol=1e-13)
+
+
+def test_lu_inverse_with_a_row_exchange_is_exact():
+    """A = [[1, -1, 0], [-1, 1, -1], [0, -1, 1]] (Eq. 3 with four inner
+    coefficients of 4): natural-order elimination meets a zero second pivot, so
+    only a pivoting LU inverts it; the inverse is the integer matrix
+    -[[0, 1, 1], [1, 1, 1], [1, 1, 0]] (det A = -1), reached exactly."""
+    beta = np.zeros((4, 3, 5))
+    beta[3, 1, 1] = beta[2, 1, 2] = beta[3, 1, 2] = beta[2, 1, 3] = 4.0
+    A, _ = grid.beta_operator(5, 3, beta)
+    assert np.array_equal(A, np.array([[1.0, -1.0, 0.0], [-1.0, 1.0, -1.0], [0.0, -1.0, 1.0]]))
+    assert np.array_equal(inverse.lu_inverse(A), -np.array([[0.0, 1.0, 1.0], [1.0, 1.0, 1.0], [1.0, 1.0, 0.0]]))
+
+
+def test_lu_inverse_of_mixed_sign_coefficients_is_a_true_inverse():
+    """beta ~ U(-3, 3): A X = I and X A = I to 1e-12 |A| |X| (max norms), the
+    two-sided residual of an inverse."""
+    g = np.random.default_rng(31)
+    nx, ny = 17, 13
+    A, _ = grid.beta_operator(nx, ny, g.uniform(-3.0, 3.0, (4, ny, nx)))
+    X = inverse.lu_inverse(A)
+    I = np.eye(A.shape[0])
+    scale = np.max(np.abs(A)) * np.max(np.abs(X)) * A.shape[0] ** 0.5
+    assert np.max(np.abs(A @ X - I)) <= 1e-12 * scale
+    assert np.max(np.abs(X @ A - I)) <= 1e-12 * scale
