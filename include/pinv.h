@@ -254,7 +254,9 @@ int32_t pinv_export_quantized(pinv_op op, int8_t* slices_host, int32_t* exponent
                               void* stream);
 
 /* Step 3: u = L^{-1} rho for nrhs right-hand sides,  u = -h^2 G rho + w.
- *   mode      PINV_FP64 / FP32 / BF16X3 / BF16X6 / INT8.
+ *   mode      PINV_FP64 / FP64_SYM / FP32 / BF16X3 / BF16X6 / INT8 /
+ *             FIX16_TILE (FP64_SYM, FP32, BF16X* and FIX16_TILE after
+ *             pinv_prepare_split; INT8 after pinv_quantize_inverse).
  *   rho_bits  8, 16 or 24: fixed-point width of rho in INT8 mode (ignored
  *             otherwise).
  *   rho, u    device, column-major N x nrhs with strides ld_rho, ld_u >= N;
@@ -271,8 +273,10 @@ int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits,
 /* Adjoint of the apply's linear part (not in the paper; the derivative of
  * step 3):  lambda = dLoss/drho = -h^2 * G^T g  for the representation that
  * the mode selects (G^T of the rounded matrix in INT8 mode, where g's row
- * scaling 2^e_k is applied exactly before g is rounded to g_bits per column).
- * Same layout rules as pinv_apply_inverse.  Asynchronous. */
+ * scaling 2^e_k is applied exactly before g is rounded to g_bits per column;
+ * the transposed 16-bit copy in FIX16_TILE mode; the packed upper triangle
+ * itself in FP64_SYM mode, G being symmetric).  Same layout rules as
+ * pinv_apply_inverse.  Asynchronous. */
 int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits,
                                    const double* g, int64_t ld_g, int32_t nrhs,
                                    double* lambda, int64_t ld_lambda, void* stream);
