@@ -236,8 +236,8 @@ class PoissonInverse:
     @classmethod
     def build_beta(cls, nx, ny, beta, u_boundary=None, stream=None):
         """Steps 1-2 for Eq. 3 with arbitrary coefficients beta [4, ny, nx]
-        (directions i-1, i+1, j-1, j+1): GPU LU inverse; the op's h is 1 and
-        apply gives u = A^{-1}(rho + b_B)."""
+        (directions i-1, i+1, j-1, j+1): GPU LU inverse with partial pivoting;
+        the op's h is 1 and apply gives u = A^{-1}(rho + b_B)."""
         b = np.ascontiguousarray(np.asarray(beta, dtype=np.float64))
         if b.shape != (4, ny, nx):
             raise ValueError(f"beta must have shape (4, {ny}, {nx}), got {b.shape}")

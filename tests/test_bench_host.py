@@ -46,3 +46,14 @@ def test_traffic_figure_tied_to_source_and_variant(bench, tmp_path, monkeypatch)
     src.write_text("// a changed kernel\n")
     assert bench._traffic("k.traffic.json", str(src)) is None
     assert bench._traffic("missing.json", str(src)) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py --gpus N with N > 1 exits non-zero with a message saying the
+    build runs on one GPU (no GPU touched: the check precedes any device call)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
