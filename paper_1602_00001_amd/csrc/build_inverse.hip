@@ -373,14 +373,6 @@ __global__ void permute_negate_kernel(const double* __restrict__ Y, int64_t ld, 
   G[(int64_t)r * ld + perm[i]] = -Y[(int64_t)r * ld + i];
 }
 
-// G = -G (n x n, row stride ld)
-__global__ void negate_kernel(double* __restrict__ G, int64_t ld, int n) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * n) return;
-  const int i = (int)(idx / n), q = (int)(idx % n);
-  G[(int64_t)i * ld + q] = -G[(int64_t)i * ld + q];
-}
-
 __global__ void set_identity_kernel(double* __restrict__ A, int64_t lda, int n) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * n) return;
