@@ -112,6 +112,81 @@ def test_quantisation_error_bound(S):
     assert np.all(np.abs(Gh - G) <= bound * (1 + 1e-12))
 
 
+def _brute_quantize_col(col, S, pre=None):
+    """One right-hand side by exact rationals: the optional row pre-scaling
+    2^pre[k] (exact), the frexp exponent of the column's largest magnitude,
+    then per entry one correctly rounded float64 multiply of the exactly
+    scaled value by M_S and a round-half-even."""
+    M = 127 * (256 ** S - 1) // 255
+    vals = [Fraction(v) * (Fraction(2) ** int(pre[k]) if pre is not None else 1) for k, v in enumerate(col)]
+    f = _frexp_exp_exact(max(abs(v) for v in vals))
+    out = [_round_half_even(Fraction(float(v / Fraction(2) ** f * M))) for v in vals]
+    return out, f
+
+
+@pytest.mark.parametrize("S", [1, 2, 3])
+def test_quantize_cols_brute_force(S):
+    """Per-column exponents and digits against exact rationals: columns of
+    magnitudes spread over 2^-12 .. 2^4, an all-zero column (exponent 0,
+    digits 0), a column whose largest magnitude is an exact power of two (its
+    exponent is one more than that power's), and a column with one negative
+    extreme."""
+    g = np.random.default_rng(30 + S)
+    K, R = 11, 7
+    X = g.standard_normal((K, R)) * np.exp2(g.uniform(-12, 4, (1, R)))
+    X[:, 2] = 0.0
+    X[:, 4] = g.uniform(-0.25, 0.25, K)
+    X[3, 4] = 0.5                      # max |x| = 2^-1 exactly -> f = 0
+    X[5, 6] = -40.0 * np.max(np.abs(X[:, 6]))
+    q, f = quant.quantize_cols(X, S)
+    for r in range(R):
+        qb, fb = _brute_quantize_col(X[:, r], S)
+        assert f[r] == fb, r
+        assert list(q[:, r]) == qb, r
+    assert f[2] == 0 and np.all(q[:, 2] == 0)
+    M = quant.max_mag(S)                 # odd, so 0.5 M is a tie: the even neighbour
+    assert f[4] == 0 and q[3, 4] == ((M + 1) // 2 if (M + 1) // 2 % 2 == 0 else (M - 1) // 2)
+    assert -M <= q[5, 6] <= -(M // 2)    # the column's extreme scales into [-1, -1/2)
+    assert np.all(np.abs(q) <= quant.max_mag(S))
+
+
+@pytest.mark.parametrize("S", [1, 2])
+def test_quantize_cols_pre_exponent_brute_force(S):
+    """The adjoint's path: row k of X scaled by 2^pre[k] before the column
+    exponent is taken, checked against exact rationals (pre-scalings that move
+    a column's maximum to another row included)."""
+    g = np.random.default_rng(40 + S)
+    K, R = 9, 5
+    X = g.standard_normal((K, R))
+    pre = g.integers(-6, 7, K)
+    pre[0] = 12                         # row 0 dominates every column after scaling
+    q, f = quant.quantize_cols(X, S, pre_exponent=pre)
+    for r in range(R):
+        qb, fb = _brute_quantize_col(X[:, r], S, pre)
+        assert f[r] == fb, r
+        assert list(q[:, r]) == qb, r
+
+
+def test_quantize_cols_ties_to_even():
+    """Entries whose scaled product lands exactly on k + 1/2 round to the even
+    neighbour, per column (a column of max 0.5 has exponent 0)."""
+    S, M = 1, quant.max_mag(1)
+    xs = [(2 * k + 1) / (2.0 * M) for k in range(50)]
+    col = np.array([0.5] + xs + [-x for x in xs])
+    X = np.stack([col, col * 0.5], axis=1)          # second column: exponent -1, same digits
+    q, f = quant.quantize_cols(X, S)
+    assert list(f) == [0, -1]
+    assert np.array_equal(q[:, 0], q[:, 1])
+    ties = 0
+    for idx, x in enumerate(col[1:], start=1):
+        p = x * M
+        if abs(p - np.trunc(p)) == 0.5:
+            ties += 1
+            assert q[idx, 0] % 2 == 0
+            assert abs(q[idx, 0] - p) == 0.5
+    assert ties >= 20
+
+
 def test_quantize_cols_pre_exponent_is_exact_scaling():
     g = np.random.default_rng(4)
     X = g.standard_normal((30, 5))
