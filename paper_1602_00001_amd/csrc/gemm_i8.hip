@@ -40,6 +40,8 @@
 
 #include "common.h"
 
+#include <type_traits>
+
 #define PINV_LDS(p) ((__attribute__((address_space(3))) void*)(p))
 
 namespace {
@@ -484,6 +486,225 @@ __global__ __launch_bounds__(256) void gemm_i8_splitk_epilogue(GemmI8Args a, int
   ucol[m] = u;
 }
 
+// One wave per SIMD: 256-thread workgroups of 4 waves in 2 x 2, tile 128 rows x
+// 128 right-hand sides, each wave 64 x 64 per class (4 x 4 blocks of 16 x 16).
+// A wave then reads 4 S + 4 SR fragments per 64 bytes of k for 16 S SR
+// products (against 2 S + 4 SR for 8 S SR at 32 x 64), so the LDS reads per
+// product drop by a third.  The C = S + SR - 1 <= 4 class accumulators (64 C
+// registers per lane, up to the whole accumulation register file) are
+// operands of inline-asm products, which read and write each accumulator in
+// place: compiled builtins at this register count copied accumulators between
+// the two register files on every iteration.  Fragments of the next k half
+// are read into a second register set while the current half's products run,
+// and the DMA of the stage two steps ahead is spread over the second half's
+// products; one barrier per 128-byte k step.
+template <int S, int SR>
+struct W4 {
+  static constexpr int C = S + SR - 1;
+  static constexpr int BK = 128;                   // k bytes per stage
+  static constexpr int PLANE = 128 * BK;           // bytes of one operand plane per stage
+  static constexpr int STAGE = (S + SR) * PLANE;
+  static constexpr int IPP = 4;                    // DMA instructions per plane per wave (32 rows)
+  static constexpr int NDMA = (S + SR) * IPP;      // DMA instructions per wave per stage
+  static constexpr int M = S * SR * 16;            // products per wave per k half
+  static constexpr int R = 4 * (S + SR);           // fragment reads per wave per k half
+  static constexpr bool ok = C <= 4 && 2 * STAGE <= LDS_BYTES;
+};
+
+// the product acc += fa * fb on the matrix cores, accumulator in place
+__device__ inline void mfma_i8_acc(v4i& acc, const v4i& fa, const v4i& fb) {
+  asm volatile("v_mfma_i32_16x16x64_i8 %0, %1, %2, %0" : "+a"(acc) : "v"(fa), "v"(fb));
+}
+
+template <int S, int SR, int MAP>
+__global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int tilesM, int tilesN,
+                                                            const GemmI8Group* __restrict__ groups, int ngroups,
+                                                            int total) {
+  using K = W4<S, SR>;
+  static_assert(K::ok, "one-wave-per-SIMD form: at most 4 classes and two stages in LDS");
+  constexpr int C = K::C, BK = K::BK, PLANE = K::PLANE, STAGE = K::STAGE, IPP = K::IPP;
+  constexpr int M = K::M, R = K::R, NDMA = K::NDMA;
+  __shared__ __attribute__((aligned(1024))) int8_t sm[2 * STAGE];
+
+  GemmI8Args a = a_in;
+  int tN = tilesN;
+  const int T = groups ? total : tilesM * tilesN;
+  int tile = tile_index<MAP>(blockIdx.x, T);
+  if (tile >= T) return;
+  if (groups) {
+    int lo = 0, hi = ngroups - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (groups[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    }
+    a = groups[lo].a;
+    tN = groups[lo].tilesN;
+    tile -= groups[lo].tile0;
+  }
+  const int mt = tile / tN, nt = tile % tN;
+  const int m0 = mt * 128, n0 = nt * 128;
+  const int64_t P = a.P;
+  const int64_t KBY = a.kbytes ? a.kbytes : P;
+  const int z = blockIdx.y;
+  const int kfirst = a.ksplit > 1 ? z * (a.kchunk / BK) : 0;
+  const int nsteps = a.ksplit > 1 ? (int)(min(KBY, (int64_t)(z + 1) * a.kchunk) / BK) - kfirst : (int)(KBY / BK);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // DMA: instruction j of wave w fills rows w*32 + j*8 .. + 7 of every plane;
+  // lane l lands at row l / 8, chunk position l % 8 of that block and loads
+  // the logical chunk that the swizzle puts there (the swizzle is an involution)
+  uint32_t off[IPP];
+#pragma unroll
+  for (int j = 0; j < IPP; ++j) {
+    const int row = wave * 32 + j * 8 + lane / 8;
+    off[j] = (uint32_t)row * (uint32_t)KBY + (uint32_t)(swz<8>(row, lane % 8) * 16);
+  }
+  const int8_t* tileA = a.Q + (int64_t)m0 * KBY;
+  const int8_t* tileB = a.X + (int64_t)n0 * KBY;
+  const int64_t planeA = P * KBY, planeB = (int64_t)a.Rpad * KBY;
+
+  // DMA instruction d (0 .. NDMA-1) of stage `step`: plane d / IPP, row block d % IPP
+  auto dma = [&](int step, int d) {
+    const int p = d / IPP, j = d % IPP;
+    const int64_t k0 = (int64_t)__builtin_amdgcn_readfirstlane((kfirst + step) * BK);
+    const int8_t* src = p < S ? tileA + p * planeA + k0 : tileB + (p - S) * planeB + k0;
+    int8_t* dst = sm + (step & 1) * STAGE + p * PLANE + wave * 32 * BK + j * 1024;
+    __builtin_amdgcn_global_load_lds((const void*)(src + off[j]), PINV_LDS(dst), 16, 0, 0);
+  };
+
+  // fragment read offsets within a plane for k half h: row lane % 16 of the
+  // 16-row block (block bases are multiples of 16 rows, where the swizzle's
+  // row term is zero), logical chunk 4h + lane / 16
+  const int frow = lane & 15;
+  const int foff0 = frow * BK + swz<8>(frow, lane >> 4) * 16;
+  const int foff1 = frow * BK + swz<8>(frow, 4 + (lane >> 4)) * 16;
+  const int aoff = (wm * 64) * BK, boff = S * PLANE + (wn * 64) * BK;
+
+  v4i acc[C][4][4];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[c][i][j] = v4i{0, 0, 0, 0};
+
+  v4i fa0[S][4], fb0[SR][4], fa1[S][4], fb1[SR][4];
+
+  // read r (0 .. R-1) of a k half into (fa, fb): G digit r / 4 block r % 4
+  // for r < 4S, else rho digit (r - 4S) / 4 block (r - 4S) % 4
+  auto read = [&](const int8_t* base, int foff, int r, v4i (&fa)[S][4], v4i (&fb)[SR][4]) {
+    if (r < 4 * S) {
+      fa[r / 4][r % 4] = *(const v4i*)(base + (r / 4) * PLANE + aoff + (r % 4) * 16 * BK + foff);
+    } else {
+      const int q = r - 4 * S;
+      fb[q / 4][q % 4] = *(const v4i*)(base + (q / 4) * PLANE + boff + (q % 4) * 16 * BK + foff);
+    }
+  };
+
+  // one k half: the M products of (fa, fb), with the R reads of the next half
+  // into (na, nb) and (when ND > 0) DMA instructions spread between them
+  auto half = [&](const v4i (&fa)[S][4], const v4i (&fb)[SR][4], const int8_t* nbase, int nfoff, v4i (&na)[S][4],
+                  v4i (&nb)[SR][4], int dstep, auto nd) {
+    constexpr int ND = decltype(nd)::value;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int s = q / (SR * 16), t = (q / 16) % SR, i = (q / 4) % 4, j = q % 4;
+      mfma_i8_acc(acc[s + t][i][j], fa[s][i], fb[t][j]);
+#pragma unroll
+      for (int r = (q * R + M - 1) / M; r < ((q + 1) * R + M - 1) / M; ++r) read(nbase, nfoff, r, na, nb);
+      if constexpr (ND > 0) {
+#pragma unroll
+        for (int d = (q * ND + M - 1) / M; d < ((q + 1) * ND + M - 1) / M; ++d) dma(dstep, d);
+      }
+    }
+  };
+
+  using DmaOn = std::integral_constant<int, NDMA>;
+  using DmaOff = std::integral_constant<int, 0>;
+
+  // prologue: stages 0 and 1 in flight, wait for stage 0, read its first half
+#pragma unroll
+  for (int d = 0; d < NDMA; ++d) dma(0, d);
+  if (nsteps > 1) {
+#pragma unroll
+    for (int d = 0; d < NDMA; ++d) dma(1, d);
+    wait_vm<NDMA>();
+  } else {
+    wait_vm<0>();
+  }
+  lds_barrier();
+#pragma unroll
+  for (int r = 0; r < R; ++r) read(sm, foff0, r, fa0, fb0);
+
+  // step k: half 0 (reads of half 1 alongside); this wave's reads of stage k
+  // are complete and its DMA of stage k + 1 has landed, barrier; half 1 (DMA of
+  // stage k + 2 into the buffer just released, reads of stage k + 1's half 0)
+  auto step = [&](int k, auto nd) {
+    const int8_t* cur = sm + (k & 1) * STAGE;
+    const int8_t* nxt = sm + ((k + 1) & 1) * STAGE;
+    half(fa0, fb0, cur, foff1, fa1, fb1, 0, DmaOff{});
+    wait_lgkm0();
+    wait_vm<0>();
+    lds_barrier();
+    half(fa1, fb1, nxt, foff0, fa0, fb0, k + 2, nd);
+  };
+  int k = 0;
+  for (; k + 2 < nsteps; ++k) step(k, DmaOn{});
+  for (; k < nsteps; ++k) step(k, DmaOff{});
+  // (the last step's reads of "stage k + 1" re-read a released buffer; the
+  // values go unused)
+  wait_lgkm0();
+  // the accumulators are read below by ordinary instructions: let the last
+  // products retire first (the hazard checks do not see inside inline asm)
+  asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+
+  if (a.ksplit > 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (n >= a.nrhs) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+          if (m >= a.n) continue;
+#pragma unroll
+          for (int c = 0; c < C; ++c) a.part[(((int64_t)z * C + c) * a.Rpad + n) * P + m] = acc[c][i][j][r];
+        }
+      }
+    return;
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+      if (n >= a.nrhs) continue;
+      const int fn = a.col_exp[n];
+      double* ucol = a.ucols ? a.ucols[n] : a.U + (int64_t)n * a.ldu;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        if (m >= a.n) continue;
+        int64_t v = acc[0][i][j][r];
+#pragma unroll
+        for (int c = 1; c < C; ++c) v = v * 256 + (int64_t)acc[c][i][j][r];
+        const int em = a.row_exp ? a.row_exp[m] : 0;
+        const double scale = ldexp(a.c, em + fn);
+        double u = (double)v * scale;
+        if (a.w) u = u + a.w[m];
+        ucol[m] = u;
+      }
+    }
+  }
+}
+
 // Variants 0-7 (8-wave workgroups, 128 x 128 tiles, one per compute unit):
 // BK = 128 if v % 2 == 0 (falls back to 64 when two 128-byte stages do not
 // fit), else 64; MAP = (v / 2) % 2; PF = v / 4 (fragment reads per digit, or all
@@ -499,6 +720,27 @@ constexpr int bk_of(int v) {
   if (v == 12) return 2 * (S + SR) * 128 * 128 <= LDS_BYTES ? 128 : 64;
   if (v >= 10) return 2 * ((S * 64 + SR * 128) * 128) <= LDS_BYTES / 2 ? 128 : 64;
   return ((v >= 8 || v % 2 == 0) && 2 * (S + SR) * 128 * 128 <= LDS_BYTES) ? 128 : 64;
+}
+
+template <int S, int SR, int V>
+hipError_t launch_v(const GemmI8Args& a, const GemmI8Group* groups, int ngroups, int total, hipStream_t s);
+
+// Variants 13-14: one wave per SIMD (gemm_i8_w4_kernel), MAP = v - 13; where
+// it does not apply (more than 4 classes) they run variants 8-9 instead.
+template <int S, int SR, int V>
+hipError_t launch_w4(const GemmI8Args& a, const GemmI8Group* groups, int ngroups, int total, hipStream_t s) {
+  if constexpr (!W4<S, SR>::ok) {
+    return launch_v<S, SR, V - 5>(a, groups, ngroups, total, s);
+  } else {
+    constexpr int MAP = V - 13;
+    const int tilesM = groups ? 0 : (int)(a.P / 128), tilesN = groups ? 0 : a.Rpad / BN;
+    const int T = groups ? total : tilesM * tilesN;
+    const int grid = MAP == 0 ? ((T + 7) / 8) * 8 : T;
+    const int zs = (!groups && a.ksplit > 1) ? a.ksplit : 1;
+    hipLaunchKernelGGL((gemm_i8_w4_kernel<S, SR, MAP>), dim3(grid, zs), dim3(256), 0, s, a, tilesM, tilesN, groups,
+                       ngroups, total);
+    return hipGetLastError();
+  }
 }
 
 template <int S, int SR, int V>
@@ -532,6 +774,8 @@ hipError_t launch_t(const GemmI8Args& a, int variant, const GemmI8Group* g, int 
     case 10: return launch_v<S, SR, 10>(a, g, ng, tot, s);
     case 11: return launch_v<S, SR, 11>(a, g, ng, tot, s);
     case 12: return launch_v<S, SR, 12>(a, g, ng, tot, s);
+    case 13: return launch_w4<S, SR, 13>(a, g, ng, tot, s);
+    case 14: return launch_w4<S, SR, 14>(a, g, ng, tot, s);
     default: return launch_v<S, SR, 0>(a, g, ng, tot, s);
   }
 }
@@ -554,7 +798,7 @@ hipError_t dispatch(int S, int SR, const GemmI8Args& a, int variant, const GemmI
 
 }  // namespace
 
-int gemm_i8_variants() { return 13; }
+int gemm_i8_variants() { return 15; }
 
 int gemm_i8_tile_rows(int variant) { return (variant == 10 || variant == 11) ? 64 : 128; }
 
