@@ -6,7 +6,7 @@ import pytest
 
 from oracle import apply, grad, metrics, quant, split
 from paper_1602_00001_amd import workloads
-from tests.gpu_util import announce, dev, host, oracle_int8, oracle_inverse, require_gpu, split_tolerances
+from tests.gpu_util import announce, check_split_solve, dev, host, oracle_int8, oracle_inverse, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -208,20 +208,19 @@ def test_int8_adjoint_bit_exact(torch, pinv, nx, ny):
 @pytest.mark.parametrize("nx,ny", [(12, 9), (66, 66)])
 def test_split_modes_against_emulation(torch, pinv, mode, nx, ny):
     """The GPU differs from the exact-product emulation only by FP32
-    accumulation; both stay inside the operand-rounding envelope of the FP64
-    solve (bounds from split_tolerances)."""
+    accumulation (element by element), stays inside the operand-rounding
+    envelope of the FP64 solve, and FP32 / BF16x6 are separated from BF16x3
+    (check_split_solve).  (66, 66) runs several tiles and split k."""
     announce(f"apply {mode} nx={nx} ny={ny}")
     g = np.random.default_rng(5)
     h = 1.0 / (max(nx, ny) - 1)
     G, _, _ = oracle_inverse(nx, ny, workloads.random_eps(nx, ny, g))
     rho = g.uniform(-1, 1, (40, G.shape[0]))
-    emu = split.split_apply(G, rho.T, h, mode)
     with pinv.PoissonInverse.from_inverse(nx, ny, h, G) as op:
         op.prepare_split(mode)
         u = host(op.apply(dev(rho), mode))
-    tol64, tol_emu = split_tolerances(G, rho.T, mode)
-    assert np.all(metrics.rel_l2_per_rhs(u.T, emu) <= tol_emu)
-    assert np.all(metrics.rel_l2_per_rhs(u.T, apply.plain_apply(G, rho.T, h)) <= tol64)
+    err = check_split_solve(u.T, G, rho.T, h, mode)
+    print(f"[split {nx}x{ny}] {mode}: max rel L2 vs FP64 {err.max():.3e}", flush=True)
 
 
 # ---------------------------------------------------------------- derivatives
