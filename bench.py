@@ -55,27 +55,65 @@ def _traffic(summary, kernel_src, variant=None):
 
 
 def _cpu_baseline(wl, bits, rho_bits, nsample, u_gpu):
-    """The oracle's integer apply (quantise rho, exact int64 product, scaling)
-    on a sample of the right-hand sides, on the host; also checks the GPU's
-    output on that sample bit for bit."""
+    """The oracle's applies on a sample of the right-hand sides, on the host's
+    cores: the integer apply that the headline value computes (quantise rho,
+    exact int64 product with the quantised inverse, scaling) and the plain
+    FP64 apply (library matmul), each on every core this process may use and
+    on one core.  The integer apply runs as independent column blocks on a
+    thread pool (numpy releases the interpreter lock inside the product); the
+    FP64 apply's BLAS gets its thread count from threadpoolctl.  The GPU's
+    output on the sample is checked bit for bit against the integer apply."""
+    import concurrent.futures
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import apply, inverse, quant
     n, h, rho = wl["n"], wl["h"], wl["rho"]
+    ncores = len(os.sched_getaffinity(0))
     G = inverse.dst_inverse(n, n)
     S, Sr = bits // 8, rho_bits // 8
     qG, e = quant.quantize_rows(G, S)
-    del G
     sample = np.ascontiguousarray(rho[:nsample].T)
-    t0 = time.perf_counter()
-    qR, f = quant.quantize_cols(sample, Sr)
-    u, _ = apply.integer_apply(qG, e, S, qR, f, Sr, h)
-    dt = time.perf_counter() - t0
-    exact = bool(np.array_equal(u, u_gpu[:nsample].T))
-    return dict(value=nsample / dt, unit="solves/s", cores=1, kind="oracle",
-                sample=f"{nsample} of {rho.shape[0]} right-hand sides of the same batch; integer apply "
-                       f"(quantise rho to {rho_bits}-bit, exact int64 product with the {bits}-bit inverse, "
-                       f"scaling) in numpy int64 matmul, single-threaded; {dt:.2f} s",
-                seconds=dt), exact
+
+    def integer_block(cols):
+        qR, f = quant.quantize_cols(sample[:, cols], Sr)
+        return apply.integer_apply(qG, e, S, qR, f, Sr, h)[0]
+
+    def integer(threads):
+        blocks = [b for b in np.array_split(np.arange(nsample), threads) if b.size]
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            with concurrent.futures.ThreadPoolExecutor(len(blocks)) as ex:
+                parts = list(ex.map(integer_block, blocks))
+            dt = time.perf_counter() - t0
+        return np.concatenate(parts, axis=1), dt
+
+    def fp64(threads):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            apply.plain_apply(G, sample, h)
+            return time.perf_counter() - t0
+
+    u_all, t_int_all = integer(ncores)
+    _, t_int_1 = integer(1)
+    t_f64_all = fp64(ncores)
+    t_f64_1 = fp64(1)
+    exact = bool(np.array_equal(u_all, u_gpu[:nsample].T))
+
+    def rate(dt, threads, what):
+        return {"value": nsample / dt, "unit": "solves/s", "threads": threads, "seconds": dt, "what": what}
+
+    int_what = (f"quantise rho to {rho_bits}-bit, exact int64 product with the {bits}-bit per-row inverse, "
+                f"scaling (numpy int64 matmul)")
+    f64_what = "u = -h^2 G rho in float64 (OpenBLAS matmul)"
+    return dict(value=nsample / t_int_all, unit="solves/s", cores=ncores, kind="oracle",
+                sample=f"{nsample} of {rho.shape[0]} right-hand sides of the same batch; the oracle's integer apply "
+                       f"(the headline arithmetic) on all {ncores} cores; also its integer apply on 1 core and its "
+                       f"FP64 apply on {ncores} cores and on 1 core",
+                nproc=ncores,
+                integer_all_cores=rate(t_int_all, ncores, int_what),
+                integer_1_core=rate(t_int_1, 1, int_what),
+                fp64_all_cores=rate(t_f64_all, ncores, f64_what),
+                fp64_1_core=rate(t_f64_1, 1, f64_what)), exact
 
 
 def main():
