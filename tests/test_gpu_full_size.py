@@ -60,6 +60,42 @@ def test_quant_128_int8_bit_exact_and_accuracy(torch, pinv, case):
     assert err.max() <= 1e-4
 
 
+def test_quant_128_accuracy_contract_uniform_rho(torch, pinv, case):
+    """The 2^-(b-2) accuracy contract on the metric's workload (126^2, iid
+    uniform[-1, 1] right-hand sides, 64 of them), b = 8, 16, 24, with rho
+    rounded to 16 and to 24 bits.  Mean-zero data make G rho cancel, so the
+    per-row rounding misses 2^-(b-2) by the factor kappa_q of the statistical
+    rounding model (tests/gpu_util.rounding_model); the test reports the error
+    against 2^-(b-2), checks that it follows the model (rms over right-hand
+    sides within a factor 2), that it stays within 2^-(b-2) max(1, 2 kappa_q)
+    where rho has at least b bits, and that 24 x 16 bits meets the metric's
+    1e-4."""
+    from tests.gpu_util import rounding_model
+    wl, G = case
+    n, h = wl["n"], wl["h"]
+    rho = wl["rho"][:64]
+    announce(f"full size accuracy contract n={n} nrhs={rho.shape[0]} bits=8/16/24 rho_bits=16/24")
+    with pinv.PoissonInverse.from_inverse(n, n, h, G) as op:
+        x = dev(rho)
+        u64 = host(op.apply(x, "fp64"))
+        for bits in (8, 16, 24):
+            op.quantize(bits)
+            for rho_bits in (16, 24):
+                u = host(op.apply(x, "int8", rho_bits))
+                err = metrics.rel_l2_per_rhs(u.T, u64.T)
+                mG, mR = rounding_model(G, rho.T, bits // 8, rho_bits // 8)
+                ratio = np.sqrt(np.mean(err ** 2)) / np.sqrt(np.mean(mG ** 2 + mR ** 2))
+                kappa = mG / 2.0 ** -(bits - 2)
+                print(f"[full-size] {bits}x{rho_bits}-bit uniform rho: max rel L2 {err.max():.3e} "
+                      f"(2^-(b-2) = {2.0 ** -(bits - 2):.3e}, ratio {err.max() / 2.0 ** -(bits - 2):.2f}); "
+                      f"rms / model {ratio:.3f}; kappa_q median {np.median(kappa):.2f}", flush=True)
+                assert 0.5 <= ratio <= 2.0
+                if rho_bits >= bits:
+                    assert np.all(err <= 2.0 ** -(bits - 2) * np.maximum(1.0, 2.0 * kappa))
+                if bits == 24 and rho_bits == 16:
+                    assert err.max() <= 1e-4
+
+
 def test_quant_128_fp64_sym_one_rhs(torch, pinv, case):
     """The symmetric-packed FP64 form at 126^2 unknowns, one and three
     right-hand sides (the pass-over-G regime), against the oracle's product."""
@@ -87,9 +123,10 @@ def test_quant_128_build_inverse_matches_dst(torch, pinv, case):
 def test_plain_32_and_vareps_64(torch, pinv):
     """The small workloads at their own sizes: 32x32 with one RHS (FP64 GEMV
     path) and 64x64 variable eps with 256 drifting-blob RHS (FP64 and split
-    modes), against the oracle's LU inverse."""
-    from tests.gpu_util import oracle_inverse, split_tolerances
-    from oracle import split
+    modes), against the oracle's LU inverse; the split modes also on the same
+    operator with 256 uniform[-1, 1] right-hand sides, where the data's
+    cancellation separates FP32 and BF16x6 from BF16x3 by accuracy."""
+    from tests.gpu_util import check_split_solve, oracle_inverse
     wl = workloads.plain_32()
     announce("plain_32 fp64 nrhs=1")
     G, _, _ = oracle_inverse(wl["n"], wl["n"])
@@ -101,18 +138,20 @@ def test_plain_32_and_vareps_64(torch, pinv):
     announce("vareps_64 fp64/fp32/bf16x3/bf16x6 nrhs=256")
     G, _, _ = oracle_inverse(wl["n"], wl["n"], wl["eps"])
     ref = apply.plain_apply(G, wl["rho"].T, wl["h"])
+    uni = np.random.default_rng(6).uniform(-1, 1, (256, G.shape[0]))
     with pinv.PoissonInverse.build(wl["n"], wl["n"], wl["h"], wl["eps"]) as op:
         u = host(op.apply(dev(wl["rho"]), "fp64"))
         assert np.max(metrics.rel_l2_per_rhs(u.T, ref)) <= 1e-12
         for mode in ("fp32", "bf16x3", "bf16x6"):
             op.prepare_split(mode)
             um = host(op.apply(dev(wl["rho"]), mode))
-            err = metrics.rel_l2_per_rhs(um.T, ref)
-            tol64, tol_emu = split_tolerances(G, wl["rho"].T, mode)
-            emu = split.split_apply(G, wl["rho"].T, wl["h"], mode)
+            # smooth positive data: FP32 accumulation errors are of the size
+            # of BF16x3's operand error, so only "nearer its own emulation"
+            err = check_split_solve(um.T, G, wl["rho"].T, wl["h"], mode, ref64=ref, separation=1.0, literal=False)
             print(f"[vareps_64] {mode}: rel L2 vs fp64 max {err.max():.3e} median {np.median(err):.3e}", flush=True)
-            assert np.all(err <= tol64)
-            assert np.all(metrics.rel_l2_per_rhs(um.T, emu) <= tol_emu)
+            uu = host(op.apply(dev(uni), mode))
+            err = check_split_solve(uu.T, G, uni.T, wl["h"], mode)
+            print(f"[vareps_64 uniform rho] {mode}: rel L2 vs fp64 max {err.max():.3e}", flush=True)
 
 
 def test_vareps_64_quantised_envelope(torch, pinv):
