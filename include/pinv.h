@@ -65,6 +65,7 @@
 #ifndef PINV_H
 #define PINV_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -269,6 +270,26 @@ int32_t pinv_export_quantized(pinv_op op, int8_t* slices_host, int32_t* exponent
 int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits,
                            const double* rho, int64_t ld_rho, int32_t nrhs,
                            double* u, int64_t ld_u, void* stream);
+
+/* Bytes of device scratch that pinv_apply_inverse_noalloc holds per GPU. */
+#define PINV_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the INT8
+ * apply of pinv_apply_inverse (same arguments, mode INT8), with identical
+ * results, that calls no allocator.  Its scratch (the quantised right-hand
+ * sides, SR * 128 ceil(nrhs / 128) * P bytes with P = 256 ceil(N / 256), plus
+ * 4 bytes per padded right-hand side) is a fixed array of
+ * PINV_NOALLOC_SCRATCH_BYTES per GPU, which the library holds until the
+ * process ends; larger requests return PINV_E_OOM.  k is never split, so ops
+ * whose int32 class sums would need a split (N * 16384 * pairs-per-class >=
+ * 2^31) return PINV_E_UNSUPPORTED.  The current device must be the op's
+ * (PINV_E_INVALID_ARG otherwise).  Every call on one GPU shares that GPU's
+ * scratch: calls that overlap in time on one GPU (other streams, other ops)
+ * race and must be ordered by the caller.  Asynchronous. */
+int32_t pinv_apply_inverse_noalloc(pinv_op op, int32_t rho_bits,
+                                   const double* rho, int64_t ld_rho, int32_t nrhs,
+                                   double* u, int64_t ld_u, void* stream);
 
 /* Adjoint of the apply's linear part (not in the paper; the derivative of
  * step 3):  lambda = dLoss/drho = -h^2 * G^T g  for the representation that

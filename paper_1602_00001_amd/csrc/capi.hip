@@ -51,7 +51,7 @@ std::vector<TraceRec> g_trace;
 }  // namespace
 
 TraceScope::TraceScope(const char* name, hipStream_t s) : name_(name), s_(s) {
-  if (!g_trace_on.load(std::memory_order_relaxed)) return;
+  if (!name || !g_trace_on.load(std::memory_order_relaxed)) return;
   if (hipEventCreate(&a_) != hipSuccess) return;
   if (hipEventCreate(&b_) != hipSuccess) {
     (void)hipEventDestroy(a_);
@@ -192,6 +192,38 @@ bool int8_headroom_ok(int n, int S, int SR) {
   return (double)n * 16384.0 * pairs < 2147483648.0 && int8_total_ok(n, S, SR);
 }
 
+// The quantisation of the right-hand sides and the slice product of one int8
+// apply, on caller-provided scratch: Xq [SR][Rpad][P] int8, f [Rpad] int32
+// and, when ksplit > 1, part [ksplit][C][Rpad][P] int32.
+// (trace = false: no timing events, for the allocation-free entry point)
+hipError_t int8_launch(pinv_op op, const int8_t* Q, const int32_t* row_exp, const int32_t* pre_exp, int SR,
+                       const double* X, int64_t ldx, int nrhs, const double* w, double* U, int64_t ldu,
+                       int Rpad, int variant, int ksplit, int kchunk, int8_t* Xq, int32_t* f, int32_t* part,
+                       hipStream_t s, bool trace = true) {
+  hipError_t e;
+  {
+    TraceScope ts(trace ? "quantize_cols" : nullptr, s);
+    e = launch_quantize_cols(X, ldx, nullptr, op->n, nrhs, Rpad, SR, op->P, pre_exp, Xq, f, s);
+  }
+  if (e != hipSuccess) return e;
+  TraceScope ts(trace ? "gemm_i8" : nullptr, s);
+  GemmI8Args a{};
+  a.Q = Q; a.S = op->S;
+  a.X = Xq; a.SR = SR;
+  a.P = op->P; a.Rpad = Rpad;
+  a.n = op->n; a.nrhs = nrhs;
+  a.row_exp = row_exp;
+  a.col_exp = f;
+  a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
+  a.w = w;
+  a.U = U; a.ldu = ldu;
+  a.variant = variant;
+  a.ksplit = ksplit;
+  a.kchunk = kchunk;
+  a.part = ksplit > 1 ? part : nullptr;
+  return launch_gemm_i8(a, s);
+}
+
 int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const int32_t* pre_exp, int SR,
                    const double* X, int64_t ldx, int nrhs, const double* w, double* U, int64_t ldu,
                    hipStream_t s) {
@@ -212,31 +244,9 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
   void* scratch = nullptr;
   configure_pool_once();
   PINV_HIP_TRY(hipMallocAsync(&scratch, xq_bytes + f_bytes + part_bytes, s));
-  int8_t* Xq = (int8_t*)scratch;
-  int32_t* f = (int32_t*)((char*)scratch + xq_bytes);
-  hipError_t e;
-  {
-    TraceScope ts("quantize_cols", s);
-    e = launch_quantize_cols(X, ldx, nullptr, op->n, nrhs, Rpad, SR, op->P, pre_exp, Xq, f, s);
-  }
-  if (e == hipSuccess) {
-    TraceScope ts("gemm_i8", s);
-    GemmI8Args a{};
-    a.Q = Q; a.S = op->S;
-    a.X = Xq; a.SR = SR;
-    a.P = op->P; a.Rpad = Rpad;
-    a.n = op->n; a.nrhs = nrhs;
-    a.row_exp = row_exp;
-    a.col_exp = f;
-    a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
-    a.w = w;
-    a.U = U; a.ldu = ldu;
-    a.variant = variant;
-    a.ksplit = ksplit;
-    a.kchunk = kchunk;
-    a.part = ksplit > 1 ? (int32_t*)((char*)scratch + xq_bytes + f_bytes) : nullptr;
-    e = launch_gemm_i8(a, s);
-  }
+  const hipError_t e = int8_launch(op, Q, row_exp, pre_exp, SR, X, ldx, nrhs, w, U, ldu, Rpad, variant, ksplit, kchunk,
+                                   (int8_t*)scratch, (int32_t*)((char*)scratch + xq_bytes),
+                                   (int32_t*)((char*)scratch + xq_bytes + f_bytes), s);
   hipError_t e2 = hipFreeAsync(scratch, s);
   if (e != hipSuccess) return pinv_hip_status(e);
   return pinv_hip_status(e2);
@@ -291,6 +301,38 @@ int32_t check_vectors(pinv_op op, const void* in, int64_t ld_in, int nrhs, const
   return PINV_OK;
 }
 
+// ---- allocation-free int8 apply ---------------------------------------------
+// Scratch of pinv_apply_inverse_noalloc: the quantised right-hand sides
+// (Xq [SR][Rpad][P] int8) and their exponents (f [Rpad] int32).  Every GPU the
+// library runs on holds its own copy of this array until the process ends.
+// In host code the array's name is only a stand-in for the symbol: its device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) int8_t scratch[PINV_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[64] = {};
+
+// The device address of `scratch` on the current device (looked up on the
+// first call on that device, with that device current).
+int32_t noalloc_scratch(void** out) {
+  int dev = 0;
+  PINV_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return PINV_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      pinv_log("pinv_apply_inverse_noalloc: hipGetSymbolAddress of the scratch array failed on device %d (%s)", dev,
+               hipGetErrorString(e));
+      return e != hipSuccess ? pinv_hip_status(e) : PINV_E_HIP;
+    }
+    g_noalloc_ptr[dev] = ptr;
+  }
+  *out = g_noalloc_ptr[dev];
+  return PINV_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -305,7 +347,7 @@ const char* pinv_status_string(int32_t st) {
     case PINV_OK: return "ok";
     case PINV_E_INVALID_ARG: return "invalid argument";
     case PINV_E_NOT_SPD: return "operator is not symmetric positive definite (non-positive Cholesky pivot)";
-    case PINV_E_OOM: return "out of device memory";
+    case PINV_E_OOM: return "out of device memory (or more scratch than pinv_apply_inverse_noalloc holds)";
     case PINV_E_HIP: return "HIP runtime error";
     case PINV_E_UNSUPPORTED: return "unsupported size or mode";
     case PINV_E_STATE: return "the op does not hold the representation this call needs";
@@ -774,6 +816,40 @@ int32_t pinv_apply_inverse(pinv_op op, int32_t mode, int32_t rho_bits, const dou
     default:
       return PINV_E_INVALID_ARG;
   }
+}
+
+int32_t pinv_apply_inverse_noalloc(pinv_op op, int32_t rho_bits, const double* rho, int64_t ld_rho, int32_t nrhs,
+                                   double* u, int64_t ld_u, void* stream) {
+  int32_t st = check_vectors(op, rho, ld_rho, nrhs, u, ld_u);
+  if (st != PINV_OK || nrhs == 0) return st;
+  const int SR = slices_of_bits(rho_bits);
+  if (!SR) return PINV_E_INVALID_ARG;
+  if (!op->S) return PINV_E_STATE;
+  // one int32 accumulation over the whole of k must not overflow (a k split
+  // would need a partial-sum buffer)
+  if (!int8_headroom_ok(op->n, op->S, SR)) return PINV_E_UNSUPPORTED;
+  int dev = 0;
+  PINV_HIP_TRY(hipGetDevice(&dev));
+  if (dev != op->device) return PINV_E_INVALID_ARG;
+  const int Rpad = (nrhs + 127) / 128 * 128;
+  const size_t xq_bytes = ((size_t)SR * Rpad * op->P + 255) / 256 * 256;
+  const size_t f_bytes = (size_t)Rpad * sizeof(int32_t);
+  if (xq_bytes + f_bytes > PINV_NOALLOC_SCRATCH_BYTES) {
+    pinv_log("pinv_apply_inverse_noalloc: %zu bytes of scratch needed (%d right-hand sides, %d-bit, %lld padded "
+             "unknowns), more than the %zu bytes held",
+             xq_bytes + f_bytes, nrhs, rho_bits, (long long)op->P, (size_t)PINV_NOALLOC_SCRATCH_BYTES);
+    return PINV_E_OOM;
+  }
+  void* ptr = nullptr;
+  st = noalloc_scratch(&ptr);
+  if (st != PINV_OK) return st;
+  // the quantisation writes every byte of Xq and f the product reads, so
+  // nothing has to start at zero; k is not split (the integer class sums are
+  // exact in any order, so the result equals pinv_apply_inverse's)
+  const hipError_t e = int8_launch(op, op->Q, op->e, nullptr, SR, rho, ld_rho, nrhs, op->w, u, ld_u, Rpad,
+                                   op->i8_variant[SR], 1, (int)op->P, (int8_t*)ptr,
+                                   (int32_t*)((char*)ptr + xq_bytes), nullptr, as_stream(stream), false);
+  return pinv_hip_status(e);
 }
 
 int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits, const double* g, int64_t ld_g,

@@ -74,7 +74,7 @@ int32_t pinv_hip_status(hipError_t e);
 void pinv_log(const char* fmt, ...);
 
 // Records a pair of events around the launches in its scope when tracing is
-// enabled (pinv_trace_enable); a no-op otherwise.
+// enabled (pinv_trace_enable) and name is not null; a no-op otherwise.
 class TraceScope {
  public:
   TraceScope(const char* name, hipStream_t s);

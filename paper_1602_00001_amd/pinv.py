@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libpinv.so")
 OK, E_INVALID_ARG, E_NOT_SPD, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8": 4, "fp64_sym": 5, "fix16_tile": 6}
 SCALE_ROW = 0
+NOALLOC_SCRATCH_BYTES = 64 << 20   # PINV_NOALLOC_SCRATCH_BYTES
 
 
 class PinvError(RuntimeError):
@@ -74,6 +75,7 @@ def _load():
         "pinv_export_quantized": ([vp, vp, vp, vp], i32),
         "pinv_export_tile16": ([vp, vp, vp, vp], i32),
         "pinv_apply_inverse": ([vp, i32, i32, dp, i64, i32, dp, i64, vp], i32),
+        "pinv_apply_inverse_noalloc": ([vp, i32, dp, i64, i32, dp, i64, vp], i32),
         "pinv_apply_inverse_adjoint": ([vp, i32, i32, dp, i64, i32, dp, i64, vp], i32),
         "pinv_grad_eps": ([vp, dp, i64, dp, i64, i32, dp, vp], i32),
         "pinv_grad_eps_general": ([vp, dp, i64, dp, i64, i32, dp, dp, vp], i32),
@@ -99,7 +101,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_build_inverse_general", "pinv_build_inverse_beta", "pinv_grad_eps_general", "pinv_grad_beta", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
-            "pinv_prepare_split", "pinv_export_quantized", "pinv_export_tile16", "pinv_apply_inverse", "pinv_apply_inverse_adjoint",
+            "pinv_prepare_split", "pinv_export_quantized", "pinv_export_tile16", "pinv_apply_inverse", "pinv_apply_inverse_noalloc", "pinv_apply_inverse_adjoint",
             "pinv_grad_eps", "pinv_apply_batched", "pinv_get_info", "pinv_destroy", "pinv_status_string",
             "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_int8_variants",
             "pinv_set_int8_variant", "pinv_autotune_int8")
@@ -309,6 +311,21 @@ class PoissonInverse:
             raise ValueError("out must have as many rows as rho")
         _check(lib.pinv_apply_inverse(self._h, _mode(mode), int(rho_bits), p_rho, ld_rho, nrhs, p_u, ld_u,
                                       _stream(stream)), "pinv_apply_inverse")
+        return out
+
+    def apply_noalloc(self, rho, rho_bits=16, out=None, stream=None):
+        """The INT8 apply through pinv_apply_inverse_noalloc (no device
+        allocation inside the call; ``out`` must then be given by callers that
+        cannot allocate either)."""
+        import torch
+        p_rho, ld_rho, nrhs = _vectors(rho, self.n, "rho")
+        if out is None:
+            out = torch.empty((nrhs, self.n), dtype=torch.float64, device=rho.device)
+        p_u, ld_u, nu = _vectors(out, self.n, "out")
+        if nu != nrhs:
+            raise ValueError("out must have as many rows as rho")
+        _check(lib.pinv_apply_inverse_noalloc(self._h, int(rho_bits), p_rho, ld_rho, nrhs, p_u, ld_u, _stream(stream)),
+               "pinv_apply_inverse_noalloc")
         return out
 
     def apply_adjoint(self, g, mode="fp64", g_bits=16, out=None, stream=None):
