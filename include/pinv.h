@@ -357,13 +357,26 @@ int32_t pinv_grad_beta(pinv_op op, const double* u, int64_t ld_u,
  * runs as one product over all of its right-hand sides: one rho quantisation
  * reading the columns through a device pointer table and one slice GEMM whose
  * epilogue writes every column straight into its request's u (bit-identical
- * to one pinv_apply_inverse call per request).  Other modes run the requests
- * one by one.  Every request is checked before anything is launched; requests
- * must not write into each other's rho or u.  The call waits for work already
- * queued on the stream once, to upload its column table; the products
- * themselves are asynchronous.  In INT8 mode an op whose class sums over all
- * of k could overflow int32 (N * 16384 * pairs-per-class >= 2^31; the grouped
- * product does not split k) gives PINV_E_UNSUPPORTED, with nothing launched. */
+ * to one pinv_apply_inverse call per request); groups whose ops share a digit
+ * count share one launch.  Other modes run the requests one by one.  Every request is checked before anything is
+ * launched; requests must not write into each other's rho or u.
+ * INT8 mode keeps a plan per request list (the device tables, the scratch of
+ * the quantised right-hand sides and the pinned host image the tables were
+ * uploaded from), keyed by the requests' ops, pointers, strides and column
+ * counts, rho_bits, the ops' digit counts, and the stream.  The first call
+ * with a key allocates the plan, uploads its tables (from the plan's own
+ * pinned image, so nothing waits for the copy) and picks each launch's int8
+ * kernel variant by timing every variant with 128-row tiles on that launch
+ * (the call then waits for those timings; results are bit-identical whichever
+ * variant runs); later calls with the same key only launch kernels, so such a call can be captured into a HIP graph, whose
+ * replays stay valid while the plan is kept.  Under stream capture a key seen
+ * for the first time gives PINV_E_STATE.  At most 4 plans are kept (the
+ * least recently used is dropped first, after a device synchronisation); a
+ * plan naming an op is dropped when the op is destroyed or re-quantised;
+ * pinv_batched_release drops all of them.  In INT8 mode an op whose class
+ * sums over all of k could overflow int32 (N * 16384 * pairs-per-class >=
+ * 2^31; the grouped product does not split k) gives PINV_E_UNSUPPORTED, with
+ * nothing launched. */
 typedef struct {
   pinv_op        op;
   const double*  rho;     /* device, column-major N x nrhs, stride ld        */
@@ -375,6 +388,10 @@ typedef struct {
 
 int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
                            int32_t rho_bits, void* stream);
+
+/* Drops every plan of pinv_apply_batched (after a device synchronisation),
+ * releasing their device and pinned host memory. */
+int32_t pinv_batched_release(void);
 
 int32_t pinv_get_info(pinv_op op, pinv_info* info);
 

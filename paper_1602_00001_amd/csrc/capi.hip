@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <cmath>
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <new>
@@ -116,7 +117,10 @@ pinv_op new_op(const pinv_grid* g) {
   return op;
 }
 
+void purge_batch_plans(pinv_op op);
+
 void free_quant(pinv_op op) {
+  purge_batch_plans(op);  // batched plans hold the digit planes' addresses
   if (op->Q) (void)hipFree(op->Q);
   if (op->QT) (void)hipFree(op->QT);
   if (op->e) (void)hipFree(op->e);
@@ -192,6 +196,18 @@ bool int8_headroom_ok(int n, int S, int SR) {
   return (double)n * 16384.0 * pairs < 2147483648.0 && int8_total_ok(n, S, SR);
 }
 
+// The k split of one int8 apply of `variant`: where the tiles alone leave
+// workgroup slots empty (gemm_i8_split_plan), and wherever one int32
+// accumulation over k could overflow (the parts are added exactly in int64).
+void int8_split(pinv_op op, int SR, int Rpad, int variant, int* ksplit, int* kchunk) {
+  gemm_i8_split_plan(op->P, Rpad, variant, ksplit, kchunk);
+  const int64_t klim = int8_k_limit(op->S, SR);
+  if (*kchunk > klim) {
+    *kchunk = (int)klim;
+    *ksplit = (int)((op->P + klim - 1) / klim);
+  }
+}
+
 // The quantisation of the right-hand sides and the slice product of one int8
 // apply, on caller-provided scratch: Xq [SR][Rpad][P] int8, f [Rpad] int32
 // and, when ksplit > 1, part [ksplit][C][Rpad][P] int32.
@@ -230,14 +246,7 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
   const int Rpad = (nrhs + 127) / 128 * 128;
   const int variant = op->i8_variant[SR];
   int ksplit = 1, kchunk = (int)op->P;
-  gemm_i8_split_plan(op->P, Rpad, variant, &ksplit, &kchunk);
-  // k is split (exact int64 sum of the parts) wherever one int32 accumulation
-  // over it could overflow
-  const int64_t klim = int8_k_limit(op->S, SR);
-  if (kchunk > klim) {
-    kchunk = (int)klim;
-    ksplit = (int)((op->P + klim - 1) / klim);
-  }
+  int8_split(op, SR, Rpad, variant, &ksplit, &kchunk);
   const size_t xq_bytes = (size_t)SR * Rpad * op->P;
   const size_t f_bytes = ((size_t)Rpad * sizeof(int32_t) + 255) / 256 * 256;
   const size_t part_bytes = ksplit > 1 ? (size_t)ksplit * (op->S + SR - 1) * Rpad * op->P * sizeof(int32_t) : 0;
@@ -299,6 +308,304 @@ int32_t check_vectors(pinv_op op, const void* in, int64_t ld_in, int nrhs, const
   const char* b1 = b0 + ((int64_t)(nrhs - 1) * ld_out + op->n) * 8;
   if (a0 < b1 && b0 < a1) return PINV_E_INVALID_ARG;
   return PINV_OK;
+}
+
+// ---- batched int8 applies: cached plans ---------------------------------------
+// A plan holds everything one request list needs on the device: the column
+// pointer table, the grouped-launch tables and the scratch of the quantised
+// right-hand sides, plus the host image the tables were uploaded from (pinned,
+// alive as long as the plan, so the upload needs no wait).  Plans are keyed by
+// the request list, the rho width, the ops' digit counts and kernel variants,
+// and the stream; a call with a known key only launches kernels (so it can be
+// captured into a HIP graph, which then stays valid while the plan is kept).
+// At most kMaxPlans are kept (least recently used goes first); plans naming an
+// op are dropped when the op is destroyed or re-quantised.
+struct BatchLaunch {
+  int S, variant;
+  int q0, nq, qcols;       // ordinary-width quantisation groups
+  int qw0, nqw, qcols_w;   // wide-column quantisation groups
+  int g0, ng, tiles;       // product groups
+};
+
+struct BatchPlan {
+  std::vector<char> key;
+  std::vector<pinv_op> ops;
+  char* dtable = nullptr;   // device: column pointers, QuantColsGroup[], GemmI8Group[]
+  char* scratch = nullptr;  // device: quantised rho and exponents
+  char* host = nullptr;     // pinned image of dtable
+  size_t dbytes = 0;
+  size_t q_off = 0, g_off = 0;  // offsets of the two group tables in dtable
+  std::vector<BatchLaunch> launches;
+  uint64_t last_use = 0;
+};
+
+constexpr size_t kMaxPlans = 4;
+std::mutex g_plan_mu;
+uint64_t g_plan_clock = 0;
+
+// (never destroyed: freeing device memory from a static destructor could run
+// after the runtime has shut down)
+std::vector<BatchPlan*>& g_plans() {
+  static std::vector<BatchPlan*>* v = new std::vector<BatchPlan*>();
+  return *v;
+}
+
+void free_plan(BatchPlan* p) {
+  if (p->dtable) (void)hipFree(p->dtable);
+  if (p->scratch) (void)hipFree(p->scratch);
+  if (p->host) (void)hipHostFree(p->host);
+  delete p;
+}
+
+void purge_batch_plans(pinv_op op) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  std::vector<BatchPlan*>& v = g_plans();
+  bool synced = false;
+  for (size_t i = 0; i < v.size();) {
+    BatchPlan* p = v[i];
+    if (std::find(p->ops.begin(), p->ops.end(), op) == p->ops.end()) {
+      ++i;
+      continue;
+    }
+    if (!synced) {
+      (void)hipDeviceSynchronize();  // no launch of the plan may still be running
+      synced = true;
+    }
+    free_plan(p);
+    v.erase(v.begin() + (long)i);
+  }
+}
+
+template <class T>
+void put(std::vector<char>& k, const T& x) {
+  const char* b = (const char*)&x;
+  k.insert(k.end(), b, b + sizeof(T));
+}
+
+std::vector<char> plan_key(const pinv_request* reqs, int nreq, int SR, hipStream_t s) {
+  std::vector<char> k;
+  k.reserve(48 + (size_t)nreq * 48);
+  put(k, SR);
+  put(k, s);
+  put(k, nreq);
+  for (int i = 0; i < nreq; ++i) {
+    const pinv_request& r = reqs[i];
+    put(k, r.op);
+    put(k, r.rho);
+    put(k, r.u);
+    put(k, r.ld);
+    put(k, r.nrhs);
+    put(k, r.op->S);
+  }
+  return k;
+}
+
+hipError_t run_quantize(const BatchPlan& plan, const BatchLaunch& L, int SR, hipStream_t s) {
+  const QuantColsGroup* dq = (const QuantColsGroup*)(plan.dtable + plan.q_off);
+  TraceScope ts("quantize_cols", s);
+  hipError_t e = launch_quantize_cols_grouped(dq + L.q0, L.nq, L.qcols, SR, false, s);
+  if (e == hipSuccess) e = launch_quantize_cols_grouped(dq + L.qw0, L.nqw, L.qcols_w, SR, true, s);
+  return e;
+}
+
+hipError_t run_product(const BatchPlan& plan, const BatchLaunch& L, int variant, int SR, hipStream_t s) {
+  const GemmI8Group* dg = (const GemmI8Group*)(plan.dtable + plan.g_off);
+  return launch_gemm_i8_grouped(dg + L.g0, L.ng, L.tiles, L.S, SR, variant, s);
+}
+
+// The kernel variant of each of a new plan's product launches: every variant
+// with 128-row tiles is timed on the launch itself (the plan's own groups and
+// right-hand sides, best of two runs after a warm-up); the results are
+// bit-identical whichever runs, so the launches write the caller's u with the
+// final values.  A one-time cost of the first call with a request list.
+int32_t tune_plan(BatchPlan* plan, int SR, hipStream_t s) {
+  hipEvent_t a = nullptr, b = nullptr;
+  PINV_HIP_TRY(hipEventCreate(&a));
+  hipError_t e = hipEventCreate(&b);
+  for (BatchLaunch& L : plan->launches) {
+    if (e == hipSuccess) e = run_quantize(*plan, L, SR, s);
+    double best = 1e30;
+    for (int v = 0; v < gemm_i8_variants() && e == hipSuccess; ++v) {
+      if (gemm_i8_tile_rows(v) != 128) continue;
+      e = run_product(*plan, L, v, SR, s);
+      double t = 1e30;
+      for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+        e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = run_product(*plan, L, v, SR, s);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess) t = std::min(t, (double)ms);
+      }
+      if (e == hipSuccess && t < best) {
+        best = t;
+        L.variant = v;
+      }
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return pinv_hip_status(e);
+}
+
+// Builds a plan: requests grouped by op (in order of first appearance); per
+// digit count S one grouped product launch (kernel variant timed on it), with
+// two grouped quantisation launches (ordinary and 16385-40960-entry columns).
+int32_t make_plan(const pinv_request* reqs, int nreq, int SR, hipStream_t s, BatchPlan* plan) {
+  std::vector<pinv_op>& ops = plan->ops;
+  std::unordered_map<pinv_op, std::vector<int>> members;
+  for (int i = 0; i < nreq; ++i) {
+    if (reqs[i].nrhs == 0) continue;
+    pinv_op op = reqs[i].op;
+    auto it = members.find(op);
+    if (it == members.end()) {
+      ops.push_back(op);
+      members[op] = {i};
+    } else {
+      it->second.push_back(i);
+    }
+  }
+  const int ng = (int)ops.size();
+  std::vector<int64_t> first(ng), count(ng), Rpad(ng), xq_off(ng), f_off(ng);
+  std::vector<const void*> cols;
+  size_t xq_bytes = 0, f_bytes = 0;
+  for (int g = 0; g < ng; ++g) {
+    first[g] = (int64_t)cols.size();
+    for (int i : members[ops[g]])
+      for (int j = 0; j < reqs[i].nrhs; ++j) cols.push_back(reqs[i].rho + (int64_t)j * reqs[i].ld);
+    count[g] = (int64_t)cols.size() - first[g];
+    for (int i : members[ops[g]])
+      for (int j = 0; j < reqs[i].nrhs; ++j) cols.push_back(reqs[i].u + (int64_t)j * reqs[i].ld);
+    Rpad[g] = (count[g] + 127) / 128 * 128;
+    xq_off[g] = (int64_t)xq_bytes;
+    xq_bytes += (size_t)SR * Rpad[g] * ops[g]->P;
+    f_off[g] = (int64_t)f_bytes;
+    f_bytes += (size_t)Rpad[g] * sizeof(int32_t);
+  }
+  auto align256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t cols_bytes = align256(cols.size() * sizeof(void*));
+  const size_t qg_bytes = align256(ng * sizeof(QuantColsGroup));
+  const size_t gg_bytes = align256(ng * sizeof(GemmI8Group));
+  plan->dbytes = cols_bytes + qg_bytes + gg_bytes;
+  plan->q_off = cols_bytes;
+  plan->g_off = cols_bytes + qg_bytes;
+  PINV_HIP_TRY(hipMalloc((void**)&plan->dtable, plan->dbytes));
+  PINV_HIP_TRY(hipMalloc((void**)&plan->scratch, align256(xq_bytes) + f_bytes));
+  PINV_HIP_TRY(hipHostMalloc((void**)&plan->host, plan->dbytes, hipHostMallocDefault));
+  std::memset(plan->host, 0, plan->dbytes);
+  const void* const* dcols = (const void* const*)plan->dtable;
+  int8_t* Xq = (int8_t*)plan->scratch;
+  int32_t* F = (int32_t*)(plan->scratch + align256(xq_bytes));
+  std::memcpy(plan->host, cols.data(), cols.size() * sizeof(void*));
+  QuantColsGroup* hq = (QuantColsGroup*)(plan->host + cols_bytes);
+  GemmI8Group* hg = (GemmI8Group*)(plan->host + cols_bytes + qg_bytes);
+
+  // launches: one per digit count S, in order of S; all variants considered
+  // below have 128-row tiles, so the tables do not depend on the choice
+  int slot = 0;
+  for (int S = 1; S <= 3; ++S) {
+    bool has = false;
+    for (int g = 0; g < ng; ++g) has = has || ops[g]->S == S;
+    if (!has) continue;
+    BatchLaunch L{S, 0, slot, 0, 0, 0, 0, 0, slot, 0, 0};
+    const int rows = 128;
+    // ordinary-width columns first, then the wide ones (their quantisation
+    // runs in a launch of its own); the product groups keep the same order
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1) L.qw0 = slot;
+      for (int g = 0; g < ng; ++g) {
+        pinv_op op = ops[g];
+        if (op->S != L.S || quantize_cols_wide(op->n) != (pass == 1)) continue;
+        QuantColsGroup& q = hq[slot];
+        q.xcols = (const double* const*)(dcols + first[g]);
+        q.Xq = Xq + xq_off[g];
+        q.f = (int32_t*)((char*)F + f_off[g]);
+        q.P = op->P;
+        q.n = op->n;
+        q.nrhs = (int)count[g];
+        q.Rpad = (int)Rpad[g];
+        q.col0 = pass == 0 ? L.qcols : L.qcols_w;
+        GemmI8Group& G = hg[slot];
+        G.a.Q = op->Q; G.a.S = op->S;
+        G.a.X = q.Xq; G.a.SR = SR;
+        G.a.P = op->P; G.a.Rpad = (int)Rpad[g];
+        G.a.n = op->n; G.a.nrhs = (int)count[g];
+        G.a.row_exp = op->e;
+        G.a.col_exp = q.f;
+        G.a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
+        G.a.w = op->w;
+        G.a.U = nullptr; G.a.ldu = 0;
+        G.a.ucols = (double* const*)(dcols + first[g] + count[g]);
+        G.tilesM = (int)(op->P / rows);
+        G.tilesN = (int)(Rpad[g] / 128);
+        G.tile0 = L.tiles;
+        if (pass == 0) {
+          L.qcols += (int)Rpad[g];
+          ++L.nq;
+        } else {
+          L.qcols_w += (int)Rpad[g];
+          ++L.nqw;
+        }
+        L.tiles += G.tilesM * G.tilesN;
+        ++L.ng;
+        ++slot;
+      }
+    }
+    plan->launches.push_back(L);
+  }
+  // the pinned image lives as long as the plan, so the upload is not waited for
+  PINV_HIP_TRY(hipMemcpyAsync(plan->dtable, plan->host, plan->dbytes, hipMemcpyHostToDevice, s));
+  return tune_plan(plan, SR, s);
+}
+
+int32_t find_or_make_plan(const pinv_request* reqs, int nreq, int SR, hipStream_t s, BatchPlan** out) {
+  std::vector<char> key = plan_key(reqs, nreq, SR, s);
+  std::vector<BatchPlan*>& v = g_plans();
+  for (BatchPlan* p : v)
+    if (p->key == key) {
+      p->last_use = ++g_plan_clock;
+      *out = p;
+      return PINV_OK;
+    }
+  // a new plan allocates: not while the stream is being captured
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  PINV_HIP_TRY(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) {
+    pinv_log("pinv_apply_batched: a request list seen for the first time cannot be planned under stream capture");
+    return PINV_E_STATE;
+  }
+  if (v.size() >= kMaxPlans) {
+    size_t lru = 0;
+    for (size_t i = 1; i < v.size(); ++i)
+      if (v[i]->last_use < v[lru]->last_use) lru = i;
+    PINV_HIP_TRY(hipDeviceSynchronize());  // its launches may still be running
+    free_plan(v[lru]);
+    v.erase(v.begin() + (long)lru);
+  }
+  BatchPlan* p = new (std::nothrow) BatchPlan();
+  if (!p) return PINV_E_OOM;
+  p->key = std::move(key);
+  const int32_t st = make_plan(reqs, nreq, SR, s, p);
+  if (st != PINV_OK) {
+    free_plan(p);
+    return st;
+  }
+  p->last_use = ++g_plan_clock;
+  v.push_back(p);
+  *out = p;
+  return PINV_OK;
+}
+
+hipError_t run_plan(const BatchPlan& plan, int SR, hipStream_t s) {
+  for (const BatchLaunch& L : plan.launches) {
+    hipError_t e = run_quantize(plan, L, SR, s);
+    if (e != hipSuccess) return e;
+    TraceScope ts("gemm_i8", s);
+    e = run_product(plan, L, L.variant, SR, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ---- allocation-free int8 apply ---------------------------------------------
@@ -971,148 +1278,29 @@ int32_t pinv_apply_batched(const pinv_request* reqs, int32_t nreq, int32_t mode,
   }
   const int SR = slices_of_bits(rho_bits);
   if (!SR) return PINV_E_INVALID_ARG;
-  // group the requests by operator, in order of first appearance
-  std::vector<pinv_op> ops;
-  std::unordered_map<pinv_op, std::vector<int>> members;
+  bool any = false;
   for (int i = 0; i < nreq; ++i) {
     if (reqs[i].nrhs == 0) continue;
-    pinv_op op = reqs[i].op;
-    if (!op->S) return PINV_E_STATE;
-    if (!int8_headroom_ok(op->n, op->S, SR)) return PINV_E_UNSUPPORTED;
-    auto it = members.find(op);
-    if (it == members.end()) {
-      ops.push_back(op);
-      members[op] = {i};
-    } else {
-      it->second.push_back(i);
-    }
+    if (!reqs[i].op->S) return PINV_E_STATE;
+    if (!int8_headroom_ok(reqs[i].op->n, reqs[i].op->S, SR)) return PINV_E_UNSUPPORTED;
+    any = true;
   }
-  if (ops.empty()) return PINV_OK;
-  const int ng = (int)ops.size();
-
-  // Every group of one digit count S runs in one grouped quantisation launch
-  // and one grouped product launch.  The product's kernel variant is that of
-  // the operator with the most work in the class.
-  std::vector<int64_t> first(ng), count(ng), Rpad(ng), xq_off(ng), f_off(ng);
-  std::vector<const void*> cols;
-  size_t xq_bytes = 0, f_bytes = 0;
-  for (int g = 0; g < ng; ++g) {
-    first[g] = (int64_t)cols.size();
-    for (int i : members[ops[g]])
-      for (int j = 0; j < reqs[i].nrhs; ++j) cols.push_back(reqs[i].rho + (int64_t)j * reqs[i].ld);
-    count[g] = (int64_t)cols.size() - first[g];
-    for (int i : members[ops[g]])
-      for (int j = 0; j < reqs[i].nrhs; ++j) cols.push_back(reqs[i].u + (int64_t)j * reqs[i].ld);
-    Rpad[g] = (count[g] + 127) / 128 * 128;
-    xq_off[g] = (int64_t)xq_bytes;
-    xq_bytes += (size_t)SR * Rpad[g] * ops[g]->P;
-    f_off[g] = (int64_t)f_bytes;
-    f_bytes += (size_t)Rpad[g] * sizeof(int32_t);
-  }
-  auto align16 = [](size_t b) { return (b + 15) / 16 * 16; };
-  const size_t cols_bytes = align16(cols.size() * sizeof(void*));
-  const size_t qg_bytes = align16(ng * sizeof(QuantColsGroup));
-  const size_t gg_bytes = align16(ng * sizeof(GemmI8Group));
-  const size_t table_bytes = cols_bytes + qg_bytes + gg_bytes;
-  const size_t scratch_bytes = align16(xq_bytes) + f_bytes;
-
+  if (!any) return PINV_OK;
   hipStream_t s = as_stream(stream);
-  configure_pool_once();
-  char* dtable = nullptr;
-  char* scratch = nullptr;
-  PINV_HIP_TRY(hipMallocAsync((void**)&dtable, table_bytes, s));
-  hipError_t e = hipMallocAsync((void**)&scratch, scratch_bytes, s);
-  if (e != hipSuccess) {
-    (void)hipFreeAsync(dtable, s);
-    return pinv_hip_status(e);
-  }
-  const void* const* dcols = (const void* const*)dtable;
-  int8_t* Xq = (int8_t*)scratch;
-  int32_t* F = (int32_t*)(scratch + align16(xq_bytes));
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  BatchPlan* plan = nullptr;
+  const int32_t st = find_or_make_plan(reqs, nreq, SR, s, &plan);
+  if (st != PINV_OK) return st;
+  return pinv_hip_status(run_plan(*plan, SR, s));
+}
 
-  // host image of the tables, groups ordered by digit count
-  std::vector<char> host(table_bytes, 0);
-  std::memcpy(host.data(), cols.data(), cols.size() * sizeof(void*));
-  QuantColsGroup* hq = (QuantColsGroup*)(host.data() + cols_bytes);
-  GemmI8Group* hg = (GemmI8Group*)(host.data() + cols_bytes + qg_bytes);
-  // per digit count: one grouped GEMM launch over all its groups, and two
-  // grouped quantisation launches (groups with 16385-40960-entry columns,
-  // which take 1024-thread workgroups, placed after the others)
-  struct Launch { int S, g0, ng, cols, tiles, variant, nn, cols_w; };
-  std::vector<Launch> launches;
-  int slot = 0;
-  for (int S = 1; S <= 3; ++S) {
-    Launch L{S, slot, 0, 0, 0, 0, 0, 0};
-    double most = -1.0;
-    for (int g = 0; g < ng; ++g)
-      if (ops[g]->S == S) {
-        const double work = (double)ops[g]->P * ops[g]->P * Rpad[g];
-        if (work > most) {
-          most = work;
-          L.variant = ops[g]->i8_variant[SR];
-        }
-      }
-    const int rows = gemm_i8_tile_rows(L.variant);
-    for (int pass = 0; pass < 2; ++pass)
-    for (int g = 0; g < ng; ++g) {
-      if (ops[g]->S != S || quantize_cols_wide(ops[g]->n) != (pass == 1)) continue;
-      pinv_op op = ops[g];
-      QuantColsGroup& q = hq[slot];
-      q.xcols = (const double* const*)(dcols + first[g]);
-      q.Xq = Xq + xq_off[g];
-      q.f = (int32_t*)((char*)F + f_off[g]);
-      q.P = op->P;
-      q.n = op->n;
-      q.nrhs = (int)count[g];
-      q.Rpad = (int)Rpad[g];
-      q.col0 = pass == 0 ? L.cols : L.cols_w;
-      GemmI8Group& G = hg[slot];
-      G.a.Q = op->Q; G.a.S = op->S;
-      G.a.X = q.Xq; G.a.SR = SR;
-      G.a.P = op->P; G.a.Rpad = (int)Rpad[g];
-      G.a.n = op->n; G.a.nrhs = (int)count[g];
-      G.a.row_exp = op->e;
-      G.a.col_exp = q.f;
-      G.a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
-      G.a.w = op->w;
-      G.a.U = nullptr; G.a.ldu = 0;
-      G.a.ucols = (double* const*)(dcols + first[g] + count[g]);
-      G.tilesM = (int)(op->P / rows);
-      G.tilesN = (int)(Rpad[g] / 128);
-      G.tile0 = L.tiles;
-      if (pass == 0) {
-        L.cols += (int)Rpad[g];
-        ++L.nn;
-      } else {
-        L.cols_w += (int)Rpad[g];
-      }
-      L.tiles += G.tilesM * G.tilesN;
-      ++L.ng;
-      ++slot;
-    }
-    if (L.ng) launches.push_back(L);
-  }
-  e = hipMemcpyAsync(dtable, host.data(), table_bytes, hipMemcpyHostToDevice, s);
-  // the host image must outlive the copy
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  const QuantColsGroup* dq = (const QuantColsGroup*)(dtable + cols_bytes);
-  const GemmI8Group* dg = (const GemmI8Group*)(dtable + cols_bytes + qg_bytes);
-  for (const Launch& L : launches) {
-    if (e != hipSuccess) break;
-    {
-      TraceScope ts("quantize_cols", s);
-      e = launch_quantize_cols_grouped(dq + L.g0, L.nn, L.cols, SR, false, s);
-      if (e == hipSuccess) e = launch_quantize_cols_grouped(dq + L.g0 + L.nn, L.ng - L.nn, L.cols_w, SR, true, s);
-    }
-    if (e != hipSuccess) break;
-    TraceScope ts("gemm_i8", s);
-    e = launch_gemm_i8_grouped(dg + L.g0, L.ng, L.tiles, L.S, SR, L.variant, s);
-  }
-  const hipError_t e2 = hipFreeAsync(scratch, s);
-  const hipError_t e3 = hipFreeAsync(dtable, s);
-  if (e != hipSuccess) return pinv_hip_status(e);
-  if (e2 != hipSuccess) return pinv_hip_status(e2);
-  return pinv_hip_status(e3);
+int32_t pinv_batched_release(void) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  if (g_plans().empty()) return PINV_OK;
+  const hipError_t e = hipDeviceSynchronize();
+  for (BatchPlan* p : g_plans()) free_plan(p);
+  g_plans().clear();
+  return pinv_hip_status(e);
 }
 
 int32_t pinv_get_info(pinv_op op, pinv_info* info) {
@@ -1152,39 +1340,52 @@ int32_t pinv_autotune_int8(pinv_op op, int32_t rho_bits, const double* rho, int6
   if (!op->S) return PINV_E_STATE;
   hipStream_t s = as_stream(stream);
   const int Rpad = (nrhs + 127) / 128 * 128;
+  const int nv = gemm_i8_variants();
+  // every variant is timed with the k split its applies would use
+  std::vector<int> ksplit(nv, 1), kchunk(nv, (int)op->P);
+  int kmax = 1;
+  for (int v = 0; v < nv; ++v) {
+    int8_split(op, SR, Rpad, v, &ksplit[v], &kchunk[v]);
+    kmax = std::max(kmax, ksplit[v]);
+  }
   const size_t xq_bytes = (size_t)SR * Rpad * op->P;
-  const size_t f_bytes = (size_t)Rpad * sizeof(int32_t);
-  const size_t u_bytes = (size_t)nrhs * op->n * sizeof(double);
+  const size_t f_bytes = ((size_t)Rpad * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t u_bytes = ((size_t)nrhs * op->n * sizeof(double) + 255) / 256 * 256;
+  const size_t part_bytes = kmax > 1 ? (size_t)kmax * (op->S + SR - 1) * Rpad * op->P * sizeof(int32_t) : 0;
   char* buf = nullptr;
-  PINV_HIP_TRY(hipMalloc(&buf, xq_bytes + f_bytes + u_bytes));
+  PINV_HIP_TRY(hipMalloc(&buf, xq_bytes + f_bytes + u_bytes + part_bytes));
+  int8_t* Xq = (int8_t*)buf;
+  int32_t* f = (int32_t*)(buf + xq_bytes);
+  double* U = (double*)(buf + xq_bytes + f_bytes);
+  int32_t* part = (int32_t*)(buf + xq_bytes + f_bytes + u_bytes);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipError_t e = hipEventCreate(&ev0);
   if (e == hipSuccess) e = hipEventCreate(&ev1);
   if (rho) {
-    if (e == hipSuccess)
-      e = launch_quantize_cols(rho, ld_rho, nullptr, op->n, nrhs, Rpad, SR, op->P, nullptr, (int8_t*)buf,
-                               (int32_t*)(buf + xq_bytes), s);
+    if (e == hipSuccess) e = launch_quantize_cols(rho, ld_rho, nullptr, op->n, nrhs, Rpad, SR, op->P, nullptr, Xq, f, s);
   } else {
-    if (e == hipSuccess) e = launch_fill_random_i8((int8_t*)buf, xq_bytes, 12345u, s);
-    if (e == hipSuccess) e = hipMemsetAsync(buf + xq_bytes, 0, f_bytes, s);
+    if (e == hipSuccess) e = launch_fill_random_i8(Xq, xq_bytes, 12345u, s);
+    if (e == hipSuccess) e = hipMemsetAsync(f, 0, f_bytes, s);
   }
   GemmI8Args a{};
   a.Q = op->Q; a.S = op->S;
-  a.X = (const int8_t*)buf; a.SR = SR;
+  a.X = Xq; a.SR = SR;
   a.P = op->P; a.Rpad = Rpad;
   a.n = op->n; a.nrhs = nrhs;
   a.row_exp = op->e;
-  a.col_exp = (const int32_t*)(buf + xq_bytes);
+  a.col_exp = f;
   a.c = -(op->h * op->h) / ((double)pinv_max_mag(op->S) * (double)pinv_max_mag(SR));
   a.w = nullptr;
-  a.U = (double*)(buf + xq_bytes + f_bytes); a.ldu = op->n;
+  a.U = U; a.ldu = op->n;
   // three rounds over all variants (so that clock drift during the call does
   // not favour one position); each variant keeps its best round
-  const int nv = gemm_i8_variants();
   std::vector<double> t(nv, 0.0);
   for (int round = 0; round < 3 && e == hipSuccess; ++round) {
     for (int v = 0; v < nv && e == hipSuccess; ++v) {
       a.variant = v;
+      a.ksplit = ksplit[v];
+      a.kchunk = kchunk[v];
+      a.part = ksplit[v] > 1 ? part : nullptr;
       e = launch_gemm_i8(a, s);  // warm-up
       if (e == hipSuccess) e = hipEventRecord(ev0, s);
       for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_gemm_i8(a, s);

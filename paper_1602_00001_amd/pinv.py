@@ -81,6 +81,7 @@ def _load():
         "pinv_grad_eps_general": ([vp, dp, i64, dp, i64, i32, dp, dp, vp], i32),
         "pinv_grad_beta": ([vp, dp, i64, dp, i64, i32, dp, vp], i32),
         "pinv_apply_batched": ([P(Request), i32, i32, i32, vp], i32),
+        "pinv_batched_release": ([], i32),
         "pinv_get_info": ([vp, P(Info)], i32),
         "pinv_destroy": ([vp], i32),
         "pinv_trace_enable": ([i32], i32),
@@ -102,7 +103,7 @@ lib = _load()
 
 EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_build_inverse_general", "pinv_build_inverse_beta", "pinv_grad_eps_general", "pinv_grad_beta", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
             "pinv_prepare_split", "pinv_export_quantized", "pinv_export_tile16", "pinv_apply_inverse", "pinv_apply_inverse_noalloc", "pinv_apply_inverse_adjoint",
-            "pinv_grad_eps", "pinv_apply_batched", "pinv_get_info", "pinv_destroy", "pinv_status_string",
+            "pinv_grad_eps", "pinv_apply_batched", "pinv_batched_release", "pinv_get_info", "pinv_destroy", "pinv_status_string",
             "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_int8_variants",
             "pinv_set_int8_variant", "pinv_autotune_int8")
 
@@ -427,6 +428,11 @@ class PoissonInverse:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def batched_release():
+    """Drop the cached plans of apply_batched (device and pinned memory)."""
+    _check(lib.pinv_batched_release(), "pinv_batched_release")
 
 
 def apply_batched(requests, mode="int8", rho_bits=16, stream=None):

@@ -2,8 +2,9 @@
 request, bit for bit in INT8 mode (the grouping only changes which columns share
 a launch; every column's quantisation and integer product are independent),
 and the per-request results match the oracle.  The operators carry different
-inverse precisions (8/16/24-bit: one grouped launch per digit count) and
-different int8 kernel variants."""
+inverse precisions (one grouped launch per digit count, its kernel variant
+timed on it when the request list is first planned).  A request list's plan is cached: a captured HIP graph of
+the call replays bit-identically, and re-quantising an op drops its plans."""
 
 import numpy as np
 import pytest
@@ -28,7 +29,7 @@ def pinv():
 
 GRIDS = [(12, 9), (20, 20), (33, 17), (40, 40), (25, 30)]
 BITS = [16, 24, 8, 16, 24]
-VARIANTS = [None, 3, None, 8, 10]   # the 24-bit class runs with variant 10 (its largest operator's)
+VARIANTS = [None, 3, None, 8, 13]   # per-op variants (single applies); batched launches time their own
 
 
 @pytest.fixture(scope="module")
@@ -109,3 +110,59 @@ def test_batched_rejects_unquantised_op(torch, pinv):
             pinv.apply_batched([(op, rho, u)], "int8", 16)
         assert ei.value.status == pinv.E_STATE
         assert float(u.abs().sum()) == 0.0
+
+
+def _capture_list(torch, ops, seed, nreq=24):
+    reqs = _requests(torch, ops, seed, nreq)
+    return reqs, [(ops[k]["op"], rho, u) for (k, rho, u, _) in reqs]
+
+
+def test_batched_graph_capture_replays_bit_identical(torch, pinv, ops):
+    """A request list planned by an eager call on a stream, then captured on
+    that stream into a HIP graph: every replay (with other batched and single
+    applies in between) reproduces the eager result bit for bit."""
+    announce("apply_batched int8 graph capture: eager plan, capture, 3 replays")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    reqs, batch = _capture_list(torch, ops, 321)
+    with torch.cuda.stream(s):
+        pinv.apply_batched(batch, "int8", 16, stream=s)
+    s.synchronize()
+    eager = [host(u).copy() for (_, _, u) in batch]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        pinv.apply_batched(batch, "int8", 16, stream=s)
+    other_reqs, other = _capture_list(torch, ops, 654)
+    for rep in range(3):
+        for (_, _, u) in batch:
+            u.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for e, (_, _, u) in zip(eager, batch):
+            assert np.array_equal(host(u), e), rep
+        # eager work between replays: another request list, a single apply
+        pinv.apply_batched(other, "int8", 16)
+        k, rho, u, _ = other_reqs[0]
+        ops[k]["op"].apply(rho, "int8", 16, out=u)
+        torch.cuda.synchronize()
+    del g
+
+
+def test_batched_plans_follow_requantisation(torch, pinv):
+    """A plan names its ops' digit planes: re-quantising an op (new planes,
+    another digit count) drops it, and the next call with the same requests
+    uses the new planes (bit-identical to per-request applies)."""
+    g = np.random.default_rng(77)
+    nx = ny = 30
+    G, _, _ = oracle_inverse(nx, ny, workloads.random_eps(nx, ny, g))
+    with pinv.PoissonInverse.from_inverse(nx, ny, 1.0 / (nx - 1), G) as op:
+        rho = dev(g.uniform(-1, 1, (50, op.n)))
+        u, u2 = torch.empty_like(rho), torch.empty_like(rho[:7])
+        for bits in (16, 24, 16):
+            announce(f"apply_batched after quantize({bits})")
+            op.quantize(bits)
+            pinv.apply_batched([(op, rho, u), (op, rho[:7], u2)], "int8", 16)
+            assert np.array_equal(host(u), host(op.apply(rho, "int8", 16)))
+            assert np.array_equal(host(u2), host(op.apply(rho[:7], "int8", 16)))
+    pinv.batched_release()
