@@ -431,6 +431,11 @@ int32_t pinv_autotune_int8(pinv_op op, int32_t rho_bits, const double* rho, int6
  * stops recording (recorded launches stay readable).  Thread-safe. */
 int32_t pinv_trace_enable(int32_t on);
 int32_t pinv_trace_read(const char* kernel, double* total_ms, int64_t* launches);
+/* The same, also writing the elapsed milliseconds of each recorded launch, in
+ * launch order, to ms_each[0 .. min(launches, cap) - 1] (ms_each may be NULL
+ * when cap is 0). */
+int32_t pinv_trace_read_each(const char* kernel, double* ms_each, int64_t cap,
+                             double* total_ms, int64_t* launches);
 
 /* Free the op and all of its device memory (waits for the device first). */
 int32_t pinv_destroy(pinv_op op);

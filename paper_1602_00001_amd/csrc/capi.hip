@@ -1420,7 +1420,12 @@ int32_t pinv_trace_enable(int32_t on) {
 }
 
 int32_t pinv_trace_read(const char* kernel, double* total_ms, int64_t* launches) {
-  if (!kernel) return PINV_E_INVALID_ARG;
+  return pinv_trace_read_each(kernel, nullptr, 0, total_ms, launches);
+}
+
+int32_t pinv_trace_read_each(const char* kernel, double* ms_each, int64_t cap, double* total_ms,
+                             int64_t* launches) {
+  if (!kernel || cap < 0 || (cap > 0 && !ms_each)) return PINV_E_INVALID_ARG;
   double tot = 0.0;
   int64_t cnt = 0;
   int32_t st = PINV_OK;
@@ -1437,6 +1442,7 @@ int32_t pinv_trace_read(const char* kernel, double* total_ms, int64_t* launches)
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
     if (e != hipSuccess) st = pinv_hip_status(e);
     tot += ms;
+    if (cnt < cap) ms_each[cnt] = ms;
     ++cnt;
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

@@ -86,6 +86,7 @@ def _load():
         "pinv_destroy": ([vp], i32),
         "pinv_trace_enable": ([i32], i32),
         "pinv_trace_read": ([ctypes.c_char_p, P(ctypes.c_double), P(i64)], i32),
+        "pinv_trace_read_each": ([ctypes.c_char_p, P(ctypes.c_double), i64, P(ctypes.c_double), P(i64)], i32),
         "pinv_int8_variants": ([], i32),
         "pinv_set_int8_variant": ([vp, i32, i32], i32),
         "pinv_autotune_int8": ([vp, i32, dp, i64, i32, i32, P(ctypes.c_double), i32, P(i32), vp], i32),
@@ -104,7 +105,7 @@ lib = _load()
 EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_build_inverse_general", "pinv_build_inverse_beta", "pinv_grad_eps_general", "pinv_grad_beta", "pinv_import_inverse", "pinv_export_inverse", "pinv_quantize_inverse",
             "pinv_prepare_split", "pinv_export_quantized", "pinv_export_tile16", "pinv_apply_inverse", "pinv_apply_inverse_noalloc", "pinv_apply_inverse_adjoint",
             "pinv_grad_eps", "pinv_apply_batched", "pinv_batched_release", "pinv_get_info", "pinv_destroy", "pinv_status_string",
-            "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_int8_variants",
+            "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_trace_read_each", "pinv_int8_variants",
             "pinv_set_int8_variant", "pinv_autotune_int8")
 
 
@@ -131,6 +132,17 @@ def trace_read(kernel):
     cnt = ctypes.c_int64()
     _check(lib.pinv_trace_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "pinv_trace_read")
     return ms.value, cnt.value
+
+
+def trace_read_each(kernel, cap=4096):
+    """(list of per-launch milliseconds, launches) of the recorded launches of
+    one kernel family, in launch order (at most ``cap`` listed)."""
+    buf = (ctypes.c_double * cap)()
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(lib.pinv_trace_read_each(kernel.encode(), buf, cap, ctypes.byref(ms), ctypes.byref(cnt)),
+           "pinv_trace_read_each")
+    return list(buf[:min(cnt.value, cap)]), cnt.value
 
 
 def _check(st, what):
