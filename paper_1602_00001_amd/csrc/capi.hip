@@ -269,6 +269,21 @@ int32_t fp64_apply(pinv_op op, bool transpose, const double* X, int64_t ldx, int
     PINV_HIP_TRY(launch_gemv_f64(op->G, op->ldg, op->n, X, ldx, nrhs, alpha, bias, U, ldu, s));
     return PINV_OK;
   }
+  if (!transpose) {
+    // the forward product: one wave per SIMD, 256 x 128 tiles
+    const ApplyF64Plan p = apply_f64_plan(op->n, nrhs, op->n);
+    configure_pool_once();
+    void* scratch = nullptr;
+    PINV_HIP_TRY(hipMallocAsync(&scratch, p.pack_bytes + p.part_bytes, s));
+    hipError_t e;
+    {
+      TraceScope ts("gemm_f64", s);
+      e = launch_apply_f64(p, op->G, op->ldg, op->n, op->n, X, ldx, nrhs, alpha, bias, U, ldu, scratch, s);
+    }
+    const hipError_t e2 = hipFreeAsync(scratch, s);
+    if (e != hipSuccess) return pinv_hip_status(e);
+    return pinv_hip_status(e2);
+  }
   GemmF64Args a{};
   a.A = op->G; a.lda = op->ldg; a.a_kcontig = transpose ? 0 : 1;
   a.B = X; a.ldb = ldx; a.b_kcontig = 1;
@@ -850,6 +865,9 @@ int32_t pinv_import_inverse(const pinv_grid* g, const double* G_host, int64_t ld
   const int n = op->n, nodes = g->nx * g->ny;
   int32_t st = PINV_OK;
   hipError_t e = hipMalloc(&op->G, (size_t)n * op->ldg * sizeof(double));
+  // rows are padded to 32 doubles with zeros (the FP64 apply reads whole
+  // 16-double pieces of k)
+  if (e == hipSuccess) e = hipMemsetAsync(op->G, 0, (size_t)n * op->ldg * sizeof(double), s);
   if (e != hipSuccess) {
     free_op(op);
     return pinv_hip_status(e);

@@ -121,6 +121,21 @@ void gemm_f64_split_plan(int M, int N, int K, int* ksplit, int* kchunk);
 hipError_t launch_splitk_reduce(const double* part, int ksplit, int M, int N, double alpha, double beta,
                                 const double* bias, double* C, int64_t csm, int64_t csn, hipStream_t s);
 
+// FP64 apply u = alpha * G X + bias for many right-hand sides (one wave per
+// SIMD, 256 x 128 tiles; G row-major [M][lda] with zeros past column K up to
+// the next multiple of 16, X column-major K x N with stride ldx).  Scratch:
+// pack_bytes (zero-padded copy of X) + part_bytes (split-k partial sums).
+struct ApplyF64Plan {
+  int tilesM = 0, tilesN = 0, Npad = 0;
+  int64_t ldp = 0;
+  int ksplit = 1, kchunk = 0;
+  size_t pack_bytes = 0, part_bytes = 0;
+};
+ApplyF64Plan apply_f64_plan(int M, int N, int K);
+hipError_t launch_apply_f64(const ApplyF64Plan& p, const double* G, int64_t lda, int M, int K, const double* X,
+                            int64_t ldx, int N, double alpha, const double* bias, double* U, int64_t ldu,
+                            void* scratch, hipStream_t s);
+
 // FP64 GEMV-style apply for few right-hand sides: u = alpha * G x + bias.
 hipError_t launch_gemv_f64(const double* G, int64_t ldg, int n, const double* x, int64_t ldx,
                            int nrhs, double alpha, const double* bias, double* u, int64_t ldu,

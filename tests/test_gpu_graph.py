@@ -1,5 +1,6 @@
 """Applies captured in a HIP graph: the FP64 GEMV apply (at most 4 right-hand
-sides; allocates nothing), the int8 apply (its stream-ordered scratch becomes
+sides; allocates nothing), the FP64 GEMM apply (packing kernel, stream-ordered
+scratch; split k at 64^2), the int8 apply (its stream-ordered scratch becomes
 alloc and free nodes; the split-K epilogue at 64^2) and the symmetric-packed
 FP64 apply.  Every replay, with eager work and synchronisations in between,
 gives the eager result bit for bit."""
@@ -55,7 +56,7 @@ def test_graph_replay_of_fp64_gemv_apply(torch, nrhs):
 
 
 @pytest.mark.parametrize("nx,nrhs,mode", [(32, 200, "int8"), (66, 200, "int8"), (40, 3, "fp64_sym"),
-                                          (40, 5, "fix16_tile")])
+                                          (40, 5, "fix16_tile"), (32, 200, "fp64"), (66, 200, "fp64")])
 def test_graph_replay_of_int8_and_packed_applies(torch, nx, nrhs, mode):
     from paper_1602_00001_amd import pinv
     announce(f"HIP graph of 4 {mode} applies nx={nx} nrhs={nrhs}")
@@ -65,7 +66,7 @@ def test_graph_replay_of_int8_and_packed_applies(torch, nx, nrhs, mode):
     with pinv.PoissonInverse.from_inverse(nx, nx, h, G) as op:
         if mode == "int8":
             op.quantize(24)
-        else:
+        elif mode != "fp64":
             op.prepare_split(mode)
         rho = dev(g.uniform(-1, 1, (nrhs, G.shape[0])))
         eager = op.apply(rho, mode, 16)
@@ -88,4 +89,7 @@ def test_graph_replay_of_int8_and_packed_applies(torch, nx, nrhs, mode):
             other = op.apply(dev(g.uniform(-1, 1, (nrhs, G.shape[0]))), mode, 16)
             torch.cuda.synchronize()
             del other
+        if mode == "fp64":
+            ref = apply.plain_apply(G, host(rho).T, h, None)
+            assert np.max(np.abs(host(u).T - ref)) <= 1e-12 * np.max(np.abs(ref))
         del graph
