@@ -196,13 +196,15 @@ bool int8_headroom_ok(int n, int S, int SR) {
   return (double)n * 16384.0 * pairs < 2147483648.0 && int8_total_ok(n, S, SR);
 }
 
-// The k split of one int8 apply of `variant`: where the tiles alone leave
-// workgroup slots empty (gemm_i8_split_plan), and wherever one int32
-// accumulation over k could overflow (the parts are added exactly in int64).
-void int8_split(pinv_op op, int SR, int Rpad, int variant, int* ksplit, int* kchunk) {
-  gemm_i8_split_plan(op->P, Rpad, variant, ksplit, kchunk);
+// The k split of one int8 apply of `variant`: where the tiles leave workgroup
+// slots empty (gemm_i8_split_plan: all tiles, or the last round's row tiles),
+// and wherever one int32 accumulation over k could overflow (then every tile
+// splits; the parts are added exactly in int64).
+void int8_split(pinv_op op, int SR, int Rpad, int variant, int* ksplit, int* kchunk, int* tail_rows) {
+  gemm_i8_split_plan(op->P, Rpad, variant, ksplit, kchunk, tail_rows);
   const int64_t klim = int8_k_limit(op->S, SR);
-  if (*kchunk > klim) {
+  if (op->P > klim && (*tail_rows > 0 || *kchunk > klim)) {
+    *tail_rows = 0;
     *kchunk = (int)klim;
     *ksplit = (int)((op->P + klim - 1) / klim);
   }
@@ -210,12 +212,12 @@ void int8_split(pinv_op op, int SR, int Rpad, int variant, int* ksplit, int* kch
 
 // The quantisation of the right-hand sides and the slice product of one int8
 // apply, on caller-provided scratch: Xq [SR][Rpad][P] int8, f [Rpad] int32
-// and, when ksplit > 1, part [ksplit][C][Rpad][P] int32.
+// and, when ksplit > 1, the partial sums (gemm_i8_part_bytes).
 // (trace = false: no timing events, for the allocation-free entry point)
 hipError_t int8_launch(pinv_op op, const int8_t* Q, const int32_t* row_exp, const int32_t* pre_exp, int SR,
                        const double* X, int64_t ldx, int nrhs, const double* w, double* U, int64_t ldu,
-                       int Rpad, int variant, int ksplit, int kchunk, int8_t* Xq, int32_t* f, int32_t* part,
-                       hipStream_t s, bool trace = true) {
+                       int Rpad, int variant, int ksplit, int kchunk, int tail_rows, int8_t* Xq, int32_t* f,
+                       int32_t* part, hipStream_t s, bool trace = true) {
   hipError_t e;
   {
     TraceScope ts(trace ? "quantize_cols" : nullptr, s);
@@ -237,6 +239,7 @@ hipError_t int8_launch(pinv_op op, const int8_t* Q, const int32_t* row_exp, cons
   a.ksplit = ksplit;
   a.kchunk = kchunk;
   a.part = ksplit > 1 ? part : nullptr;
+  a.tail_rows = ksplit > 1 ? tail_rows : 0;
   return launch_gemm_i8(a, s);
 }
 
@@ -245,16 +248,16 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
                    hipStream_t s) {
   const int Rpad = (nrhs + 127) / 128 * 128;
   const int variant = op->i8_variant[SR];
-  int ksplit = 1, kchunk = (int)op->P;
-  int8_split(op, SR, Rpad, variant, &ksplit, &kchunk);
+  int ksplit = 1, kchunk = (int)op->P, tail_rows = 0;
+  int8_split(op, SR, Rpad, variant, &ksplit, &kchunk, &tail_rows);
   const size_t xq_bytes = (size_t)SR * Rpad * op->P;
   const size_t f_bytes = ((size_t)Rpad * sizeof(int32_t) + 255) / 256 * 256;
-  const size_t part_bytes = ksplit > 1 ? (size_t)ksplit * (op->S + SR - 1) * Rpad * op->P * sizeof(int32_t) : 0;
+  const size_t part_bytes = gemm_i8_part_bytes(op->P, Rpad, variant, op->S + SR - 1, ksplit, tail_rows);
   void* scratch = nullptr;
   configure_pool_once();
   PINV_HIP_TRY(hipMallocAsync(&scratch, xq_bytes + f_bytes + part_bytes, s));
   const hipError_t e = int8_launch(op, Q, row_exp, pre_exp, SR, X, ldx, nrhs, w, U, ldu, Rpad, variant, ksplit, kchunk,
-                                   (int8_t*)scratch, (int32_t*)((char*)scratch + xq_bytes),
+                                   tail_rows, (int8_t*)scratch, (int32_t*)((char*)scratch + xq_bytes),
                                    (int32_t*)((char*)scratch + xq_bytes + f_bytes), s);
   hipError_t e2 = hipFreeAsync(scratch, s);
   if (e != hipSuccess) return pinv_hip_status(e);
@@ -1172,7 +1175,7 @@ int32_t pinv_apply_inverse_noalloc(pinv_op op, int32_t rho_bits, const double* r
   // nothing has to start at zero; k is not split (the integer class sums are
   // exact in any order, so the result equals pinv_apply_inverse's)
   const hipError_t e = int8_launch(op, op->Q, op->e, nullptr, SR, rho, ld_rho, nrhs, op->w, u, ld_u, Rpad,
-                                   op->i8_variant[SR], 1, (int)op->P, (int8_t*)ptr,
+                                   op->i8_variant[SR], 1, (int)op->P, 0, (int8_t*)ptr,
                                    (int32_t*)((char*)ptr + xq_bytes), nullptr, as_stream(stream), false);
   return pinv_hip_status(e);
 }
@@ -1360,16 +1363,15 @@ int32_t pinv_autotune_int8(pinv_op op, int32_t rho_bits, const double* rho, int6
   const int Rpad = (nrhs + 127) / 128 * 128;
   const int nv = gemm_i8_variants();
   // every variant is timed with the k split its applies would use
-  std::vector<int> ksplit(nv, 1), kchunk(nv, (int)op->P);
-  int kmax = 1;
+  std::vector<int> ksplit(nv, 1), kchunk(nv, (int)op->P), tail(nv, 0);
+  size_t part_bytes = 0;
   for (int v = 0; v < nv; ++v) {
-    int8_split(op, SR, Rpad, v, &ksplit[v], &kchunk[v]);
-    kmax = std::max(kmax, ksplit[v]);
+    int8_split(op, SR, Rpad, v, &ksplit[v], &kchunk[v], &tail[v]);
+    part_bytes = std::max(part_bytes, gemm_i8_part_bytes(op->P, Rpad, v, op->S + SR - 1, ksplit[v], tail[v]));
   }
   const size_t xq_bytes = (size_t)SR * Rpad * op->P;
   const size_t f_bytes = ((size_t)Rpad * sizeof(int32_t) + 255) / 256 * 256;
   const size_t u_bytes = ((size_t)nrhs * op->n * sizeof(double) + 255) / 256 * 256;
-  const size_t part_bytes = kmax > 1 ? (size_t)kmax * (op->S + SR - 1) * Rpad * op->P * sizeof(int32_t) : 0;
   char* buf = nullptr;
   PINV_HIP_TRY(hipMalloc(&buf, xq_bytes + f_bytes + u_bytes + part_bytes));
   int8_t* Xq = (int8_t*)buf;
@@ -1404,6 +1406,7 @@ int32_t pinv_autotune_int8(pinv_op op, int32_t rho_bits, const double* rho, int6
       a.ksplit = ksplit[v];
       a.kchunk = kchunk[v];
       a.part = ksplit[v] > 1 ? part : nullptr;
+      a.tail_rows = ksplit[v] > 1 ? tail[v] : 0;
       e = launch_gemm_i8(a, s);  // warm-up
       if (e == hipSuccess) e = hipEventRecord(ev0, s);
       for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_gemm_i8(a, s);

@@ -183,10 +183,18 @@ struct GemmI8Args {
   int variant;                     // kernel variant (0 .. gemm_i8_variants()-1)
   // split-K: ksplit > 1 workgroups share each tile, each over k in
   // [z*kchunk, (z+1)*kchunk) (kchunk a multiple of 128); their int32 class
-  // sums go to part[z][class][Rpad][P] and a second kernel adds them (exactly)
-  // and applies the epilogue
+  // sums go to part[z][class][Rpad][rows] (rows: the row tiles that run
+  // split, times the tile height) and a second kernel adds them (exactly) and
+  // applies the epilogue.  tail_rows > 0: only the last tail_rows row tiles
+  // run split (the rest, whole rounds of resident workgroups, unsplit in a
+  // launch of their own), so a short last round of tiles is spread over
+  // ksplit times as many workgroups.
   int ksplit, kchunk;
   int32_t* part;
+  int tail_rows;
+  // row tiles of one launch: tiles mt0 .. mt0 + mtiles - 1 (mtiles = 0: all
+  // from mt0 on); set by the launcher
+  int mt0, mtiles;
   // bytes of k per operand row (the row stride); 0 means P (int8 digits)
   int64_t kbytes;
 };
@@ -199,8 +207,11 @@ hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s);
 // them.  col_exp and row_exp are unused.
 hipError_t launch_gemm_bf16_parts(const GemmI8Args& a, double* partf, hipStream_t s);
 int gemm_i8_variants();
-// split plan for one launch of `variant` (ksplit = 1: none)
-void gemm_i8_split_plan(int64_t P, int Rpad, int variant, int* ksplit, int* kchunk);
+// split plan for one apply with `variant` (ksplit = 1: none; tail_rows > 0:
+// only the last tail_rows row tiles split, as in GemmI8Args)
+void gemm_i8_split_plan(int64_t P, int Rpad, int variant, int* ksplit, int* kchunk, int* tail_rows);
+// bytes of the int32 partial sums of such a plan (C classes)
+size_t gemm_i8_part_bytes(int64_t P, int Rpad, int variant, int C, int ksplit, int tail_rows);
 
 // Grouped int8 product: several operators (same S and SR) in one launch.
 // Group g owns global tiles [tile0, tile0 + tilesM*tilesN) of the launch, tiles

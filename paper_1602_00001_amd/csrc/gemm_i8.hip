@@ -153,7 +153,8 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
     tile -= groups[lo].tile0;
   }
   const int mt = tile / tN, nt = tile % tN;
-  const int m0 = mt * BM, n0 = nt * BN;
+  const int m0 = (a.mt0 + mt) * BM, n0 = nt * BN;
+  const int64_t prow = (int64_t)tilesM * BM;  // rows of the split-K partial sums
   const int64_t P = a.P;
   const int64_t KBY = a.kbytes ? a.kbytes : P;  // bytes of k per row
   // k steps of this workgroup: all of k, or its split's share
@@ -434,7 +435,8 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
           const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
           if (m >= a.n) continue;
 #pragma unroll
-          for (int c = 0; c < C; ++c) a.part[(((int64_t)z * C + c) * a.Rpad + n) * P + m] = acc[c][i][j][r];
+          for (int c = 0; c < C; ++c)
+            a.part[(((int64_t)z * C + c) * a.Rpad + n) * prow + (m - a.mt0 * BM)] = acc[c][i][j][r];
         }
       }
     return;
@@ -469,13 +471,15 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
 // Split-K epilogue: one thread per output (rows fastest); the splits' class
 // sums are added exactly in int64, then recombined and scaled as in the GEMM
 // epilogue (same operations, so the result is bit-identical).
-__global__ __launch_bounds__(256) void gemm_i8_splitk_epilogue(GemmI8Args a, int C) {
+// Rows m0 .. m0 + rows - 1 of the output, partial sums with row stride prow.
+__global__ __launch_bounds__(256) void gemm_i8_splitk_epilogue(GemmI8Args a, int C, int m0, int rows, int64_t prow) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)a.n * a.nrhs) return;
-  const int m = (int)(idx % a.n), n = (int)(idx / a.n);
+  if (idx >= (int64_t)rows * a.nrhs) return;
+  const int mr = (int)(idx % rows), n = (int)(idx / rows);
+  const int m = m0 + mr;
   int64_t cls[5] = {0, 0, 0, 0, 0};
   for (int z = 0; z < a.ksplit; ++z)
-    for (int c = 0; c < C; ++c) cls[c] += a.part[(((int64_t)z * C + c) * a.Rpad + n) * a.P + m];
+    for (int c = 0; c < C; ++c) cls[c] += a.part[(((int64_t)z * C + c) * a.Rpad + n) * prow + mr];
   int64_t v = cls[0];
   for (int c = 1; c < C; ++c) v = v * 256 + cls[c];
   const int em = a.row_exp ? a.row_exp[m] : 0;
@@ -542,7 +546,8 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int
     tile -= groups[lo].tile0;
   }
   const int mt = tile / tN, nt = tile % tN;
-  const int m0 = mt * 128, n0 = nt * 128;
+  const int m0 = (a.mt0 + mt) * 128, n0 = nt * 128;
+  const int64_t prow = (int64_t)tilesM * 128;  // rows of the split-K partial sums
   const int64_t P = a.P;
   const int64_t KBY = a.kbytes ? a.kbytes : P;
   const int z = blockIdx.y;
@@ -674,7 +679,8 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int
           const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
           if (m >= a.n) continue;
 #pragma unroll
-          for (int c = 0; c < C; ++c) a.part[(((int64_t)z * C + c) * a.Rpad + n) * P + m] = acc[c][i][j][r];
+          for (int c = 0; c < C; ++c)
+            a.part[(((int64_t)z * C + c) * a.Rpad + n) * prow + (m - a.mt0 * 128)] = acc[c][i][j][r];
         }
       }
     return;
@@ -733,7 +739,7 @@ hipError_t launch_w4(const GemmI8Args& a, const GemmI8Group* groups, int ngroups
     return launch_v<S, SR, V - 5>(a, groups, ngroups, total, s);
   } else {
     constexpr int MAP = V - 13;
-    const int tilesM = groups ? 0 : (int)(a.P / 128), tilesN = groups ? 0 : a.Rpad / BN;
+    const int tilesM = groups ? 0 : (a.mtiles ? a.mtiles : (int)(a.P / 128) - a.mt0), tilesN = groups ? 0 : a.Rpad / BN;
     const int T = groups ? total : tilesM * tilesN;
     const int grid = MAP == 0 ? ((T + 7) / 8) * 8 : T;
     const int zs = (!groups && a.ksplit > 1) ? a.ksplit : 1;
@@ -750,7 +756,7 @@ hipError_t launch_v(const GemmI8Args& a, const GemmI8Group* groups, int ngroups,
   constexpr int MAP = V == 12 ? 0 : V >= 10 ? V - 10 : V >= 8 ? V - 8 : (V / 2) % 2;
   constexpr int PF = V == 12 ? 3 : V >= 10 ? 1 : V >= 8 ? 2 : V / 4;
   using K = Cfg<S, SR, BKV, NWV>;
-  const int tilesM = groups ? 0 : (int)(a.P / K::BM), tilesN = groups ? 0 : a.Rpad / BN;
+  const int tilesM = groups ? 0 : (a.mtiles ? a.mtiles : (int)(a.P / K::BM) - a.mt0), tilesN = groups ? 0 : a.Rpad / BN;
   const int T = groups ? total : tilesM * tilesN;
   const int grid = MAP == 0 ? ((T + 7) / 8) * 8 : T;
   const int zs = (!groups && a.ksplit > 1) ? a.ksplit : 1;
@@ -802,39 +808,91 @@ int gemm_i8_variants() { return 15; }
 
 int gemm_i8_tile_rows(int variant) { return (variant == 10 || variant == 11) ? 64 : 128; }
 
-void gemm_i8_split_plan(int64_t P, int Rpad, int variant, int* ksplit, int* kchunk) {
-  // Split k only when the tiles alone leave resident workgroup slots empty
-  // (T < W): z = min(W / T, 4), with at least 2048 of k per split.  (With more
-  // tiles than slots, splitting the last round measured no gain: the product
-  // is then limited by the operand stream into LDS, not by idle units.)
-  const int rows = gemm_i8_tile_rows(variant);
-  const int T = (int)(P / rows) * (Rpad / BN);
-  const int W = rows == 128 ? 256 : 512;  // workgroups resident at once
-  int zz = T > 0 ? W / T : 1;
-  if (zz > 4) zz = 4;
-  while (zz > 1 && P / zz < 2048) --zz;
-  if (zz < 2) {
-    *ksplit = 1;
-    *kchunk = (int)P;
-    return;
-  }
-  int64_t chunk = (P + zz - 1) / zz;
+namespace {
+
+// k split into z parts of whole 128-byte steps
+void split_k(int64_t P, int z, int* ksplit, int* kchunk) {
+  int64_t chunk = (P + z - 1) / z;
   chunk = (chunk + 127) / 128 * 128;
   *ksplit = (int)((P + chunk - 1) / chunk);
   *kchunk = (int)chunk;
 }
 
-hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s) {
-  if (a.nrhs <= 0) return hipSuccess;
-  if (a.P % 256 != 0 || a.Rpad % BN != 0) return hipErrorInvalidValue;  // tiles cover P and Rpad exactly
-  const bool split = a.ksplit > 1;
-  if (split && (!a.part || a.kchunk <= 0 || a.kchunk % 128 != 0 || (int64_t)a.kchunk * (a.ksplit - 1) >= a.P))
+}  // namespace
+
+void gemm_i8_split_plan(int64_t P, int Rpad, int variant, int* ksplit, int* kchunk, int* tail_rows) {
+  // W workgroups are resident at once.  With fewer tiles than that (T < W),
+  // every tile splits k: z = min(W / T, 4).  With more, the tiles run in
+  // rounds of W; when the last round is at most half full, only its row tiles
+  // split (z = min(W / tail tiles, 4)), so that it takes about 1/z of a
+  // round instead of a whole one.  At least 2048 of k per split.  (A last
+  // round more than half full is not split: splitting it measured no gain, the
+  // product being limited by the operand stream into LDS rather than by idle
+  // units.)
+  const int rows = gemm_i8_tile_rows(variant);
+  const int tM = (int)(P / rows), tN = Rpad / BN;
+  const int T = tM * tN;
+  const int W = rows == 128 ? 256 : 512;
+  *ksplit = 1;
+  *kchunk = (int)P;
+  *tail_rows = 0;
+  if (T <= 0) return;
+  int zz = 1, trows = 0;
+  if (T < W) {
+    zz = W / T;
+  } else if (T % W != 0 && T % W <= W / 2) {
+    const int main_rows = (T / W) * W / tN;  // row tiles of the whole rounds
+    trows = tM - main_rows;
+    zz = W / (trows * tN);
+  }
+  if (zz > 4) zz = 4;
+  while (zz > 1 && P / zz < 2048) --zz;
+  if (zz < 2) return;
+  split_k(P, zz, ksplit, kchunk);
+  *tail_rows = trows;
+}
+
+size_t gemm_i8_part_bytes(int64_t P, int Rpad, int variant, int C, int ksplit, int tail_rows) {
+  if (ksplit <= 1) return 0;
+  const int64_t rows = tail_rows > 0 ? (int64_t)tail_rows * gemm_i8_tile_rows(variant) : P;
+  return (size_t)ksplit * C * Rpad * rows * sizeof(int32_t);
+}
+
+hipError_t launch_gemm_i8(const GemmI8Args& a_in, hipStream_t s) {
+  if (a_in.nrhs <= 0) return hipSuccess;
+  if (a_in.P % 256 != 0 || a_in.Rpad % BN != 0) return hipErrorInvalidValue;  // tiles cover P and Rpad exactly
+  const bool split = a_in.ksplit > 1;
+  if (split && (!a_in.part || a_in.kchunk <= 0 || a_in.kchunk % 128 != 0 ||
+                (int64_t)a_in.kchunk * (a_in.ksplit - 1) >= a_in.P))
     return hipErrorInvalidValue;
-  hipError_t e = dispatch(a.S, a.SR, a, a.variant, nullptr, 0, 0, s);
+  const int rows = gemm_i8_tile_rows(a_in.variant);
+  const int tM = (int)(a_in.P / rows);
+  if (a_in.tail_rows < 0 || a_in.tail_rows >= tM) return hipErrorInvalidValue;
+  GemmI8Args a = a_in;
+  a.mt0 = 0;
+  a.mtiles = 0;
+  hipError_t e;
+  if (split && a_in.tail_rows > 0) {
+    // the whole rounds unsplit, then the last row tiles split
+    GemmI8Args m = a;
+    m.ksplit = 1;
+    m.kchunk = (int)a.P;
+    m.part = nullptr;
+    m.mtiles = tM - a_in.tail_rows;
+    e = dispatch(m.S, m.SR, m, m.variant, nullptr, 0, 0, s);
+    if (e != hipSuccess) return e;
+    a.mt0 = tM - a_in.tail_rows;
+    a.mtiles = a_in.tail_rows;
+  }
+  e = dispatch(a.S, a.SR, a, a.variant, nullptr, 0, 0, s);
   if (e != hipSuccess || !split) return e;
-  const int64_t outs = (int64_t)a.n * a.nrhs;
+  const int m0 = a.mt0 * rows;
+  const int64_t prow = (int64_t)(tM - a.mt0) * rows;
+  const int out_rows = a.n - m0;
+  if (out_rows <= 0) return hipSuccess;
+  const int64_t outs = (int64_t)out_rows * a.nrhs;
   hipLaunchKernelGGL(gemm_i8_splitk_epilogue, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s, a,
-                     a.S + a.SR - 1);
+                     a.S + a.SR - 1, m0, out_rows, prow);
   return hipGetLastError();
 }
 

@@ -83,3 +83,38 @@ def test_autotune_picks_a_variant_and_keeps_results(torch, pinv):
             assert ei.value.status == pinv.E_INVALID_ARG
         with pytest.raises(pinv.PinvError):
             op.set_int8_variant(16, pinv.int8_variants())
+
+
+def test_split_of_the_last_round_of_tiles(torch, pinv):
+    """4096 unknowns x 1100 right-hand sides: 288 tiles of 128 x 128 for 256
+    resident workgroups (576 of 64 x 128 for 512), so the last round's row
+    tiles run split over k and the rest unsplit.  Every variant gives the
+    allocation-free apply's result (which never splits k) bit for bit, and
+    sampled columns of it and of the adjoint the oracle's integer result."""
+    nx = ny = 66
+    g = np.random.default_rng(5)
+    h = 1.0 / (nx - 1)
+    ub = g.standard_normal((ny, nx))
+    G, w, _ = oracle_inverse(nx, ny, workloads.random_eps(nx, ny, g), ub)
+    N = G.shape[0]
+    R = 1100
+    rho = g.uniform(-1, 1, (R, N))
+    gv = g.uniform(-1, 1, (R, N))
+    cols = np.sort(g.choice(R, 8, replace=False))
+    ref, _, _ = oracle_int8(G, 3, rho[cols].T, 2, h, w)
+    qG, e = quant.quantize_rows(G, 3)
+    qg, f = quant.quantize_cols(gv[cols].T, 2, pre_exponent=e)
+    ref_adj, _ = apply.integer_apply(qG.T, e, 3, qg, f, 2, h, None, row_exponent=False)
+    with pinv.PoissonInverse.from_inverse(nx, ny, h, G, None, ub, w) as op:
+        op.quantize(24)
+        x, xg = dev(rho), dev(gv)
+        announce("int8 4096 x 1100, unsplit reference (allocation-free apply)")
+        unsplit = host(op.apply_noalloc(x, 16))
+        assert np.array_equal(unsplit[cols].T, ref)
+        for v in range(pinv.int8_variants()):
+            announce(f"int8 variant {v}, 4096 x 1100 (last round split over k)")
+            op.set_int8_variant(16, v)
+            u = host(op.apply(x, "int8", 16))
+            assert np.array_equal(u, unsplit), v
+            lam = host(op.apply_adjoint(xg, "int8", 16))
+            assert np.array_equal(lam[cols].T, ref_adj), v
