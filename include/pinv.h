@@ -415,7 +415,14 @@ int32_t pinv_get_info(pinv_op op, pinv_info* info);
  *   the fastest variant for the op and writes its id to *best (may be NULL) and
  *   the mean milliseconds per launch of variant v to variant_ms[v] for
  *   v < n_ms (variant_ms may be NULL).  Synchronises the stream.
- *   E_STATE if the op is not quantised, E_INVALID_ARG for bad sizes. */
+ *   E_STATE if the op is not quantised, E_INVALID_ARG for bad sizes.
+ *   With the environment variable PINV_AUTOTUNE_CACHE naming a file, a choice
+ *   stored there for the same device kind (architecture name and compute-unit
+ *   count), unknowns, digit counts and padded right-hand-side count is taken
+ *   without timing (variant_ms[v] is then the stored time for the chosen
+ *   variant and -1 for the others); otherwise the choice is appended to the
+ *   file as one text line "int8 <arch> <CUs> <N> <S> <SR> <Rpad> <variant>
+ *   <ms>" (later lines win; lines that do not parse are ignored). */
 int32_t pinv_int8_variants(void);
 int32_t pinv_set_int8_variant(pinv_op op, int32_t rho_bits, int32_t variant);
 int32_t pinv_autotune_int8(pinv_op op, int32_t rho_bits, const double* rho, int64_t ld_rho,

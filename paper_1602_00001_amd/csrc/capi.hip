@@ -1362,6 +1362,21 @@ int32_t pinv_autotune_int8(pinv_op op, int32_t rho_bits, const double* rho, int6
   hipStream_t s = as_stream(stream);
   const int Rpad = (nrhs + 127) / 128 * 128;
   const int nv = gemm_i8_variants();
+  // a stored choice for this device kind and problem, if a cache file is named
+  const char* cache = std::getenv("PINV_AUTOTUNE_CACHE");
+  std::string dkey;
+  if (cache && *cache) {
+    dkey = tune_device_key(op->device);
+    int v = 0;
+    double vms = 0.0;
+    if (tune_cache_lookup(cache, dkey, op->n, op->S, SR, Rpad, nv, &v, &vms)) {
+      for (int i = 0; i < n_ms; ++i) variant_ms[i] = i == v ? vms : -1.0;
+      op->i8_variant[SR] = v;
+      if (best) *best = v;
+      pinv_log("autotune_int8: n=%d S=%d SR=%d Rpad=%d: variant %d from %s", op->n, op->S, SR, Rpad, v, cache);
+      return PINV_OK;
+    }
+  }
   // every variant is timed with the k split its applies would use
   std::vector<int> ksplit(nv, 1), kchunk(nv, (int)op->P), tail(nv, 0);
   size_t part_bytes = 0;
@@ -1432,6 +1447,7 @@ int32_t pinv_autotune_int8(pinv_op op, int32_t rho_bits, const double* rho, int6
   if (e != hipSuccess) return pinv_hip_status(e);
   op->i8_variant[SR] = pick;
   if (best) *best = pick;
+  if (cache && *cache) tune_cache_store(cache, dkey, op->n, op->S, SR, Rpad, pick, t[pick]);
   return PINV_OK;
 }
 

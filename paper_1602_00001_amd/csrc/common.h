@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <string>
 #include <cstdint>
 #include <cstddef>
 
@@ -72,6 +74,15 @@ struct pinv_op_s {
 
 int32_t pinv_hip_status(hipError_t e);
 void pinv_log(const char* fmt, ...);
+
+// Autotune cache (file named by PINV_AUTOTUNE_CACHE): device kind key
+// ("<arch> <compute units>", empty if unknown), lookup of a stored int8
+// variant choice, and appending one.
+std::string tune_device_key(int device);
+bool tune_cache_lookup(const char* path, const std::string& dkey, int n, int S, int SR, int Rpad, int nvariants,
+                       int* variant, double* ms);
+void tune_cache_store(const char* path, const std::string& dkey, int n, int S, int SR, int Rpad, int variant,
+                      double ms);
 
 // Records a pair of events around the launches in its scope when tracing is
 // enabled (pinv_trace_enable) and name is not null; a no-op otherwise.

@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libpinv.so")
+# PINV_LIBRARY: another build of the same library (the sanitized host build,
+# _lib/libpinv_san.so); the default is the release build
+LIB_PATH = os.environ.get("PINV_LIBRARY") or os.path.join(_HERE, "_lib", "libpinv.so")
 
 OK, E_INVALID_ARG, E_NOT_SPD, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8": 4, "fp64_sym": 5, "fix16_tile": 6}
@@ -407,7 +409,10 @@ class PoissonInverse:
         """Time every int8 kernel variant on this op and keep the fastest.
         rho: representative right-hand sides ([nrhs, N] float64 CUDA tensor),
         or None for random digits of ``nrhs`` columns.
-        Returns (best variant id, list of mean ms per launch)."""
+        Returns (best variant id, list of mean ms per launch).  With
+        PINV_AUTOTUNE_CACHE naming a file, a stored choice is taken without
+        timing (the list then holds its stored time and -1 elsewhere) and a new
+        choice is appended there."""
         if rho is not None:
             p, ld, R = _vectors(rho, self.n, "rho")
         else:

@@ -118,3 +118,42 @@ def test_split_of_the_last_round_of_tiles(torch, pinv):
             assert np.array_equal(u, unsplit), v
             lam = host(op.apply_adjoint(xg, "int8", 16))
             assert np.array_equal(lam[cols].T, ref_adj), v
+
+
+def test_autotune_cache_file(torch, pinv, tmp_path, monkeypatch):
+    """PINV_AUTOTUNE_CACHE: the first tuning appends its choice; a second op
+    of the same size takes it from the file without timing (the others'
+    times reported as -1); another right-hand-side count is tuned afresh;
+    results stay the oracle's."""
+    nx = ny = 40
+    g = np.random.default_rng(9)
+    h = 1.0 / (nx - 1)
+    G, _, _ = oracle_inverse(nx, ny)
+    rho = g.uniform(-1, 1, (150, G.shape[0]))
+    ref, _, _ = oracle_int8(G, 2, rho.T, 2, h)
+    cache = tmp_path / "tune.txt"
+    cache.write_text("a line that is not an entry\nint8 short\n")
+    monkeypatch.setenv("PINV_AUTOTUNE_CACHE", str(cache))
+    nv = pinv.int8_variants()
+    with pinv.PoissonInverse.from_inverse(nx, ny, h, G) as op:
+        op.quantize(16)
+        announce("autotune with an empty cache file")
+        best, ms = op.autotune_int8(16, nrhs=150, reps=2)
+        assert all(t > 0 for t in ms) and ms[best] == min(ms)
+        lines = cache.read_text().splitlines()
+        entry = lines[-1].split()
+        assert len(lines) == 3 and entry[0] == "int8" and entry[3:8] == [str(G.shape[0]), "2", "2", "256", str(best)]
+    with pinv.PoissonInverse.from_inverse(nx, ny, h, G) as op:
+        op.quantize(16)
+        announce("autotune served from the cache file")
+        best2, ms2 = op.autotune_int8(16, nrhs=150, reps=2)
+        assert best2 == best
+        assert ms2[best] > 0 and all(t == -1.0 for v, t in enumerate(ms2) if v != best)
+        assert len(cache.read_text().splitlines()) == 3
+        u = host(op.apply(dev(rho), "int8", 16))
+        assert np.array_equal(u.T, ref)
+        announce("autotune for another right-hand-side count")
+        _, ms3 = op.autotune_int8(16, nrhs=300, reps=1)
+        assert all(t > 0 for t in ms3)
+        assert len(cache.read_text().splitlines()) == 4
+    assert nv == len(ms)
