@@ -460,7 +460,7 @@ def bench_poisson3d_26(args):
     t_build = time.perf_counter() - t0
     op.quantize(24)
     rho = torch.from_numpy(workloads.uniform_rhs_n(N, R, workloads.rng(6, 0))).cuda()
-    variant, _ = _autotune(op, args, 16, rho)
+    variant, variant_ms = _autotune(op, args, 16, rho)
     u8 = torch.empty_like(rho)
     u64 = torch.empty_like(rho)
     for _ in range(args.warmup):
@@ -493,6 +493,7 @@ def bench_poisson3d_26(args):
                              "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach64 / PEAK_FP64_TFLOPS,
                              "avg_launch_ms": kms64}
     line["setup_s"] = {"build_inverse": t_build}
+    line["int8_variant"] = {"chosen": variant, "ms_per_launch": variant_ms}
     return line
 
 
@@ -649,7 +650,7 @@ def bench_grad_192(args):
     t_build = time.perf_counter() - t0
     op.quantize(16, keep_fp64=False)
     rho = torch.from_numpy(wl["rho"]).cuda()
-    variant, _ = _autotune(op, args, 16, rho)
+    variant, variant_ms = _autotune(op, args, 16, rho)
     idx = torch.from_numpy(wl["sample"]).cuda()
     d = torch.randn(R, idx.numel(), dtype=torch.float64, device="cuda") * 1e-3
     u = torch.empty_like(rho)
@@ -687,6 +688,7 @@ def bench_grad_192(args):
     line["grad_eps_avg_ms"] = ems / max(ecnt, 1)
     line["quantize_avg_ms"] = qms / max(qcnt, 1)
     line["setup_s"] = {"build_inverse": t_build}
+    line["int8_variant"] = {"chosen": variant, "ms_per_launch": variant_ms}
     return line
 
 
