@@ -264,12 +264,29 @@ ApplyF64Plan apply_f64_plan(int M, int N, int K) {
   p.tilesN = (N + FBN - 1) / FBN;
   p.Npad = p.tilesN * FBN;
   p.ldp = ((int64_t)K + 31) / 32 * 32;
-  // one workgroup per compute unit: split k when the tiles leave units idle,
-  // at least 512 of k per split, chunks of whole 16-wide steps
+  // One workgroup per compute unit, so the tiles run in rounds of 256.  k is
+  // split z ways (at least 512 of k per split, at most 16 splits, chunks of
+  // whole 16-wide steps) where that shortens the estimate
+  //   ceil(T z / 256) / z   rounds of whole-tile time
+  //   + (z M N 16 bytes of partial sums written and read at ~4 TB/s + 10 us
+  //      for the adding kernel) / whole-tile time,
+  // whole-tile time being 2 * 256 * 128 * K flops at 90% of a compute unit's
+  // share of the FP64 matrix peak: a grid smaller than the chip, or a last
+  // round mostly empty (24^3 unknowns x 1024: 432 tiles), is then spread over
+  // more workgroups, while 504 tiles (two nearly full rounds) stay unsplit.
   const int T = p.tilesM * p.tilesN;
-  int z = 256 / (T > 0 ? T : 1);
-  if (z > K / 512) z = K / 512;
-  if (z > 16) z = 16;
+  const double t_tile = 2.0 * FBM * FBN * (double)K / (0.9 * 78.6e12 / 256.0);
+  int z = 1;
+  double best = 1e300;
+  for (int c = 1; c <= 16; ++c) {
+    if (c > 1 && K / c < 512) break;
+    const double rounds = (double)(((int64_t)T * c + 255) / 256) / c;
+    const double extra = c > 1 ? ((double)c * M * N * 16.0 / 4e12 + 10e-6) / t_tile : 0.0;
+    if (rounds + extra < best * 0.98) {
+      best = rounds + extra;
+      z = c;
+    }
+  }
   p.ksplit = 1;
   p.kchunk = K;
   if (z >= 2) {
