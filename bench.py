@@ -522,7 +522,7 @@ def bench_gemv_128(args):
         op.apply(rho, "fp64_sym", out=us)
         op.apply(rho, "fix16_tile", out=ut)
     torch.cuda.synchronize()
-    for k in ("gemv_f64", "gemm_i8", "quantize_cols", "gemv_sym", "gemv_tile16"):
+    for k in ("gemv_f64", "gemv_i8", "quantize_cols", "gemv_sym", "gemv_tile16"):
         pinv.trace_read(k)
     pinv.trace_enable(True)
     dt64 = _timed(lambda: op.apply(rho, "fp64", out=u64), args.steps, 0)
@@ -531,7 +531,7 @@ def bench_gemv_128(args):
     dtt = _timed(lambda: op.apply(rho, "fix16_tile", out=ut), args.steps, 0)
     pinv.trace_enable(False)
     fms, fcnt = pinv.trace_read("gemv_f64")
-    ims, icnt = pinv.trace_read("gemm_i8")
+    ims, icnt = pinv.trace_read("gemv_i8")
     sms, scnt = pinv.trace_read("gemv_sym")
     tms, tcnt = pinv.trace_read("gemv_tile16")
     err = float(torch.linalg.vector_norm(u8 - u64) / torch.linalg.vector_norm(u64))
@@ -564,7 +564,7 @@ def bench_gemv_128(args):
                                        "avg_launch_ms": kt,
                                        "bytes": "int16 entries + tile exponents + rho read + u written"}}
     line["int8"] = {"value": 1.0 / dt8, "unit": "solves/s", "ms_per_step": dt8 * 1e3, "rel_l2_vs_fp64": err,
-                    "roofline": {"kernel": "gemm_i8_kernel<3,2> (+ split-K epilogue)", "bound": "hbm",
+                    "roofline": {"kernel": "gemv_i8_kernel<3,2,1>", "bound": "hbm",
                                  "achieved": gbs8, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs8 / PEAK_HBM_GBS,
                                  "avg_launch_ms": k8}}
     return line

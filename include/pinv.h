@@ -432,8 +432,9 @@ int32_t pinv_autotune_int8(pinv_op op, int32_t rho_bits, const double* rho, int6
 /* Kernel tracing (profiling aid).  While enabled, every kernel launched by the
  * library is bracketed by a pair of HIP events recorded on the same stream.
  * pinv_trace_read sums the elapsed times of the recorded launches of one
- * kernel family -- "gemm_i8", "quantize_cols", "gemm_f64", "gemv_f64",
- * "gemm_split", "pack_split", "grad_eps" -- waiting for their events, and
+ * kernel family -- "gemm_i8", "gemv_i8" (the int8 apply for at most 4
+ * right-hand sides), "quantize_cols", "gemm_f64", "gemv_f64", "gemv_sym",
+ * "gemv_tile16", "gemm_split", "grad_eps" -- waiting for their events, and
  * forgets them; total_ms and launches may be NULL.  pinv_trace_enable(0)
  * stops recording (recorded launches stay readable).  Thread-safe. */
 int32_t pinv_trace_enable(int32_t on);

@@ -224,7 +224,10 @@ hipError_t int8_launch(pinv_op op, const int8_t* Q, const int32_t* row_exp, cons
     e = launch_quantize_cols(X, ldx, nullptr, op->n, nrhs, Rpad, SR, op->P, pre_exp, Xq, f, s);
   }
   if (e != hipSuccess) return e;
-  TraceScope ts(trace ? "gemm_i8" : nullptr, s);
+  // few right-hand sides: a pass over the digit planes (HBM-bound), else the
+  // tiled matrix-core product
+  const bool gemv = nrhs <= GEMV_I8_MAX_RHS;
+  TraceScope ts(trace ? (gemv ? "gemv_i8" : "gemm_i8") : nullptr, s);
   GemmI8Args a{};
   a.Q = Q; a.S = op->S;
   a.X = Xq; a.SR = SR;
@@ -240,7 +243,7 @@ hipError_t int8_launch(pinv_op op, const int8_t* Q, const int32_t* row_exp, cons
   a.kchunk = kchunk;
   a.part = ksplit > 1 ? part : nullptr;
   a.tail_rows = ksplit > 1 ? tail_rows : 0;
-  return launch_gemm_i8(a, s);
+  return gemv ? launch_gemv_i8(a, s) : launch_gemm_i8(a, s);
 }
 
 int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const int32_t* pre_exp, int SR,
@@ -249,7 +252,8 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
   const int Rpad = (nrhs + 127) / 128 * 128;
   const int variant = op->i8_variant[SR];
   int ksplit = 1, kchunk = (int)op->P, tail_rows = 0;
-  int8_split(op, SR, Rpad, variant, &ksplit, &kchunk, &tail_rows);
+  // (the few-right-hand-side pass adds its lanes' class sums in int64: no split)
+  if (nrhs > GEMV_I8_MAX_RHS) int8_split(op, SR, Rpad, variant, &ksplit, &kchunk, &tail_rows);
   const size_t xq_bytes = (size_t)SR * Rpad * op->P;
   const size_t f_bytes = ((size_t)Rpad * sizeof(int32_t) + 255) / 256 * 256;
   const size_t part_bytes = gemm_i8_part_bytes(op->P, Rpad, variant, op->S + SR - 1, ksplit, tail_rows);

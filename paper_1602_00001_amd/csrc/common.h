@@ -210,6 +210,11 @@ struct GemmI8Args {
   int64_t kbytes;
 };
 hipError_t launch_gemm_i8(const GemmI8Args& a, hipStream_t s);
+// The same product for at most GEMV_I8_MAX_RHS right-hand sides as one pass
+// over the digit planes (one wave per row; no k split needed, ksplit and part
+// are ignored; ucols must be null).  Bit-identical to launch_gemm_i8.
+constexpr int GEMV_I8_MAX_RHS = 4;
+hipError_t launch_gemv_i8(const GemmI8Args& a, hipStream_t s);
 // The same tiled product over bfloat16 split parts (G parts in Q as
 // [S][P][P] bf16, right-hand-side parts in X as [S][Rpad][P] bf16, kbytes =
 // 2P): products of parts p + q <= S-1 summed in two FP32 accumulators

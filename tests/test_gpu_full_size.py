@@ -46,11 +46,15 @@ def test_quant_128_int8_bit_exact_and_accuracy(torch, pinv, case):
         op.quantize(24)
         u_int8 = host(op.apply(dev(rho), "int8", 16))
         u_fp64 = host(op.apply(dev(rho), "fp64"))
+        # at most 4 right-hand sides the apply is a pass over the digit planes
+        # (one wave per row), not the tiled product: the same integers
+        few = host(op.apply(dev(rho[pick[:3]]), "int8", 16))
     # integer path: bit-exact on the sampled right-hand sides
     qG, e = quant.quantize_rows(G, 3)
     qR, f = quant.quantize_cols(rho[pick].T, 2)
     ref_int, _ = apply.integer_apply(qG, e, 3, qR, f, 2, h)
     assert np.array_equal(u_int8[pick].T, ref_int)
+    assert np.array_equal(few.T, ref_int[:, :3])
     # FP64 path: within 1e-12 of the oracle's FP64 product
     ref64 = apply.plain_apply(G, rho[pick].T, h)
     assert np.max(metrics.rel_l2_per_rhs(u_fp64[pick].T, ref64)) <= 1e-12

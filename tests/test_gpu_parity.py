@@ -155,12 +155,13 @@ def test_apply_with_a_very_large_row_stride(torch, pinv):
 
 
 @pytest.mark.parametrize("nx,ny", [(3, 3), (12, 9), (40, 33)])
-@pytest.mark.parametrize("nrhs", [1, 2, 7, 16, 17])
-@pytest.mark.parametrize("bits,rho_bits", [(24, 16), (16, 16), (8, 24)])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 4, 7, 16, 17])
+@pytest.mark.parametrize("bits,rho_bits", [(24, 16), (16, 16), (8, 24), (24, 24)])
 def test_int8_few_rhs_bit_exact(torch, pinv, nx, ny, nrhs, bits, rho_bits):
-    """Few right-hand sides (one padded 128-column tile, k split over several
-    workgroups): forward and adjoint bit for bit against the oracle's integer
-    product."""
+    """Few right-hand sides: at most 4 run as one pass over the digit planes
+    (one wave per row, 1 KB blocks of k, a 256-byte tail at 40 x 33), more as
+    one padded 128-column tile with k split over several workgroups.  Forward
+    and adjoint bit for bit against the oracle's integer product."""
     announce(f"int8 few rhs nx={nx} ny={ny} nrhs={nrhs} bits={bits} rho_bits={rho_bits}")
     g = np.random.default_rng(nx * nrhs + bits)
     ub = g.standard_normal((ny, nx))
