@@ -80,6 +80,7 @@ extern "C" {
 #define PINV_E_HIP           -4  /* a HIP runtime call failed                  */
 #define PINV_E_UNSUPPORTED   -5  /* size beyond the integer headroom limits, or an operation the op does not support */
 #define PINV_E_STATE         -6  /* representation needed by the call missing  */
+#define PINV_E_IO            -7  /* a file could not be opened, read or written */
 
 /* ---- enums -------------------------------------------------------------- */
 #define PINV_FP64    0
@@ -242,6 +243,23 @@ int32_t pinv_quantize_inverse(pinv_op op, int32_t bits, int32_t scale_mode,
  * exactly the transposes of G's): 4 N (64 ceil(N/64)) bytes in all.  Applies
  * and adjoints in this mode allocate nothing. */
 int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream);
+
+/* Checkpoint (not in the paper, whose method precomputes once and applies at
+ * every time moment): pinv_save writes the op's grid description and what it
+ * holds of {FP64 G, the int8 digit slices with their row exponents, the lift
+ * w, the Dirichlet data, a non-uniform grid's node coordinates} and its int8
+ * variant choices to a file (host byte order; about 8 N^2 bytes for G and
+ * S P^2 for the slices, P = 256 ceil(N / 256)).  Split-precision, packed and
+ * tile-scaled copies are not written (pinv_prepare_split rebuilds them from
+ * G).  pinv_load creates an op on the current device from such a file without
+ * the O(N^3) build, bit for bit the same data (the transposed digit planes of
+ * the adjoint are formed on the device).  The header and the file's length
+ * are checked before anything is allocated: PINV_E_INVALID_ARG for a file
+ * that is not such a checkpoint, PINV_E_IO if it cannot be opened, read or
+ * written, PINV_E_STATE (save) for an op holding neither G nor slices.
+ * Synchronous. */
+int32_t pinv_save(pinv_op op, const char* path, void* stream);
+int32_t pinv_load(const char* path, void* stream, pinv_op* out);
 
 /* Export the 16-bit tile-scaled copy: q (host [N][N] int16, row-major) and
  * the tile exponents (host [ceil(N/64)][ceil(N/64)] int32, row-major).  Either

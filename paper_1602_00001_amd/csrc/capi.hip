@@ -680,6 +680,7 @@ const char* pinv_status_string(int32_t st) {
     case PINV_E_HIP: return "HIP runtime error";
     case PINV_E_UNSUPPORTED: return "unsupported size or mode";
     case PINV_E_STATE: return "the op does not hold the representation this call needs";
+    case PINV_E_IO: return "file could not be opened, read or written";
     default: return "unknown status";
   }
 }
@@ -1082,6 +1083,219 @@ int32_t pinv_export_quantized(pinv_op op, int8_t* slices_host, int32_t* exponent
   if (exponents_host)
     PINV_HIP_TRY(hipMemcpyAsync(exponents_host, op->e, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   PINV_HIP_TRY(hipStreamSynchronize(s));
+  return PINV_OK;
+}
+
+// ---- checkpoint: save / load an op ------------------------------------------
+namespace {
+
+// File layout (host byte order): the header, then, each present according to
+// the flags, node coordinates x [nx] and y [ny] (non-uniform grids), the
+// Dirichlet data [nodes], the lift w [n], G [n][n] row-major FP64, the row
+// exponents [P] int32 and the digit planes [S][P][P] int8.
+constexpr char kMagic[8] = {'P', 'I', 'N', 'V', 'O', 'P', '0', '1'};
+enum : int32_t { kHasG = 1, kHasW = 2, kHasUb = 4, kHasQ = 8, kHasXY = 16 };
+
+struct FileHeader {
+  char magic[8];
+  int32_t version;
+  int32_t nx, ny, nz;
+  int32_t general, beta;
+  int32_t n;
+  int32_t flags;
+  int32_t S;
+  int32_t i8_variant[4];
+  int32_t _pad;
+  int64_t P;
+  double h;
+};
+
+int64_t op_nodes(int nx, int ny, int nz) { return (int64_t)nx * ny * (nz > 0 ? nz : 1); }
+
+// bytes of the payload that the header announces
+int64_t payload_bytes(const FileHeader& f) {
+  int64_t b = 0;
+  if (f.flags & kHasXY) b += (int64_t)(f.nx + f.ny) * 8;
+  if (f.flags & kHasUb) b += op_nodes(f.nx, f.ny, f.nz) * 8;
+  if (f.flags & kHasW) b += (int64_t)f.n * 8;
+  if (f.flags & kHasG) b += (int64_t)f.n * f.n * 8;
+  if (f.flags & kHasQ) b += f.P * 4 + (int64_t)f.S * f.P * f.P;
+  return b;
+}
+
+struct File {
+  FILE* f = nullptr;
+  ~File() {
+    if (f) std::fclose(f);
+  }
+};
+
+constexpr size_t kChunk = (size_t)64 << 20;
+
+// device -> file in chunks of whole rows (rows of `width` bytes, `pitch` apart)
+int32_t write_rows(FILE* f, const void* dev, size_t pitch, size_t width, int64_t rows, std::vector<char>& buf,
+                   hipStream_t s) {
+  const int64_t per = std::max<int64_t>(1, (int64_t)(kChunk / width));
+  for (int64_t r0 = 0; r0 < rows; r0 += per) {
+    const int64_t nr = std::min(per, rows - r0);
+    buf.resize((size_t)nr * width);
+    PINV_HIP_TRY(hipMemcpy2DAsync(buf.data(), width, (const char*)dev + r0 * pitch, pitch, width, (size_t)nr,
+                                  hipMemcpyDeviceToHost, s));
+    PINV_HIP_TRY(hipStreamSynchronize(s));
+    if (std::fwrite(buf.data(), 1, buf.size(), f) != buf.size()) return PINV_E_IO;
+  }
+  return PINV_OK;
+}
+
+// file -> device in chunks of whole rows
+int32_t read_rows(FILE* f, void* dev, size_t pitch, size_t width, int64_t rows, std::vector<char>& buf,
+                  hipStream_t s) {
+  const int64_t per = std::max<int64_t>(1, (int64_t)(kChunk / width));
+  for (int64_t r0 = 0; r0 < rows; r0 += per) {
+    const int64_t nr = std::min(per, rows - r0);
+    buf.resize((size_t)nr * width);
+    if (std::fread(buf.data(), 1, buf.size(), f) != buf.size()) return PINV_E_IO;
+    PINV_HIP_TRY(hipMemcpy2DAsync((char*)dev + r0 * pitch, pitch, buf.data(), width, width, (size_t)nr,
+                                  hipMemcpyHostToDevice, s));
+    PINV_HIP_TRY(hipStreamSynchronize(s));
+  }
+  return PINV_OK;
+}
+
+int32_t alloc_read(FILE* f, size_t bytes, void** dev, std::vector<char>& buf, hipStream_t s) {
+  PINV_HIP_TRY(hipMalloc(dev, bytes));
+  return read_rows(f, *dev, bytes, bytes, 1, buf, s);
+}
+
+}  // namespace
+
+int32_t pinv_save(pinv_op op, const char* path, void* stream) {
+  if (!op || !path || !*path) return PINV_E_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  FileHeader h{};
+  std::memcpy(h.magic, kMagic, 8);
+  h.version = 1;
+  h.nx = op->nx;
+  h.ny = op->ny;
+  h.nz = op->nz;
+  h.general = op->general;
+  h.beta = op->beta;
+  h.n = op->n;
+  h.h = op->h;
+  h.S = op->S;
+  h.P = op->S ? op->P : 0;
+  for (int i = 0; i < 4; ++i) h.i8_variant[i] = op->i8_variant[i];
+  h.flags = (op->G ? kHasG : 0) | (op->w ? kHasW : 0) | (op->ub ? kHasUb : 0) | (op->S ? kHasQ : 0) |
+            (op->xc && op->yc ? kHasXY : 0);
+  if (!(h.flags & (kHasG | kHasQ))) return PINV_E_STATE;
+  PINV_HIP_TRY(hipStreamSynchronize(s));
+  File file;
+  file.f = std::fopen(path, "wb");
+  if (!file.f) return PINV_E_IO;
+  if (std::fwrite(&h, sizeof h, 1, file.f) != 1) return PINV_E_IO;
+  std::vector<char> buf;
+  int32_t st = PINV_OK;
+  if (h.flags & kHasXY) {
+    st = write_rows(file.f, op->xc, (size_t)h.nx * 8, (size_t)h.nx * 8, 1, buf, s);
+    if (st == PINV_OK) st = write_rows(file.f, op->yc, (size_t)h.ny * 8, (size_t)h.ny * 8, 1, buf, s);
+  }
+  const size_t nodes_b = (size_t)op_nodes(h.nx, h.ny, h.nz) * 8;
+  if (st == PINV_OK && (h.flags & kHasUb)) st = write_rows(file.f, op->ub, nodes_b, nodes_b, 1, buf, s);
+  if (st == PINV_OK && (h.flags & kHasW)) st = write_rows(file.f, op->w, (size_t)h.n * 8, (size_t)h.n * 8, 1, buf, s);
+  if (st == PINV_OK && (h.flags & kHasG))
+    st = write_rows(file.f, op->G, (size_t)op->ldg * 8, (size_t)h.n * 8, h.n, buf, s);
+  if (st == PINV_OK && (h.flags & kHasQ)) {
+    st = write_rows(file.f, op->e, (size_t)h.P * 4, (size_t)h.P * 4, 1, buf, s);
+    if (st == PINV_OK) st = write_rows(file.f, op->Q, (size_t)h.P, (size_t)h.P, (int64_t)h.S * h.P, buf, s);
+  }
+  if (st == PINV_OK && std::fflush(file.f) != 0) st = PINV_E_IO;
+  return st;
+}
+
+int32_t pinv_load(const char* path, void* stream, pinv_op* out) {
+  if (!out) return PINV_E_INVALID_ARG;
+  *out = nullptr;
+  if (!path || !*path) return PINV_E_INVALID_ARG;
+  File file;
+  file.f = std::fopen(path, "rb");
+  if (!file.f) return PINV_E_IO;
+  FileHeader h{};
+  if (std::fread(&h, sizeof h, 1, file.f) != 1) return PINV_E_IO;
+  // the header and the file's length must agree before anything is allocated
+  const int64_t n3 = (int64_t)(h.nx - 2) * (h.ny - 2) * (h.nz > 0 ? h.nz - 2 : 1);
+  if (std::memcmp(h.magic, kMagic, 8) != 0 || h.version != 1 || h.nx < 3 || h.ny < 3 ||
+      (h.nz != 0 && h.nz < 3) || n3 != h.n || h.n > (1 << 20) || !(h.h > 0.0) || !std::isfinite(h.h) ||
+      (h.flags & ~(kHasG | kHasW | kHasUb | kHasQ | kHasXY)) != 0 || !(h.flags & (kHasG | kHasQ)) ||
+      ((h.flags & kHasQ) ? (h.S < 1 || h.S > 3 || h.P != pinv_pad_dim(h.n)) : (h.S != 0 || h.P != 0)) ||
+      ((h.flags & kHasXY) != 0) != (h.general != 0) || (h.general && (h.beta || h.nz != 0)))
+    return PINV_E_INVALID_ARG;
+  for (int i = 0; i < 4; ++i)
+    if (h.i8_variant[i] < 0 || h.i8_variant[i] >= gemm_i8_variants()) return PINV_E_INVALID_ARG;
+  if (std::fseek(file.f, 0, SEEK_END) != 0) return PINV_E_IO;
+  const long end = std::ftell(file.f);
+  if (end < 0 || (int64_t)end != (int64_t)sizeof h + payload_bytes(h)) return PINV_E_INVALID_ARG;
+  if (std::fseek(file.f, (long)sizeof h, SEEK_SET) != 0) return PINV_E_IO;
+
+  hipStream_t s = as_stream(stream);
+  pinv_grid g2{h.nx, h.ny, h.h};
+  pinv_op op = new_op(&g2);
+  if (!op) return PINV_E_OOM;
+  op->nz = h.nz;
+  op->mz = h.nz > 0 ? h.nz - 2 : 1;
+  op->n = h.n;
+  op->ldg = (op->n + 31) / 32 * 32;
+  op->general = h.general;
+  op->beta = h.beta;
+  for (int i = 0; i < 4; ++i) op->i8_variant[i] = h.i8_variant[i];
+  std::vector<char> buf;
+  int32_t st = PINV_OK;
+  if (h.flags & kHasXY) {
+    st = alloc_read(file.f, (size_t)h.nx * 8, (void**)&op->xc, buf, s);
+    if (st == PINV_OK) st = alloc_read(file.f, (size_t)h.ny * 8, (void**)&op->yc, buf, s);
+    if (st == PINV_OK) op->bytes += (int64_t)(h.nx + h.ny) * 8;
+  }
+  const size_t nodes_b = (size_t)op_nodes(h.nx, h.ny, h.nz) * 8;
+  if (st == PINV_OK && (h.flags & kHasUb)) {
+    st = alloc_read(file.f, nodes_b, (void**)&op->ub, buf, s);
+    if (st == PINV_OK) op->bytes += (int64_t)nodes_b;
+  }
+  if (st == PINV_OK && (h.flags & kHasW)) {
+    st = alloc_read(file.f, (size_t)h.n * 8, (void**)&op->w, buf, s);
+    if (st == PINV_OK) op->bytes += (int64_t)h.n * 8;
+  }
+  if (st == PINV_OK && (h.flags & kHasG)) {
+    const size_t gb = (size_t)op->n * op->ldg * sizeof(double);
+    hipError_t e = hipMalloc(&op->G, gb);
+    // rows padded with zeros, as at build and import
+    if (e == hipSuccess) e = hipMemsetAsync(op->G, 0, gb, s);
+    st = pinv_hip_status(e);
+    if (st == PINV_OK) {
+      op->bytes += (int64_t)gb;
+      st = read_rows(file.f, op->G, (size_t)op->ldg * 8, (size_t)h.n * 8, h.n, buf, s);
+    }
+  }
+  if (st == PINV_OK && (h.flags & kHasQ)) {
+    const size_t plane_bytes = (size_t)h.S * h.P * h.P;
+    hipError_t e = hipMalloc(&op->Q, plane_bytes);
+    if (e == hipSuccess) e = hipMalloc(&op->QT, plane_bytes);
+    if (e == hipSuccess) e = hipMalloc(&op->e, (size_t)h.P * sizeof(int32_t));
+    st = pinv_hip_status(e);
+    if (st == PINV_OK) {
+      op->S = h.S;
+      op->P = h.P;
+      op->bytes += 2 * (int64_t)plane_bytes + h.P * (int64_t)sizeof(int32_t);
+      st = read_rows(file.f, op->e, (size_t)h.P * 4, (size_t)h.P * 4, 1, buf, s);
+    }
+    if (st == PINV_OK) st = read_rows(file.f, op->Q, (size_t)h.P, (size_t)h.P, (int64_t)h.S * h.P, buf, s);
+    if (st == PINV_OK) st = pinv_hip_status(launch_transpose_planes(op->Q, op->QT, h.S, h.P, s));
+  }
+  if (st == PINV_OK) st = pinv_hip_status(hipStreamSynchronize(s));
+  if (st != PINV_OK) {
+    free_op(op);
+    return st;
+  }
+  pinv_log("load: %s n=%d flags=%d S=%d", path, op->n, h.flags, op->S);
+  *out = op;
   return PINV_OK;
 }
 

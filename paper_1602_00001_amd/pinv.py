@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # _lib/libpinv_san.so); the default is the release build
 LIB_PATH = os.environ.get("PINV_LIBRARY") or os.path.join(_HERE, "_lib", "libpinv.so")
 
-OK, E_INVALID_ARG, E_NOT_SPD, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVALID_ARG, E_NOT_SPD, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE, E_IO = 0, -1, -2, -3, -4, -5, -6, -7
 MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8": 4, "fp64_sym": 5, "fix16_tile": 6}
 SCALE_ROW = 0
 NOALLOC_SCRATCH_BYTES = 64 << 20   # PINV_NOALLOC_SCRATCH_BYTES
@@ -92,6 +92,8 @@ def _load():
         "pinv_int8_variants": ([], i32),
         "pinv_set_int8_variant": ([vp, i32, i32], i32),
         "pinv_autotune_int8": ([vp, i32, dp, i64, i32, i32, P(ctypes.c_double), i32, P(i32), vp], i32),
+        "pinv_save": ([vp, ctypes.c_char_p, vp], i32),
+        "pinv_load": ([ctypes.c_char_p, vp, P(vp)], i32),
         "pinv_status_string": ([i32], ctypes.c_char_p),
         "pinv_version": ([], ctypes.c_char_p),
     }
@@ -108,7 +110,7 @@ EXPORTED = ("pinv_build_inverse", "pinv_build_inverse_3d", "pinv_build_inverse_g
             "pinv_prepare_split", "pinv_export_quantized", "pinv_export_tile16", "pinv_apply_inverse", "pinv_apply_inverse_noalloc", "pinv_apply_inverse_adjoint",
             "pinv_grad_eps", "pinv_apply_batched", "pinv_batched_release", "pinv_get_info", "pinv_destroy", "pinv_status_string",
             "pinv_version", "pinv_trace_enable", "pinv_trace_read", "pinv_trace_read_each", "pinv_int8_variants",
-            "pinv_set_int8_variant", "pinv_autotune_int8")
+            "pinv_set_int8_variant", "pinv_autotune_int8", "pinv_save", "pinv_load")
 
 
 def status_string(st):
@@ -279,6 +281,21 @@ class PoissonInverse:
         _check(lib.pinv_import_inverse(ctypes.byref(g), _ptr(G), n, _ptr(e), _ptr(ub), _ptr(wv), _stream(stream),
                                        ctypes.byref(out)), "pinv_import_inverse")
         return cls(out, nx, ny, h)
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """An op from a file written by save() (no rebuild)."""
+        out = ctypes.c_void_p()
+        _check(lib.pinv_load(os.fsencode(path), _stream(stream), ctypes.byref(out)), "pinv_load")
+        h = cls(out, 3, 3, 1.0)
+        i = h.info()
+        h.nx, h.ny, h.nz, h.h, h.n = i["nx"], i["ny"], i["nz"], i["h"], i["n"]
+        return h
+
+    def save(self, path, stream=None):
+        """Write the op's G and/or int8 slices, lift and grid to a file."""
+        _check(lib.pinv_save(self._h, os.fsencode(path), _stream(stream)), "pinv_save")
+        return self
 
     # -- representations ------------------------------------------------------
     def quantize(self, bits, keep_fp64=True, stream=None):

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(pinv):
 
 
 def test_status_strings(pinv):
-    for st in (0, -1, -2, -3, -4, -5, -6):
+    for st in (0, -1, -2, -3, -4, -5, -6, -7):
         assert pinv.status_string(st)
     assert pinv.status_string(-99) == "unknown status"
     assert re.match(r"\d+\.\d+\.\d+$", pinv.version())
@@ -117,6 +117,48 @@ def test_header_constants_match_the_binding(pinv):
     for c, name in modes.items():
         assert defs[c] == pinv.MODES[name], c
     assert set(pinv.MODES) == set(modes.values())
-    for c in ("OK", "E_INVALID_ARG", "E_NOT_SPD", "E_OOM", "E_HIP", "E_UNSUPPORTED", "E_STATE"):
+    for c in ("OK", "E_INVALID_ARG", "E_NOT_SPD", "E_OOM", "E_HIP", "E_UNSUPPORTED", "E_STATE", "E_IO"):
         assert defs[c] == getattr(pinv, c), c
     assert defs["SCALE_ROW"] == pinv.SCALE_ROW
+
+
+def test_checkpoint_files_are_checked_before_any_device_call(pinv, tmp_path):
+    """pinv_load reads and checks the header and the file's length first:
+    a missing file is PINV_E_IO; a file that is not a checkpoint, a header
+    with inconsistent sizes, or a length that does not match the header is
+    PINV_E_INVALID_ARG, with nothing allocated (so this runs without a GPU)."""
+    import struct
+    lib = pinv.lib
+    out = ctypes.c_void_p()
+    assert lib.pinv_load(str(tmp_path / "missing.pinv").encode(), None, ctypes.byref(out)) == pinv.E_IO
+    assert not out.value
+    assert lib.pinv_load(None, None, ctypes.byref(out)) == pinv.E_INVALID_ARG
+    assert lib.pinv_load(b"x", None, None) == pinv.E_INVALID_ARG
+    assert lib.pinv_save(None, str(tmp_path / "x.pinv").encode(), None) == pinv.E_INVALID_ARG
+    junk = tmp_path / "junk.pinv"
+    junk.write_bytes(b"not a checkpoint" * 8)
+    assert lib.pinv_load(str(junk).encode(), None, ctypes.byref(out)) == pinv.E_INVALID_ARG
+    short = tmp_path / "short.pinv"
+    short.write_bytes(b"PINVOP01")
+    assert lib.pinv_load(str(short).encode(), None, ctypes.byref(out)) == pinv.E_IO
+
+    def header(nx=10, ny=10, nz=0, n=64, flags=1 | 2, S=0, P=0, h=0.1, general=0, beta=0, variants=(0, 0, 0, 0)):
+        return struct.pack("<8s14iqd", b"PINVOP01", 1, nx, ny, nz, general, beta, n, flags, S, *variants, 0, P, h)
+
+    good_len = 8 * 64 + 8 * 64 * 64            # w, then G
+    cases = [
+        header() + bytes(good_len - 8),          # one value short
+        header() + bytes(good_len + 8),          # one value long
+        header(n=65) + bytes(good_len),          # N is not (nx - 2)(ny - 2)
+        header(flags=2) + bytes(8 * 64),         # neither G nor slices
+        header(flags=1 | 8, S=2, P=64) + bytes(8 * 64 * 64 + 4 * 64 + 2 * 64 * 64),   # P not padded to 256
+        header(flags=1 | 16) + bytes(8 * 64 * 64 + 8 * 20),     # node coordinates on a uniform grid
+        header(variants=(0, 99, 0, 0)) + bytes(good_len),        # no such kernel variant
+        header(h=-1.0) + bytes(good_len),
+        header(h=float("nan")) + bytes(good_len),
+    ]
+    for i, blob in enumerate(cases):
+        f = tmp_path / f"bad{i}.pinv"
+        f.write_bytes(blob)
+        assert lib.pinv_load(str(f).encode(), None, ctypes.byref(out)) == pinv.E_INVALID_ARG, i
+        assert not out.value
