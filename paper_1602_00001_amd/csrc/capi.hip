@@ -1222,9 +1222,13 @@ int32_t pinv_load(const char* path, void* stream, pinv_op* out) {
   FileHeader h{};
   if (std::fread(&h, sizeof h, 1, file.f) != 1) return PINV_E_IO;
   // the header and the file's length must agree before anything is allocated
-  const int64_t n3 = (int64_t)(h.nx - 2) * (h.ny - 2) * (h.nz > 0 ? h.nz - 2 : 1);
-  if (std::memcmp(h.magic, kMagic, 8) != 0 || h.version != 1 || h.nx < 3 || h.ny < 3 ||
-      (h.nz != 0 && h.nz < 3) || n3 != h.n || h.n > (1 << 20) || !(h.h > 0.0) || !std::isfinite(h.h) ||
+  // (sizes are bounded before they are multiplied)
+  constexpr int32_t kMaxSide = (1 << 20) + 2;
+  if (std::memcmp(h.magic, kMagic, 8) != 0 || h.version != 1 || h.nx < 3 || h.ny < 3 || h.nx > kMaxSide ||
+      h.ny > kMaxSide || (h.nz != 0 && (h.nz < 3 || h.nz > kMaxSide)))
+    return PINV_E_INVALID_ARG;
+  const int64_t n3 = (int64_t)(h.nx - 2) * (h.ny - 2) * (h.nz > 0 ? h.nz - 2 : 1);  // < 2^63
+  if (n3 != h.n || h.n > (1 << 20) || !(h.h > 0.0) || !std::isfinite(h.h) ||
       (h.flags & ~(kHasG | kHasW | kHasUb | kHasQ | kHasXY)) != 0 || !(h.flags & (kHasG | kHasQ)) ||
       ((h.flags & kHasQ) ? (h.S < 1 || h.S > 3 || h.P != pinv_pad_dim(h.n)) : (h.S != 0 || h.P != 0)) ||
       ((h.flags & kHasXY) != 0) != (h.general != 0) || (h.general && (h.beta || h.nz != 0)))
