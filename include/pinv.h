@@ -114,6 +114,9 @@ typedef struct {
   int32_t beta;             /* built by pinv_build_inverse_beta (h = 1)         */
   int32_t has_sym;          /* symmetric-packed FP64 copy held                  */
   int32_t has_tile16;       /* 16-bit tile-scaled copy held                     */
+  int32_t fp64_symmetric;   /* G resident and equal to G^T bit for bit (checked
+                               when G is built, imported or loaded; the FP64
+                               adjoint then runs the forward product)          */
 } pinv_info;
 
 /* Steps 1-2 of "The solution steps": assemble the interior operator K from the
@@ -314,8 +317,9 @@ int32_t pinv_apply_inverse_noalloc(pinv_op op, int32_t rho_bits,
  * the mode selects (G^T of the rounded matrix in INT8 mode, where g's row
  * scaling 2^e_k is applied exactly before g is rounded to g_bits per column;
  * the transposed 16-bit copy in FIX16_TILE mode; the packed upper triangle
- * itself in FP64_SYM mode, G being symmetric).  Same layout rules as
- * pinv_apply_inverse.  Asynchronous. */
+ * itself in FP64_SYM mode, G being symmetric; in FP64 mode the forward
+ * product itself when G equals G^T bit for bit, see pinv_info).  Same layout
+ * rules as pinv_apply_inverse.  Asynchronous. */
 int32_t pinv_apply_inverse_adjoint(pinv_op op, int32_t mode, int32_t g_bits,
                                    const double* g, int64_t ld_g, int32_t nrhs,
                                    double* lambda, int64_t ld_lambda, void* stream);

@@ -119,6 +119,24 @@ pinv_op new_op(const pinv_grid* g) {
 
 void purge_batch_plans(pinv_op op);
 
+// Sets op->g_symmetric: whether G equals its transpose bit for bit (then the
+// FP64 adjoint runs the forward product).  One pass over G; synchronises.
+int32_t detect_symmetry(pinv_op op, hipStream_t s) {
+  op->g_symmetric = 0;
+  if (!op->G) return PINV_OK;
+  int* flag = nullptr;
+  PINV_HIP_TRY(hipMalloc(&flag, sizeof(int)));
+  int hflag = 1;
+  hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
+  if (e == hipSuccess) e = launch_sym_check(op->G, op->ldg, op->n, 0.0, flag, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(flag);
+  if (e != hipSuccess) return pinv_hip_status(e);
+  op->g_symmetric = hflag == 0;
+  return PINV_OK;
+}
+
 void free_quant(pinv_op op) {
   purge_batch_plans(op);  // batched plans hold the digit planes' addresses
   if (op->Q) (void)hipFree(op->Q);
@@ -271,6 +289,8 @@ int32_t int8_apply(pinv_op op, const int8_t* Q, const int32_t* row_exp, const in
 int32_t fp64_apply(pinv_op op, bool transpose, const double* X, int64_t ldx, int nrhs, const double* bias,
                    double* U, int64_t ldu, hipStream_t s) {
   const double alpha = -(op->h * op->h);
+  // G^T = G bit for bit: the adjoint is the forward product
+  if (transpose && op->g_symmetric) transpose = false;
   if (!transpose && nrhs <= 4) {
     TraceScope ts("gemv_f64", s);
     PINV_HIP_TRY(launch_gemv_f64(op->G, op->ldg, op->n, X, ldx, nrhs, alpha, bias, U, ldu, s));
@@ -853,7 +873,13 @@ int32_t build_op(pinv_op op, int nodes, bool has_ub, const double* eps_nodes, co
   }
   op->ub = ub_d;
   if (ub_d) op->bytes += (int64_t)nodes * sizeof(double);
-  pinv_log("build_inverse: n=%d ldg=%lld bytes=%lld", op->n, (long long)op->ldg, (long long)op->bytes);
+  st = detect_symmetry(op, s);
+  if (st != PINV_OK) {
+    free_op(op);
+    return st;
+  }
+  pinv_log("build_inverse: n=%d ldg=%lld bytes=%lld symmetric=%d", op->n, (long long)op->ldg, (long long)op->bytes,
+           op->g_symmetric);
   *out = op;
   return PINV_OK;
 }
@@ -914,6 +940,7 @@ int32_t pinv_import_inverse(const pinv_grid* g, const double* G_host, int64_t ld
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) st = pinv_hip_status(e);
   }
+  if (st == PINV_OK) st = detect_symmetry(op, s);
   if (st != PINV_OK) {
     free_op(op);
     return st;
@@ -1009,12 +1036,13 @@ int32_t pinv_prepare_split(pinv_op op, int32_t mode, void* stream) {
     return PINV_OK;
   }
   if (mode == PINV_FP64_SYM) {
-    // only an exactly symmetric G may be stored as its upper triangle
+    // only a G symmetric to 1e-12 (relative to its diagonal) may be stored as
+    // its upper triangle
     int* flag = nullptr;
     PINV_HIP_TRY(hipMalloc(&flag, sizeof(int)));
     int hflag = 0;
     hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
-    if (e == hipSuccess) e = launch_sym_check(op->G, op->ldg, op->n, flag, s);
+    if (e == hipSuccess) e = launch_sym_check(op->G, op->ldg, op->n, 1e-12, flag, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(flag);
@@ -1294,6 +1322,7 @@ int32_t pinv_load(const char* path, void* stream, pinv_op* out) {
     if (st == PINV_OK) st = pinv_hip_status(launch_transpose_planes(op->Q, op->QT, h.S, h.P, s));
   }
   if (st == PINV_OK) st = pinv_hip_status(hipStreamSynchronize(s));
+  if (st == PINV_OK) st = detect_symmetry(op, s);
   if (st != PINV_OK) {
     free_op(op);
     return st;
@@ -1563,6 +1592,7 @@ int32_t pinv_get_info(pinv_op op, pinv_info* info) {
   info->has_sym = op->Gsym != nullptr;
   info->has_tile16 = op->Gt16 != nullptr;
   info->general = op->general;
+  info->fp64_symmetric = op->G != nullptr && op->g_symmetric;
   return PINV_OK;
 }
 

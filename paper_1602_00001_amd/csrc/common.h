@@ -35,6 +35,7 @@ struct pinv_op_s {
   // FP64 inverse, row-major [n][ldg] (ldg multiple of 32 doubles)
   double* G = nullptr;
   int64_t ldg = 0;
+  int g_symmetric = 0;       // G is exactly symmetric (checked when G is formed or loaded)
   double* w = nullptr;       // lift [n] (nullptr when the Dirichlet data is zero)
   double* ub = nullptr;      // nodal Dirichlet data [ny*nx] (nullptr when zero)
 
@@ -278,7 +279,7 @@ int sym_blocks_per_side(int n);
 size_t sym_packed_elems(int n);
 // scratch for launch_gemv_sym (partials of up to 8 right-hand sides)
 size_t sym_scratch_bytes(int n, int nrhs);
-hipError_t launch_sym_check(const double* G, int64_t ld, int n, int* flag, hipStream_t s);
+hipError_t launch_sym_check(const double* G, int64_t ld, int n, double tol, int* flag, hipStream_t s);
 hipError_t launch_pack_upper(const double* G, int64_t ld, int n, double* Gp, hipStream_t s);
 // U = alpha * G X + bias from the packed copy; Y: sym_scratch_bytes(n, nrhs)
 hipError_t launch_gemv_sym(const double* Gp, int n, const double* X, int64_t ldx, int nrhs, double alpha,

@@ -34,14 +34,16 @@ __device__ inline void block_of(int64_t b, int nb, int& I, int& J) {
 // flag = 1 unless |G[i][j] - G[j][i]| <= 1e-12 sqrt(|G[i][i] G[j][j]|) for all
 // i < j (the scale of a symmetric positive definite matrix's entries; a NaN
 // fails the test)
-__global__ void sym_check_kernel(const double* __restrict__ G, int64_t ld, int n, int* __restrict__ flag) {
+// flag = 1 if some |G_ij - G_ji| exceeds tol sqrt(|G_ii G_jj|) (tol = 0: if G
+// is not exactly symmetric; NaN entries count as asymmetric)
+__global__ void sym_check_kernel(const double* __restrict__ G, int64_t ld, int n, double tol, int* __restrict__ flag) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
   const int i = (int)(idx / n), j = (int)(idx % n);
   if (i >= j) return;
   const double d = fabs(G[(int64_t)i * ld + j] - G[(int64_t)j * ld + i]);
   const double scale = sqrt(fabs(G[(int64_t)i * ld + i] * G[(int64_t)j * ld + j]));
-  if (!(d <= 1e-12 * scale)) *flag = 1;
+  if (!(d <= tol * scale)) *flag = 1;
 }
 
 __global__ __launch_bounds__(256) void pack_upper_kernel(const double* __restrict__ G, int64_t ld, int n, int nb,
@@ -186,10 +188,10 @@ size_t sym_scratch_bytes(int n, int nrhs) {
   return nr * nb * nb * SB * sizeof(double);
 }
 
-hipError_t launch_sym_check(const double* G, int64_t ld, int n, int* flag, hipStream_t s) {
+hipError_t launch_sym_check(const double* G, int64_t ld, int n, double tol, int* flag, hipStream_t s) {
   const int64_t total = (int64_t)n * n;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(sym_check_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G, ld, n, flag);
+  hipLaunchKernelGGL(sym_check_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G, ld, n, tol, flag);
   return hipGetLastError();
 }
 

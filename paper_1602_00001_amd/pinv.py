@@ -51,7 +51,7 @@ class Info(ctypes.Structure):
                 ("has_bf16", ctypes.c_int32), ("has_lift", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("nz", ctypes.c_int32), ("general", ctypes.c_int32), ("beta", ctypes.c_int32),
                 ("has_sym", ctypes.c_int32),
-                ("has_tile16", ctypes.c_int32)]
+                ("has_tile16", ctypes.c_int32), ("fp64_symmetric", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):

@@ -251,6 +251,41 @@ def test_fp64_adjoint_and_grad_eps(torch, pinv, nx, ny, R):
     assert np.linalg.norm(ge - ge_ref) <= 1e-12 * np.linalg.norm(ge_ref)
 
 
+@pytest.mark.parametrize("R", [3, 40])
+def test_fp64_adjoint_of_exactly_symmetric_and_other_inverses(torch, pinv, R):
+    """The FP64 adjoint runs the forward product when G equals G^T bit for bit
+    (checked when G is built, imported or loaded): a GPU-built operator, an
+    imported symmetrised inverse; and the transposed product otherwise (an
+    imported inverse with one entry pair made unequal).  Each against the
+    oracle's G^T product, and the symmetric ones bit for bit against the
+    forward apply of the same vectors.  R = 3: GEMV; 40: the tiled product."""
+    nx, ny = 40, 33
+    announce(f"fp64 adjoint, symmetric shortcut nrhs={R}")
+    g = np.random.default_rng(5 + R)
+    h = 1.0 / (nx - 1)
+    eps = workloads.random_eps(nx, ny, g)
+    G, _, _ = oracle_inverse(nx, ny, eps)
+    N = G.shape[0]
+    gv = g.standard_normal((R, N))
+    Gs = 0.5 * (G + G.T)                  # exactly symmetric
+    Gn = Gs.copy()
+    Gn[3, 17] *= 1.0 + 1e-9               # not symmetric
+    with pinv.PoissonInverse.build(nx, ny, h, eps) as op:
+        assert op.info()["fp64_symmetric"] == 1
+        Gb, _ = op.export_inverse()
+        assert np.array_equal(Gb, Gb.T)
+        lam = op.apply_adjoint(dev(gv), "fp64")
+        assert torch.equal(lam, op.apply(dev(gv), "fp64"))
+        assert np.max(metrics.rel_l2_per_rhs(host(lam).T, grad.adjoint(Gb, gv.T, h))) <= 1e-12
+    for M, sym in ((Gs, 1), (Gn, 0)):
+        with pinv.PoissonInverse.from_inverse(nx, ny, h, M) as op:
+            assert op.info()["fp64_symmetric"] == sym
+            lam = op.apply_adjoint(dev(gv), "fp64")
+            if sym:
+                assert torch.equal(lam, op.apply(dev(gv), "fp64"))
+            assert np.max(metrics.rel_l2_per_rhs(host(lam).T, grad.adjoint(M, gv.T, h))) <= 1e-12
+
+
 def test_grad_eps_without_right_hand_sides_is_zero(torch, pinv):
     announce("grad_eps nrhs=0")
     nx, ny = 10, 8
