@@ -137,10 +137,11 @@ __global__ void assemble_general_kernel(int nx, int ny, const double* __restrict
 
 // G[i][q] *= A[q]: the inverse then maps rho straight to u (u = -G rho + w)
 __global__ void scale_columns_kernel(double* __restrict__ G, int64_t ld, int n, const double* __restrict__ A) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * n) return;
-  const int i = (int)(idx / n), q = (int)(idx % n);
-  G[(int64_t)i * ld + q] *= A[q];
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / n), q = (int)(idx % n);
+    G[(int64_t)i * ld + q] *= A[q];
+  }
 }
 
 // Factor the kn x kn diagonal block at (k0, k0) in place (lower triangle, zero
@@ -367,10 +368,11 @@ __global__ void iota_kernel(int* __restrict__ perm, int n) {
 // A^{-1} = Y P and G = -A^{-1}.
 __global__ void permute_negate_kernel(const double* __restrict__ Y, int64_t ld, int n, const int* __restrict__ perm,
                                       double* __restrict__ G) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * n) return;
-  const int r = (int)(idx / n), i = (int)(idx % n);
-  G[(int64_t)r * ld + perm[i]] = -Y[(int64_t)r * ld + i];
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / n), i = (int)(idx % n);
+    G[(int64_t)r * ld + perm[i]] = -Y[(int64_t)r * ld + i];
+  }
 }
 
 __global__ void set_identity_kernel(double* __restrict__ A, int64_t lda, int n) {
@@ -494,7 +496,7 @@ int32_t build_inverse_device(pinv_op op, const double* eps_dev, const double* ub
   }
   if (gen) {
     // after the lift (w = K^{-1} b_B): fold the control volumes into G's columns
-    hipLaunchKernelGGL(scale_columns_kernel, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, s, Kb, ld,
+    hipLaunchKernelGGL(scale_columns_kernel, dim3(grid_1d((int64_t)n * n)), dim3(256), 0, s, Kb, ld,
                        n, (const double*)gen->area);
     PINV_BAIL(hipGetLastError());
   }
@@ -645,7 +647,7 @@ int32_t build_inverse_lu_device(pinv_op op, const double* beta_dev, const double
   }
 
   // G = -(P A)^{-1} P, into Kb (its factors are no longer read); w = -G b_B
-  hipLaunchKernelGGL(permute_negate_kernel, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, s, Wb, ld,
+  hipLaunchKernelGGL(permute_negate_kernel, dim3(grid_1d((int64_t)n * n)), dim3(256), 0, s, Wb, ld,
                      n, perm, Kb);
   PINV_BAIL(hipGetLastError());
   if (ub_dev) {

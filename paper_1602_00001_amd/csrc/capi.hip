@@ -297,19 +297,24 @@ int32_t fp64_apply(pinv_op op, bool transpose, const double* X, int64_t ldx, int
     return PINV_OK;
   }
   if (!transpose) {
-    // the forward product: one wave per SIMD, 256 x 128 tiles
-    const ApplyF64Plan p = apply_f64_plan(op->n, nrhs, op->n);
+    // the forward product: one wave per SIMD, 256 x 128 tiles; right-hand
+    // sides in chunks whose padded copy holds fewer than 2^31 values
+    const int64_t ldp = ((int64_t)op->n + 31) / 32 * 32;
+    const int chunk = (int)std::max<int64_t>(128, (((int64_t)1 << 31) / ldp) / 128 * 128);
     configure_pool_once();
-    void* scratch = nullptr;
-    PINV_HIP_TRY(hipMallocAsync(&scratch, p.pack_bytes + p.part_bytes, s));
-    hipError_t e;
-    {
-      TraceScope ts("gemm_f64", s);
-      e = launch_apply_f64(p, op->G, op->ldg, op->n, op->n, X, ldx, nrhs, alpha, bias, U, ldu, scratch, s);
+    TraceScope ts("gemm_f64", s);
+    for (int c0 = 0; c0 < nrhs; c0 += chunk) {
+      const int nc = std::min(chunk, nrhs - c0);
+      const ApplyF64Plan p = apply_f64_plan(op->n, nc, op->n);
+      void* scratch = nullptr;
+      PINV_HIP_TRY(hipMallocAsync(&scratch, p.pack_bytes + p.part_bytes, s));
+      const hipError_t e = launch_apply_f64(p, op->G, op->ldg, op->n, op->n, X + (int64_t)c0 * ldx, ldx, nc, alpha,
+                                            bias, U + (int64_t)c0 * ldu, ldu, scratch, s);
+      const hipError_t e2 = hipFreeAsync(scratch, s);
+      if (e != hipSuccess) return pinv_hip_status(e);
+      if (e2 != hipSuccess) return pinv_hip_status(e2);
     }
-    const hipError_t e2 = hipFreeAsync(scratch, s);
-    if (e != hipSuccess) return pinv_hip_status(e);
-    return pinv_hip_status(e2);
+    return PINV_OK;
   }
   GemmF64Args a{};
   a.A = op->G; a.lda = op->ldg; a.a_kcontig = transpose ? 0 : 1;

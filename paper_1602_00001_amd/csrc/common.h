@@ -17,6 +17,14 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 #define PINV_WAVE 64
 
+// Workgroups for an element-wise kernel over `total` items with 256 threads
+// and a grid-stride loop: at most 2^20 workgroups, so the launch stays far
+// below the 2^32 work-items a dispatch can hold.
+inline unsigned grid_1d(int64_t total) {
+  const int64_t b = (total + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > (1 << 20) ? (1 << 20) : b));
+}
+
 // Padded square dimension of the int8 digit planes and of split-precision
 // copies: a multiple of 256 so that every 128x128 (or 256-row) tile and every
 // 64/128-byte k chunk lies inside the allocation; the padding holds zeros.

@@ -379,17 +379,17 @@ __global__ __launch_bounds__(256) void gemv_f64_kernel(const double* __restrict_
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const double* __restrict__ part, int ksplit, int M, int N,
                                                            double alpha, double beta, const double* __restrict__ bias,
                                                            double* __restrict__ C, int64_t csm, int64_t csn) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t MN = (int64_t)M * N;
-  if (idx >= MN) return;
-  const int m = (int)(idx % M), n = (int)(idx / M);
-  double acc = 0.0;
-  for (int z = 0; z < ksplit; ++z) acc += part[(int64_t)z * MN + idx];
-  double* c = C + (int64_t)m * csm + (int64_t)n * csn;
-  double v = alpha * acc;
-  if (beta != 0.0) v += beta * *c;
-  if (bias) v += bias[m];
-  *c = v;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < MN; idx += (int64_t)gridDim.x * 256) {
+    const int m = (int)(idx % M), n = (int)(idx / M);
+    double acc = 0.0;
+    for (int z = 0; z < ksplit; ++z) acc += part[(int64_t)z * MN + idx];
+    double* c = C + (int64_t)m * csm + (int64_t)n * csn;
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * *c;
+    if (bias) v += bias[m];
+    *c = v;
+  }
 }
 
 }  // namespace
@@ -417,7 +417,7 @@ hipError_t launch_splitk_reduce(const double* part, int ksplit, int M, int N, do
                                 const double* bias, double* C, int64_t csm, int64_t csn, hipStream_t s) {
   const int64_t MN = (int64_t)M * N;
   if (MN == 0) return hipSuccess;
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, part, ksplit, M, N,
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_1d(MN)), dim3(256), 0, s, part, ksplit, M, N,
                      alpha, beta, bias, C, csm, csn);
   return hipGetLastError();
 }

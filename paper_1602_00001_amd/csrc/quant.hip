@@ -318,19 +318,19 @@ __global__ __launch_bounds__(1024) void quantize_cols_grouped_wide_kernel(const 
 }
 
 __global__ void fill_random_i8_kernel(int8_t* __restrict__ p, size_t n, uint32_t seed) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t x = (uint32_t)i * 2654435761u + seed;
-  x ^= x >> 15;
-  x *= 2246822519u;
-  x ^= x >> 13;
-  p[i] = (int8_t)(x >> 24);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    uint32_t x = (uint32_t)i * 2654435761u + seed;
+    x ^= x >> 15;
+    x *= 2246822519u;
+    x ^= x >> 13;
+    p[i] = (int8_t)(x >> 24);
+  }
 }
 
 }  // namespace
 
 hipError_t launch_fill_random_i8(int8_t* p, size_t n, uint32_t seed, hipStream_t s) {
-  hipLaunchKernelGGL(fill_random_i8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, seed);
+  hipLaunchKernelGGL(fill_random_i8_kernel, dim3(grid_1d((int64_t)n)), dim3(256), 0, s, p, n, seed);
   return hipGetLastError();
 }
 

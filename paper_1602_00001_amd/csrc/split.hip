@@ -37,45 +37,47 @@ __device__ inline __bf16 to_bf16_exact(double v) {
 
 __global__ __launch_bounds__(256) void make_fp32_kernel(const double* __restrict__ G, int64_t ldg, int n, int64_t P,
                                                        float* __restrict__ G32) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= P * P) return;
-  const int64_t i = idx / P, k = idx % P;
-  G32[idx] = (i < n && k < n) ? (float)G[i * ldg + k] : 0.0f;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < P * P; idx += (int64_t)gridDim.x * 256) {
+    const int64_t i = idx / P, k = idx % P;
+    G32[idx] = (i < n && k < n) ? (float)G[i * ldg + k] : 0.0f;
+  }
 }
 
 __global__ __launch_bounds__(256) void make_bf16_kernel(const double* __restrict__ G, int64_t ldg, int n, int64_t P,
                                                        int parts, __bf16* __restrict__ Gb) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= P * P) return;
-  const int64_t i = idx / P, k = idx % P;
-  double rest = (i < n && k < n) ? G[i * ldg + k] : 0.0;
-  for (int p = 0; p < parts; ++p) {
-    const double v = round_bf16_exact(rest);
-    Gb[(int64_t)p * P * P + idx] = to_bf16_exact(v);
-    rest = rest - v;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < P * P; idx += (int64_t)gridDim.x * 256) {
+    const int64_t i = idx / P, k = idx % P;
+    double rest = (i < n && k < n) ? G[i * ldg + k] : 0.0;
+    for (int p = 0; p < parts; ++p) {
+      const double v = round_bf16_exact(rest);
+      Gb[(int64_t)p * P * P + idx] = to_bf16_exact(v);
+      rest = rest - v;
+    }
   }
 }
 
 // right-hand sides (column-major n x nrhs, stride ldx) -> [parts][Rpad][P] bf16
 __global__ __launch_bounds__(256) void pack_bf16_kernel(const double* __restrict__ X, int64_t ldx, int n, int nrhs,
                                                        int Rpad, int64_t P, int parts, __bf16* __restrict__ Xb) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)Rpad * P) return;
-  const int64_t r = idx / P, k = idx % P;
-  double rest = (r < nrhs && k < n) ? X[r * ldx + k] : 0.0;
-  for (int p = 0; p < parts; ++p) {
-    const double v = round_bf16_exact(rest);
-    Xb[(int64_t)p * Rpad * P + idx] = to_bf16_exact(v);
-    rest = rest - v;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < (int64_t)Rpad * P;
+       idx += (int64_t)gridDim.x * 256) {
+    const int64_t r = idx / P, k = idx % P;
+    double rest = (r < nrhs && k < n) ? X[r * ldx + k] : 0.0;
+    for (int p = 0; p < parts; ++p) {
+      const double v = round_bf16_exact(rest);
+      Xb[(int64_t)p * Rpad * P + idx] = to_bf16_exact(v);
+      rest = rest - v;
+    }
   }
 }
 
 __global__ __launch_bounds__(256) void pack_fp32_kernel(const double* __restrict__ X, int64_t ldx, int n, int nrhs,
                                                        int Rpad, int64_t P, float* __restrict__ Xf) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)Rpad * P) return;
-  const int64_t r = idx / P, k = idx % P;
-  Xf[idx] = (r < nrhs && k < n) ? (float)X[r * ldx + k] : 0.0f;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < (int64_t)Rpad * P;
+       idx += (int64_t)gridDim.x * 256) {
+    const int64_t r = idx / P, k = idx % P;
+    Xf[idx] = (r < nrhs && k < n) ? (float)X[r * ldx + k] : 0.0f;
+  }
 }
 
 __device__ inline void tile_of(int bid, int tilesM, int tilesN, int& mt, int& nt, bool& valid) {
@@ -204,13 +206,13 @@ __global__ __launch_bounds__(256, 2) void gemm_fp32_kernel(SplitArgs a, int tile
 
 hipError_t launch_make_fp32(const double* G, int64_t ldg, int n, float* G32, hipStream_t s) {
   const int64_t P = pinv_pad_dim(n);
-  hipLaunchKernelGGL(make_fp32_kernel, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, s, G, ldg, n, P, G32);
+  hipLaunchKernelGGL(make_fp32_kernel, dim3(grid_1d(P * P)), dim3(256), 0, s, G, ldg, n, P, G32);
   return hipGetLastError();
 }
 
 hipError_t launch_make_bf16_parts(const double* G, int64_t ldg, int n, int parts, __bf16* Gb, hipStream_t s) {
   const int64_t P = pinv_pad_dim(n);
-  hipLaunchKernelGGL(make_bf16_kernel, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, s, G, ldg, n, P, parts,
+  hipLaunchKernelGGL(make_bf16_kernel, dim3(grid_1d(P * P)), dim3(256), 0, s, G, ldg, n, P, parts,
                      Gb);
   return hipGetLastError();
 }
@@ -263,7 +265,7 @@ hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int
   const int tilesM = (int)(P / BM), tilesN = Rpad / BN;
   const int T = tilesM * tilesN;
   const int grid = ((T + 7) / 8) * 8;
-  const unsigned pgrid = (unsigned)(((int64_t)Rpad * P + 255) / 256);
+  const unsigned pgrid = grid_1d((int64_t)Rpad * P);
   SplitArgs a{};
   a.P = P; a.Rpad = Rpad; a.n = op->n; a.nrhs = nrhs; a.alpha = alpha; a.w = op->w; a.U = U; a.ldu = ldu;
   a.B = scratch;

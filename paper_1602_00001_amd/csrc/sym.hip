@@ -31,19 +31,32 @@ __device__ inline void block_of(int64_t b, int nb, int& I, int& J) {
   J = i + (int)(b - block_row_start(i, nb));
 }
 
-// flag = 1 unless |G[i][j] - G[j][i]| <= 1e-12 sqrt(|G[i][i] G[j][j]|) for all
-// i < j (the scale of a symmetric positive definite matrix's entries; a NaN
-// fails the test)
-// flag = 1 if some |G_ij - G_ji| exceeds tol sqrt(|G_ii G_jj|) (tol = 0: if G
-// is not exactly symmetric; NaN entries count as asymmetric)
-__global__ void sym_check_kernel(const double* __restrict__ G, int64_t ld, int n, double tol, int* __restrict__ flag) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * n) return;
-  const int i = (int)(idx / n), j = (int)(idx % n);
-  if (i >= j) return;
-  const double d = fabs(G[(int64_t)i * ld + j] - G[(int64_t)j * ld + i]);
-  const double scale = sqrt(fabs(G[(int64_t)i * ld + i] * G[(int64_t)j * ld + j]));
-  if (!(d <= tol * scale)) *flag = 1;
+// flag = 1 if some |G[i][j] - G[j][i]| with i < j exceeds tol sqrt(|G[i][i]
+// G[j][j]|) (the scale of a symmetric positive definite matrix's entries;
+// tol = 0 asks for exact symmetry; a NaN fails the test).  One workgroup per
+// 64 x 64 block pair (I, J), J >= I: block (J, I) is read into LDS by rows
+// (coalesced) and compared, transposed, with block (I, J).
+__global__ __launch_bounds__(256) void sym_check_kernel(const double* __restrict__ G, int64_t ld, int n, int nb,
+                                                        double tol, int* __restrict__ flag) {
+  __shared__ double t[SB][SB + 1];
+  int I, J;
+  block_of(blockIdx.x, nb, I, J);
+  for (int e = threadIdx.x; e < SB * SB; e += 256) {
+    const int r = e / SB, c = e % SB;
+    const int row = J * SB + r, col = I * SB + c;
+    t[c][r] = (row < n && col < n) ? G[(int64_t)row * ld + col] : 0.0;
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int e = threadIdx.x; e < SB * SB; e += 256) {
+    const int r = e / SB, c = e % SB;
+    const int i = I * SB + r, j = J * SB + c;
+    if (i >= n || j >= n || i >= j) continue;
+    const double d = fabs(G[(int64_t)i * ld + j] - t[r][c]);
+    const double scale = sqrt(fabs(G[(int64_t)i * ld + i] * G[(int64_t)j * ld + j]));
+    bad = bad || !(d <= tol * scale);
+  }
+  if (bad) *flag = 1;
 }
 
 __global__ __launch_bounds__(256) void pack_upper_kernel(const double* __restrict__ G, int64_t ld, int n, int nb,
@@ -189,9 +202,10 @@ size_t sym_scratch_bytes(int n, int nrhs) {
 }
 
 hipError_t launch_sym_check(const double* G, int64_t ld, int n, double tol, int* flag, hipStream_t s) {
-  const int64_t total = (int64_t)n * n;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(sym_check_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G, ld, n, tol, flag);
+  if (n <= 0) return hipSuccess;
+  const int nb = sym_blocks_per_side(n);
+  const int64_t blocks = (int64_t)nb * (nb + 1) / 2;
+  hipLaunchKernelGGL(sym_check_kernel, dim3((unsigned)blocks), dim3(256), 0, s, G, ld, n, nb, tol, flag);
   return hipGetLastError();
 }
 
