@@ -141,7 +141,7 @@ def main():
                     help="also run a plain device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--workload", default="quant_128",
                     choices=["quant_128", "plain_32", "vareps_64", "grad_192", "batched", "coupled_32", "gemv_128",
-                             "poisson3d_26"],
+                             "poisson3d_26", "split_128"],
                     help="quant_128 is the headline metric; the others measure the remaining paths")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -751,9 +751,54 @@ def bench_batched(args):
     return line
 
 
+def bench_split_128(args):
+    """The split-precision forms (FP32, BF16x3, BF16x6) at the metric's size,
+    126^2 unknowns x 1024 uniform right-hand sides, against FP64: the split
+    kernels on a problem large enough to fill the chip without splitting k
+    (the 62^2 x 256 workload is a few tens of microseconds of work)."""
+    import torch
+    from paper_1602_00001_amd import pinv, workloads
+    wl = workloads.quant_128(1024)
+    n, h = wl["n"], wl["h"]
+    N = (n - 2) ** 2
+    R = wl["rho"].shape[0]
+    op = pinv.PoissonInverse.build(n, n, h)
+    rho = torch.from_numpy(wl["rho"]).cuda()
+    ref = op.apply(rho, "fp64")
+    modes = {}
+    for mode, kern, prods, peak, unit in (("fp64", "gemm_f64", 1, PEAK_FP64_TFLOPS, "TFLOP/s"),
+                                          ("fp32", "gemm_split", 1, PEAK_FP32_TFLOPS, "TFLOP/s"),
+                                          ("bf16x3", "gemm_split", 3, PEAK_BF16_TFLOPS, "TFLOP/s"),
+                                          ("bf16x6", "gemm_split", 6, PEAK_BF16_TFLOPS, "TFLOP/s")):
+        if mode != "fp64":
+            op.prepare_split(mode)
+        u = torch.empty_like(rho)
+        for _ in range(args.warmup):
+            op.apply(rho, mode, out=u)
+        torch.cuda.synchronize()
+        pinv.trace_read(kern)
+        pinv.trace_enable(True)
+        dt = _timed(lambda: op.apply(rho, mode, out=u), args.steps, 0)
+        pinv.trace_enable(False)
+        ms, cnt = pinv.trace_read(kern)
+        kms = ms / max(cnt, 1)
+        ach = 2.0 * prods * N * N * R / (kms * 1e-3) / 1e12
+        err = torch.linalg.vector_norm(u - ref, dim=1) / torch.linalg.vector_norm(ref, dim=1)
+        modes[mode] = {"solves_per_s": R / dt, "ms_per_step": dt * 1e3, "kernel_ms": kms,
+                       "rel_l2_vs_fp64_max": float(err.max()), "rel_l2_vs_fp64_median": float(err.median()),
+                       "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak}}
+    op.close()
+    line = _base("solves/sec at 126^2 unknowns, 1024 RHS: FP64 vs FP32 / BF16x3 / BF16x6 split precision",
+                 modes["bf16x3"]["solves_per_s"], "solves/s", args, modes["bf16x3"]["ms_per_step"], "bf16",
+                 {"workload": f"split_128: 128x128 grid, {N} unknowns, eps=1, {R} uniform[-1,1] RHS"})
+    line["modes"] = modes
+    line["roofline"] = dict(modes["bf16x3"]["roofline"], kernel="gemm_i8_kernel<2,2,...,1> (bf16 parts)", traffic=None)
+    return line
+
+
 OTHER = {"plain_32": bench_plain_32, "vareps_64": bench_vareps_64, "grad_192": bench_grad_192,
          "batched": bench_batched, "coupled_32": bench_coupled_32, "poisson3d_26": bench_poisson3d_26,
-         "gemv_128": bench_gemv_128}
+         "gemv_128": bench_gemv_128, "split_128": bench_split_128}
 
 
 if __name__ == "__main__":
