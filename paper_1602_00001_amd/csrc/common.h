@@ -231,6 +231,18 @@ hipError_t launch_gemv_i8(const GemmI8Args& a, hipStream_t s);
 // the splits' FP64 sums go to partf[z][r][m] and launch_splitk_reduce adds
 // them.  col_exp and row_exp are unused.
 hipError_t launch_gemm_bf16_parts(const GemmI8Args& a, double* partf, hipStream_t s);
+
+// BF16x3 product on 128 x 256 tiles, one wave per SIMD (G parts [2+][P][P],
+// rho parts [2][Rpad][P] with Rpad = 256 ceil(nrhs / 256)); with ksplit > 1
+// the splits' FP64 sums go to part [ksplit][nrhs][nrows] and
+// launch_splitk_reduce adds them.  u = alpha (hi hi + hi lo + lo hi) + w.
+struct BF16W4Plan {
+  int Rpad = 0, tilesM = 0, tilesN = 0, ksplit = 1, kchunk = 0;
+};
+BF16W4Plan bf16x3_w4_plan(int64_t P, int nrhs);
+hipError_t launch_gemm_bf16x3_w4(const BF16W4Plan& p, const __bf16* Gb, int64_t P, const __bf16* Xb, int nrows,
+                                 int nrhs, double alpha, const double* w, double* U, int64_t ldu, double* part,
+                                 hipStream_t s);
 int gemm_i8_variants();
 // split plan for one apply with `variant` (ksplit = 1: none; tail_rows > 0:
 // only the last tail_rows row tiles split, as in GemmI8Args)

@@ -243,10 +243,25 @@ int split_target(int mode) { return mode == PINV_FP32 ? 512 : 256; }
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// BF16x3 on the 128 x 256 one-wave-per-SIMD tiles where they fill at least
+// half the chip without splitting k (126^2 x 1024: 1.62 -> 1.34 ms); smaller
+// problems keep the 128 x 128 tiles, whose k splits are shorter (62^2 x 256:
+// 52 us against 70 us)
+bool bf16x3_wide(int64_t P, int nrhs) {
+  const BF16W4Plan w = bf16x3_w4_plan(P, nrhs);
+  return w.tilesM * w.tilesN >= 128;
+}
+
 }  // namespace
 
 size_t split_scratch_bytes(int mode, const pinv_op_s* op, int nrhs) {
   const int64_t P = pinv_pad_dim(op->n);
+  if (mode == PINV_BF16X3 && bf16x3_wide(P, nrhs)) {
+    // 128 x 256 tiles, one wave per SIMD: rho parts padded to 256 columns
+    const BF16W4Plan w = bf16x3_w4_plan(P, nrhs);
+    const size_t part = w.ksplit > 1 ? (size_t)w.ksplit * op->n * nrhs * sizeof(double) : 0;
+    return align256((size_t)2 * w.Rpad * P * sizeof(__bf16)) + part;
+  }
   const int Rpad = (nrhs + 127) / 128 * 128;
   int ksplit;
   int64_t kchunk;
@@ -260,8 +275,19 @@ size_t split_scratch_bytes(int mode, const pinv_op_s* op, int nrhs) {
 hipError_t launch_gemm_split(int mode, const pinv_op_s* op, const double* X, int64_t ldx, int nrhs, double alpha,
                              double* U, int64_t ldu, hipStream_t s, void* scratch, size_t scratch_bytes) {
   const int64_t P = pinv_pad_dim(op->n);
-  const int Rpad = (nrhs + 127) / 128 * 128;
   if (scratch_bytes < split_scratch_bytes(mode, op, nrhs)) return hipErrorInvalidValue;
+  if (mode == PINV_BF16X3 && bf16x3_wide(P, nrhs)) {
+    const BF16W4Plan w = bf16x3_w4_plan(P, nrhs);
+    __bf16* Xb = (__bf16*)scratch;
+    double* part = w.ksplit > 1 ? (double*)((char*)scratch + align256((size_t)2 * w.Rpad * P * sizeof(__bf16)))
+                                : nullptr;
+    hipLaunchKernelGGL(pack_bf16_kernel, dim3(grid_1d((int64_t)w.Rpad * P)), dim3(256), 0, s, X, ldx, op->n, nrhs,
+                       w.Rpad, P, 2, Xb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gemm_bf16x3_w4(w, op->Gb, P, Xb, op->n, nrhs, alpha, op->w, U, ldu, part, s);
+  }
+  const int Rpad = (nrhs + 127) / 128 * 128;
   const int tilesM = (int)(P / BM), tilesN = Rpad / BN;
   const int T = tilesM * tilesN;
   const int grid = ((T + 7) / 8) * 8;

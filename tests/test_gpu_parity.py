@@ -224,6 +224,29 @@ def test_split_modes_against_emulation(torch, pinv, mode, nx, ny):
     print(f"[split {nx}x{ny}] {mode}: max rel L2 vs FP64 {err.max():.3e}", flush=True)
 
 
+@pytest.mark.parametrize("nrhs", [1000, 1100])
+def test_bf16x3_on_wide_tiles(torch, pinv, nrhs):
+    """BF16x3 with at least 128 tiles of 128 x 256 runs the one-wave-per-SIMD
+    kernel: 4096 unknowns x 1000 right-hand sides is 32 x 4 tiles with k split
+    in two (ragged last column tile), x 1100 is 32 x 5 tiles without a split.
+    Element by element against the exact-product emulation, and within the
+    operand-rounding envelope of the FP64 solve (check_split_solve)."""
+    nx = ny = 66
+    announce(f"apply bf16x3 on 128 x 256 tiles nx={nx} nrhs={nrhs}")
+    g = np.random.default_rng(nrhs)
+    h = 1.0 / (nx - 1)
+    ub = g.standard_normal((ny, nx))
+    G, w, _ = oracle_inverse(nx, ny, workloads.random_eps(nx, ny, g), ub)
+    rho = g.uniform(-1, 1, (nrhs, G.shape[0]))
+    with pinv.PoissonInverse.from_inverse(nx, ny, h, G, None, ub, w) as op:
+        op.prepare_split("bf16x3")
+        u = host(op.apply(dev(rho), "bf16x3"))
+    # the lift is added exactly in FP64 after the product
+    u = u - w[None, :]
+    err = check_split_solve(u.T, G, rho.T, h, "bf16x3")
+    print(f"[bf16x3 wide] nrhs={nrhs}: max rel L2 vs FP64 {err.max():.3e}", flush=True)
+
+
 # ---------------------------------------------------------------- derivatives
 
 @pytest.mark.parametrize("nx,ny,R", [(12, 9, 6), (40, 33, 6), (40, 33, 53), (17, 23, 16)])
