@@ -498,10 +498,19 @@ __global__ __launch_bounds__(256) void gemm_i8_splitk_epilogue(GemmI8Args a, int
 // registers per lane, up to the whole accumulation register file) are
 // operands of inline-asm products, which read and write each accumulator in
 // place: compiled builtins at this register count copied accumulators between
-// the two register files on every iteration.  Fragments of the next k half
-// are read into a second register set while the current half's products run,
-// and the DMA of the stage two steps ahead is spread over the second half's
-// products; one barrier per 128-byte k step.
+// the two register files on every iteration.
+//
+// Schedule of 128-byte k step k (two LDS stages, k in one, k + 1 in the other):
+// the fragments of the next k half are read into a second register set in the
+// first RW products of each half.  In the first half, once this wave's reads
+// of stage k are complete, a barrier frees stage k's buffer, and the DMA of
+// stage k + 2 into it starts right away: N0 instructions over the rest of the
+// first half, the others over the second half.  The middle of the step waits
+// for stage k + 1 (issued one step earlier; the N0 newest instructions may
+// still be in flight) and a barrier makes it visible.  The DMA is thus spread
+// over about 160 of the step's 192 products (a DMA instruction holds up its
+// wave's issue for tens of cycles while the operand stream is busy, so
+// bunching the 20 instructions into one half leaves the matrix cores idle).
 template <int S, int SR>
 struct W4 {
   static constexpr int C = S + SR - 1;
@@ -512,6 +521,9 @@ struct W4 {
   static constexpr int NDMA = (S + SR) * IPP;      // DMA instructions per wave per stage
   static constexpr int M = S * SR * 16;            // products per wave per k half
   static constexpr int R = 4 * (S + SR);           // fragment reads per wave per k half
+  static constexpr int RW = R < M / 2 ? R : M / 2; // the reads go into the first RW products
+  static constexpr int PB = RW + 8 < M - 8 ? RW + 8 : M - 8;  // barrier after product PB of the first half
+  static constexpr int N0 = NDMA * (M - 1 - PB) / (2 * M - 1 - PB);  // DMA instructions in the first half
   static constexpr bool ok = C <= 4 && 2 * STAGE <= LDS_BYTES;
 };
 
@@ -571,14 +583,32 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int
   const int8_t* tileA = a.Q + (int64_t)m0 * KBY;
   const int8_t* tileB = a.X + (int64_t)n0 * KBY;
   const int64_t planeA = P * KBY, planeB = (int64_t)a.Rpad * KBY;
-
-  // DMA instruction d (0 .. NDMA-1) of stage `step`: plane d / IPP, row block d % IPP
+  // The LDS row block of DMA instruction j is its immediate offset 1024 j
+  // (applied to both addresses, so the row offsets drop it), and the 4
+  // instructions of a plane share one LDS base; the global address is a
+  // scalar base (plane, tile, k) plus the lane's 32-bit row offset.  DMA
+  // instruction d (0 .. NDMA-1) of stage `step`: plane d / IPP, row block
+  // d % IPP.
+#pragma unroll
+  for (int j = 0; j < IPP; ++j) off[j] -= (uint32_t)(j * 1024);
   auto dma = [&](int step, int d) {
     const int p = d / IPP, j = d % IPP;
-    const int64_t k0 = (int64_t)__builtin_amdgcn_readfirstlane((kfirst + step) * BK);
-    const int8_t* src = p < S ? tileA + p * planeA + k0 : tileB + (p - S) * planeB + k0;
-    int8_t* dst = sm + (step & 1) * STAGE + p * PLANE + wave * 32 * BK + j * 1024;
-    __builtin_amdgcn_global_load_lds((const void*)(src + off[j]), PINV_LDS(dst), 16, 0, 0);
+    const int64_t k0 = (int64_t)(kfirst + step) * BK;
+    const uint64_t src = (uint64_t)(p < S ? tileA + p * planeA + k0 : tileB + (p - S) * planeB + k0);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)src);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(src >> 32));
+    const int8_t* base = (const int8_t*)(((uint64_t)hi << 32) | lo);
+    // (an opaque copy: otherwise the compiler folds the zero-extended offset
+    // into a 64-bit per-lane address, one 64-bit add per instruction)
+    uint32_t o = off[j];
+    asm volatile("" : "+v"(o));
+    int8_t* dst = sm + (step & 1) * STAGE + p * PLANE + wave * 32 * BK;
+    switch (j) {  // (the immediate offset must be a constant)
+      case 0: __builtin_amdgcn_global_load_lds((const void*)(base + o), PINV_LDS(dst), 16, 0, 0); break;
+      case 1: __builtin_amdgcn_global_load_lds((const void*)(base + o), PINV_LDS(dst), 16, 1024, 0); break;
+      case 2: __builtin_amdgcn_global_load_lds((const void*)(base + o), PINV_LDS(dst), 16, 2048, 0); break;
+      default: __builtin_amdgcn_global_load_lds((const void*)(base + o), PINV_LDS(dst), 16, 3072, 0); break;
+    }
   };
 
   // fragment read offsets within a plane for k half h: row lane % 16 of the
@@ -610,26 +640,44 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int
     }
   };
 
+  constexpr int RW = K::RW, PB = K::PB, N0 = K::N0;
+
   // one k half: the M products of (fa, fb), with the R reads of the next half
-  // into (na, nb) and (when ND > 0) DMA instructions spread between them
+  // into (na, nb) in the first RW products; in the first half (FIRST) the wait
+  // for those reads and the barrier that frees the stage after product PB; ND
+  // DMA instructions D0 .. D0 + ND - 1 of stage dstep spread over the products
+  // after the barrier (first half) or over all of them (second half)
   auto half = [&](const v4i (&fa)[S][4], const v4i (&fb)[SR][4], const int8_t* nbase, int nfoff, v4i (&na)[S][4],
-                  v4i (&nb)[SR][4], int dstep, auto nd) {
-    constexpr int ND = decltype(nd)::value;
+                  v4i (&nb)[SR][4], int dstep, auto first, auto nd, auto d0) {
+    constexpr bool FIRST = decltype(first)::value;
+    constexpr int ND = decltype(nd)::value, D0 = decltype(d0)::value;
+    constexpr int Q0 = FIRST ? PB + 1 : 0, W = M - Q0;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       const int s = q / (SR * 16), t = (q / 16) % SR, i = (q / 4) % 4, j = q % 4;
       mfma_i8_acc(acc[s + t][i][j], fa[s][i], fb[t][j]);
+      if (q < RW) {
 #pragma unroll
-      for (int r = (q * R + M - 1) / M; r < ((q + 1) * R + M - 1) / M; ++r) read(nbase, nfoff, r, na, nb);
+        for (int r = (q * R + RW - 1) / RW; r < ((q + 1) * R + RW - 1) / RW; ++r) read(nbase, nfoff, r, na, nb);
+      }
+      if constexpr (FIRST) {
+        if (q == PB) {
+          wait_lgkm0();
+          lds_barrier();
+        }
+      }
       if constexpr (ND > 0) {
+        if (q >= Q0) {
+          const int qq = q - Q0;
 #pragma unroll
-        for (int d = (q * ND + M - 1) / M; d < ((q + 1) * ND + M - 1) / M; ++d) dma(dstep, d);
+          for (int d = (qq * ND + W - 1) / W; d < ((qq + 1) * ND + W - 1) / W; ++d) dma(dstep, D0 + d);
+        }
       }
     }
   };
 
-  using DmaOn = std::integral_constant<int, NDMA>;
-  using DmaOff = std::integral_constant<int, 0>;
+  using DmaOn = std::true_type;
+  using DmaOff = std::false_type;
 
   // prologue: stages 0 and 1 in flight, wait for stage 0, read its first half
 #pragma unroll
@@ -645,17 +693,23 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int
 #pragma unroll
   for (int r = 0; r < R; ++r) read(sm, foff0, r, fa0, fb0);
 
-  // step k: half 0 (reads of half 1 alongside); this wave's reads of stage k
-  // are complete and its DMA of stage k + 1 has landed, barrier; half 1 (DMA of
-  // stage k + 2 into the buffer just released, reads of stage k + 1's half 0)
-  auto step = [&](int k, auto nd) {
+  // step k: half 0 (reads of stage k's half 1, barrier, DMA of stage k + 2
+  // begins); this wave's DMA of stage k + 1 has landed, barrier; half 1 (rest
+  // of the DMA of stage k + 2, reads of stage k + 1's half 0).  Without DMA
+  // (the last two steps) the wait is for everything.
+  auto step = [&](int k, auto on) {
+    constexpr bool ON = decltype(on)::value;
+    using I = std::integral_constant<int, 0>;
+    using N0c = std::integral_constant<int, ON ? N0 : 0>;
+    using N1c = std::integral_constant<int, ON ? NDMA - N0 : 0>;
+    using D1c = std::integral_constant<int, N0>;
     const int8_t* cur = sm + (k & 1) * STAGE;
     const int8_t* nxt = sm + ((k + 1) & 1) * STAGE;
-    half(fa0, fb0, cur, foff1, fa1, fb1, 0, DmaOff{});
+    half(fa0, fb0, cur, foff1, fa1, fb1, k + 2, std::true_type{}, N0c{}, I{});
     wait_lgkm0();
-    wait_vm<0>();
+    if constexpr (ON) wait_vm<N0>(); else wait_vm<0>();
     lds_barrier();
-    half(fa1, fb1, nxt, foff0, fa0, fb0, k + 2, nd);
+    half(fa1, fb1, nxt, foff0, fa0, fb0, k + 2, std::false_type{}, N1c{}, D1c{});
   };
   int k = 0;
   for (; k + 2 < nsteps; ++k) step(k, DmaOn{});
