@@ -527,6 +527,20 @@ struct W4 {
   static constexpr bool ok = C <= 4 && 2 * STAGE <= LDS_BYTES;
 };
 
+// One 16-byte-per-lane DMA into LDS through a buffer resource made for the
+// plane (nrec bytes from base): lane offset voff, scalar k offset soff, and the
+// LDS row block of instruction j (0 .. 3) as the immediate offset 1024 j (it
+// applies to both addresses, so voff has it taken off).
+__device__ __forceinline__ void dma_plane(const int8_t* base, int nrec, int8_t* lds, uint32_t voff, int soff, int j) {
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, nrec, 0x00020000);
+  switch (j) {  // (the immediate offset must be a constant)
+    case 0: __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, PINV_LDS(lds), 16, voff, soff, 0, 0); break;
+    case 1: __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, PINV_LDS(lds), 16, voff, soff, 1024, 0); break;
+    case 2: __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, PINV_LDS(lds), 16, voff, soff, 2048, 0); break;
+    default: __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, PINV_LDS(lds), 16, voff, soff, 3072, 0); break;
+  }
+}
+
 // the product acc += fa * fb on the matrix cores, accumulator in place
 __device__ inline void mfma_i8_acc(v4i& acc, const v4i& fa, const v4i& fb) {
   asm volatile("v_mfma_i32_16x16x64_i8 %0, %1, %2, %0" : "+a"(acc) : "v"(fa), "v"(fb));
@@ -593,22 +607,9 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int
   for (int j = 0; j < IPP; ++j) off[j] -= (uint32_t)(j * 1024);
   auto dma = [&](int step, int d) {
     const int p = d / IPP, j = d % IPP;
-    const int64_t k0 = (int64_t)(kfirst + step) * BK;
-    const uint64_t src = (uint64_t)(p < S ? tileA + p * planeA + k0 : tileB + (p - S) * planeB + k0);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)src);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(src >> 32));
-    const int8_t* base = (const int8_t*)(((uint64_t)hi << 32) | lo);
-    // (an opaque copy: otherwise the compiler folds the zero-extended offset
-    // into a 64-bit per-lane address, one 64-bit add per instruction)
-    uint32_t o = off[j];
-    asm volatile("" : "+v"(o));
-    int8_t* dst = sm + (step & 1) * STAGE + p * PLANE + wave * 32 * BK;
-    switch (j) {  // (the immediate offset must be a constant)
-      case 0: __builtin_amdgcn_global_load_lds((const void*)(base + o), PINV_LDS(dst), 16, 0, 0); break;
-      case 1: __builtin_amdgcn_global_load_lds((const void*)(base + o), PINV_LDS(dst), 16, 1024, 0); break;
-      case 2: __builtin_amdgcn_global_load_lds((const void*)(base + o), PINV_LDS(dst), 16, 2048, 0); break;
-      default: __builtin_amdgcn_global_load_lds((const void*)(base + o), PINV_LDS(dst), 16, 3072, 0); break;
-    }
+    const int k0 = __builtin_amdgcn_readfirstlane((kfirst + step) * BK);
+    const int8_t* base = p < S ? tileA + p * planeA : tileB + (p - S) * planeB;
+    dma_plane(base, (int)(128 * KBY), sm + (step & 1) * STAGE + p * PLANE + wave * 32 * BK, off[j], k0, j);
   };
 
   // fragment read offsets within a plane for k half h: row lane % 16 of the
