@@ -24,10 +24,14 @@ def pinv():
     return p
 
 
-@pytest.mark.parametrize("nx,ny,bits,rho_bits", [(40, 31, 24, 16), (33, 20, 16, 24), (12, 9, 8, 8), (66, 66, 24, 16)])
+@pytest.mark.parametrize("nx,ny,bits,rho_bits", [(40, 31, 24, 16), (33, 20, 16, 24), (12, 9, 8, 8), (66, 66, 24, 16),
+                                                 (14, 14, 24, 16), (19, 19, 16, 16), (22, 22, 8, 16)])
 def test_every_variant_bit_exact(torch, pinv, nx, ny, bits, rho_bits):
     """(66, 66) has P = 4096 and few tiles, so every variant also runs split
-    over k (integer class sums of the splits added exactly)."""
+    over k (integer class sums of the splits added exactly).  The k loops run
+    1 to 32 steps of 128 bytes; (14, 14), (19, 19) and (22, 22) give 2, 3 and
+    4 steps, where the one-wave-per-SIMD schedule has no step, one step or two
+    steps that load a stage two ahead."""
     g = np.random.default_rng(nx * ny + bits)
     ub = g.standard_normal((ny, nx))
     h = 1.0 / (max(nx, ny) - 1)
