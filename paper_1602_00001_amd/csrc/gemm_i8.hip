@@ -741,13 +741,55 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int
     return;
   }
 
+  // the exponents of this lane's 16 rows and 4 columns are loaded before the
+  // first store (loads and stores share one in-order counter, so a load
+  // after a store would wait for the store)
+  int erow[4][4], ecol[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+      erow[i][r] = (m < a.n && a.row_exp) ? a.row_exp[m] : 0;
+    }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+    ecol[j] = n < a.nrhs ? a.col_exp[n] : 0;
+  }
+  // (one wait for all of them here, so none is left for the compiler to place
+  // among the stores)
+  __builtin_amdgcn_s_waitcnt(0);
+  asm volatile("" ::: "memory");
+  if (!a.ucols && !a.w) {
+    // output columns at a fixed stride, no lift: no loads among the stores
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (n >= a.nrhs) continue;
+        double* ucol = a.U + (int64_t)n * a.ldu;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+          if (m >= a.n) continue;
+          int64_t v = acc[0][i][j][r];
+#pragma unroll
+          for (int c = 1; c < C; ++c) v = v * 256 + (int64_t)acc[c][i][j][r];
+          const double scale = ldexp(a.c, erow[i][r] + ecol[j]);
+          ucol[m] = (double)v * scale;
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int n = n0 + wn * 64 + j * 16 + (lane & 15);
       if (n >= a.nrhs) continue;
-      const int fn = a.col_exp[n];
       double* ucol = a.ucols ? a.ucols[n] : a.U + (int64_t)n * a.ldu;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -756,8 +798,7 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int
         int64_t v = acc[0][i][j][r];
 #pragma unroll
         for (int c = 1; c < C; ++c) v = v * 256 + (int64_t)acc[c][i][j][r];
-        const int em = a.row_exp ? a.row_exp[m] : 0;
-        const double scale = ldexp(a.c, em + fn);
+        const double scale = ldexp(a.c, erow[i][r] + ecol[j]);
         double u = (double)v * scale;
         if (a.w) u = u + a.w[m];
         ucol[m] = u;
