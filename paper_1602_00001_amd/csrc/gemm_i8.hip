@@ -442,15 +442,36 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
     return;
   }
 
-  // exact recombination and the single scaling
+  // exact recombination and the single scaling; the exponents, lift values
+  // and output columns of this lane's 8 rows and 4 columns are loaded before
+  // the first store (loads and stores share one in-order counter, so a load
+  // after a store would wait for the store)
+  int erow[2][4], ecol[4];
+  double wrow[2][4];
+  double* ucol[4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+      erow[i][r] = (m < a.n && a.row_exp) ? a.row_exp[m] : 0;
+      wrow[i][r] = (m < a.n && a.w) ? a.w[m] : 0.0;
+    }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+    const bool in = n < a.nrhs;
+    ecol[j] = in ? a.col_exp[n] : 0;
+    ucol[j] = !in ? nullptr : a.ucols ? a.ucols[n] : a.U + (int64_t)n * a.ldu;
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  asm volatile("" ::: "memory");
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int n = n0 + wn * 64 + j * 16 + (lane & 15);
       if (n >= a.nrhs) continue;
-      const int fn = a.col_exp[n];
-      double* ucol = a.ucols ? a.ucols[n] : a.U + (int64_t)n * a.ldu;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
@@ -458,11 +479,10 @@ __global__ __launch_bounds__(NWV * 64, NWV == 8 ? 1 : 2) void gemm_i8_kernel(Gem
         int64_t v = acc[0][i][j][r];
 #pragma unroll
         for (int c = 1; c < C; ++c) v = v * 256 + (int64_t)acc[c][i][j][r];
-        const int em = a.row_exp ? a.row_exp[m] : 0;
-        const double scale = ldexp(a.c, em + fn);
+        const double scale = ldexp(a.c, erow[i][r] + ecol[j]);
         double u = (double)v * scale;
-        if (a.w) u = u + a.w[m];
-        ucol[m] = u;
+        if (a.w) u = u + wrow[i][r];
+        ucol[j][m] = u;
       }
     }
   }
@@ -784,13 +804,29 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int
     }
     return;
   }
+  // with a lift or a table of output columns, those are loaded first too
+  double wrow[4][4];
+  double* ucol[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+      wrow[i][r] = (m < a.n && a.w) ? a.w[m] : 0.0;
+    }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+    ucol[j] = n >= a.nrhs ? nullptr : a.ucols ? a.ucols[n] : a.U + (int64_t)n * a.ldu;
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  asm volatile("" ::: "memory");
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int n = n0 + wn * 64 + j * 16 + (lane & 15);
       if (n >= a.nrhs) continue;
-      double* ucol = a.ucols ? a.ucols[n] : a.U + (int64_t)n * a.ldu;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
@@ -800,8 +836,8 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_w4_kernel(GemmI8Args a_in, int
         for (int c = 1; c < C; ++c) v = v * 256 + (int64_t)acc[c][i][j][r];
         const double scale = ldexp(a.c, erow[i][r] + ecol[j]);
         double u = (double)v * scale;
-        if (a.w) u = u + a.w[m];
-        ucol[m] = u;
+        if (a.w) u = u + wrow[i][r];
+        ucol[j][m] = u;
       }
     }
   }
